@@ -1,0 +1,249 @@
+"""Brute-force FP64 renderer of rectangular plane primitives (oracle).
+
+TEST INFRASTRUCTURE ONLY: see the package docstring.
+
+Every pixel's ray is intersected with every plane; nothing is tiled, culled
+or reordered beyond what the method states.  Readings of points the paper
+leaves open (each also listed in the design doc):
+
+* Eq. 4 prints the numerator as "(p - o . n)"; it is read as (p - o) . n.
+* the pinhole ray of pixel (i, j) passes through the pixel center
+  (i + 1/2, j + 1/2); the direction has camera-frame z component 1, so the
+  ray parameter t of Eq. 4 is the camera z-depth, which is the "depth" t_j of
+  Eq. 11.
+* Eq. 7-8 print 2*sigmoid(.), which exceeds 1 inside the rectangle.  Mode "A"
+  (default) keeps the printed weight and clamps it at 1: a point inside the
+  rectangle is opaque (the primitives are described as solid).  Mode "B"
+  uses sigmoid(.) without the factor 2.
+* Eq. 9's "otherwise" gives w_Y on a tie, Eq. 7's "otherwise" takes r^{x-}
+  at P_X = 0.
+* intersections with |d . n| <= 1e-12 |d| or depth t <= z_near are no hits.
+* the filter keeps w >= tau; the survivors are ordered by depth, and the
+  per-ray order is decided on the depth rounded to float32 (the precision of
+  the kernels), ties broken by the plane index; the first M are composited.
+* the rendered normal is the plane normal in the camera frame, flipped to
+  face the camera (two-sided); with two_sided=False it is R(q) e_z as is.
+* a pixel with no surviving intersection renders depth 0 and normal 0.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+F64 = torch.float64
+
+
+@dataclass
+class OracleParams:
+    M: int = 30             # nearest intersections composited per ray (Sec. 3.2)
+    tau: float = 1e-4       # weight filter threshold (Sec. 3.2)
+    z_near: float = 0.01    # near clip in metres (not in the paper)
+    weight_mode: str = "A"  # "A": min(1, 2 sigmoid(5 lambda a)); "B": sigmoid(5 lambda a)
+    two_sided: bool = True
+
+
+def lambda_at(ite: int) -> float:
+    """Eq. 10: lambda = min(20 e^{-(1 - 0.001 ite)}, 300), ite counted from 0."""
+    return min(20.0 * math.exp(-(1.0 - 0.001 * ite)), 300.0)
+
+
+def fringe_margin(lam: float, prm: OracleParams) -> float:
+    """delta such that w >= tau  <=>  min(a_X, a_Y) >= -delta (closed form)."""
+    if prm.weight_mode == "A":
+        return math.log(2.0 / prm.tau - 1.0) / (5.0 * lam)
+    return math.log(1.0 / prm.tau - 1.0) / (5.0 * lam)
+
+
+def _t(x):
+    if isinstance(x, torch.Tensor):
+        return x.to(F64)
+    return torch.as_tensor(np.asarray(x), dtype=F64)
+
+
+def quat_to_frame(q: torch.Tensor):
+    """Eq. 2-3: v_x = R(q) e_x, v_y = R(q) e_y, n = R(q) e_z, with q normalised
+    first and R the Hamilton rotation matrix of q = (w, x, y, z)."""
+    qn = q / q.norm(dim=-1, keepdim=True)
+    w, x, y, z = qn.unbind(-1)
+    vx = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z - w * y)], dim=-1)
+    vy = torch.stack([2 * (x * y - w * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w * x)], dim=-1)
+    n = torch.stack([2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y)], dim=-1)
+    return vx, vy, n
+
+
+def camera_rays(cam, pix: torch.Tensor):
+    """Origin o (world) and world directions d of the rays through the pixel
+    centers of the flat pixel indices `pix` (row-major, index = j*W + i)."""
+    Rcw = _t(cam.R)
+    tcw = _t(cam.t)
+    o = -(Rcw.T @ tcw)
+    i = (pix % cam.width).to(F64)
+    j = torch.div(pix, cam.width, rounding_mode="floor").to(F64)
+    dc = torch.stack([(i + 0.5 - cam.cx) / cam.fx, (j + 0.5 - cam.cy) / cam.fy, torch.ones_like(i)], dim=-1)
+    d = dc @ Rcw  # row form of R^T d_c
+    return o, d, Rcw
+
+
+def _pairs(center, quat, radii, cam, lam, pix, prm: OracleParams, cand=None):
+    """All (pixel, plane) quantities of Sec. 3.2 for the pixels `pix`.
+
+    Parameters have shape [K, .] (shared) or [P, K, .] (one copy per pixel, used
+    to read per-pixel gradients).  Returns a dict of [P, K] tensors."""
+    o, d, Rcw = camera_rays(cam, pix)
+    if center.dim() == 2:
+        center, quat, radii = center[None], quat[None], radii[None]
+    vx, vy, n = quat_to_frame(quat)                       # [., K, 3]
+    dd = d[:, None, :]                                    # [P, 1, 3]
+    den = (dd * n).sum(-1)                                # d . n
+    num = ((center - o) * n).sum(-1)                      # (p - o) . n   (Eq. 4, reading of the numerator)
+    ok = den.abs() > 1e-12 * dd.norm(dim=-1)
+    t = num / torch.where(ok, den, torch.ones_like(den))  # Eq. 4 ray parameter = z-depth
+    valid = ok & (t > prm.z_near)
+    x = o + t[..., None] * dd                             # intersection x^r_pi (Eq. 4)
+    rel = x - center
+    PX = (rel * vx).sum(-1)                               # Eq. 6
+    PY = (rel * vy).sum(-1)
+    rX = torch.where(PX > 0, radii[..., 0], radii[..., 1])  # Eq. 7: r^{x+} if P_X > 0 else r^{x-}
+    rY = torch.where(PY > 0, radii[..., 2], radii[..., 3])  # Eq. 8
+    if prm.weight_mode == "A":
+        wX = 2 * torch.sigmoid(5 * lam * (rX - PX.abs()))
+        wY = 2 * torch.sigmoid(5 * lam * (rY - PY.abs()))
+    else:
+        wX = torch.sigmoid(5 * lam * (rX - PX.abs()))
+        wY = torch.sigmoid(5 * lam * (rY - PY.abs()))
+    w = torch.where(wX < wY, wX, wY)                      # Eq. 9
+    if prm.weight_mode == "A":
+        w = torch.where(w < 1, w, torch.ones_like(w))     # solid primitive: weight at most 1
+    keep = valid & (w >= prm.tau)                         # filter (Sec. 3.2)
+    if cand is not None:
+        keep = keep & cand
+    # rendered normal: camera frame, facing the camera
+    n_cam = n @ Rcw.T
+    if prm.two_sided:
+        s = -torch.sign(num)
+        n_cam = n_cam * s[..., None]
+    return dict(t=t, w=w, keep=keep, n=n_cam, PX=PX, PY=PY, rX=rX, rY=rY, num=num, den=den)
+
+
+def _composite(q, prm: OracleParams):
+    """Sort the kept intersections of each ray near to far, keep the first M,
+    composite depth and normal front to back (Eq. 11-13)."""
+    t, w, keep, n = q["t"], q["w"], q["keep"], q["n"]
+    P, K = t.shape
+    key = torch.where(keep, t.detach().to(torch.float32).to(F64), torch.full_like(t, math.inf))
+    order = torch.sort(key, dim=1, stable=True).indices   # stable: ties keep plane order
+    Msel = min(prm.M, K)
+    sel = order[:, :Msel]
+    ks = keep.gather(1, sel)
+    w_s = torch.where(ks, w.gather(1, sel), torch.zeros((), dtype=F64))
+    t_s = torch.where(ks, t.gather(1, sel), torch.zeros((), dtype=F64))
+    if n.shape[0] == 1:
+        n = n.expand(P, K, 3)
+    n_s = n.gather(1, sel[..., None].expand(P, Msel, 3))
+    T = torch.ones(P, dtype=F64)
+    D = torch.zeros(P, dtype=F64)
+    N = torch.zeros(P, 3, dtype=F64)
+    cov = torch.zeros(P, dtype=F64)
+    for j in range(Msel):
+        Tw = T * w_s[:, j]
+        D = D + Tw * t_s[:, j]                            # Eq. 11
+        N = N + Tw[:, None] * n_s[:, j]                   # Eq. 12
+        cov = cov + Tw
+        T = T * (1 - w_s[:, j])                           # Eq. 13
+    ids = torch.where(ks, sel, torch.full_like(sel, -1))
+    return D, N, dict(count=ks.sum(1), coverage=cov.detach(), ids=ids, T=T.detach())
+
+
+def render_pixels(center, quat, radii, cam, lam, pix, prm: OracleParams = OracleParams(),
+                  chunk: int = 4096, cand=None):
+    """Depth [P] and camera-frame normal [P, 3] for flat pixel indices `pix`."""
+    center, quat, radii = _t(center), _t(quat), _t(radii)
+    pix = torch.as_tensor(np.asarray(pix), dtype=torch.int64)
+    Ds, Ns, aux = [], [], []
+    for s in range(0, pix.numel(), chunk):
+        pc = pix[s:s + chunk]
+        args = (center, quat, radii)
+        if center.dim() == 3:   # per-pixel parameter copies
+            args = tuple(a[s:s + chunk] for a in args)
+        cc = None if cand is None else cand[s:s + chunk]
+        q = _pairs(*args, cam, lam, pc, prm, cand=cc)
+        D, N, a = _composite(q, prm)
+        Ds.append(D)
+        Ns.append(N)
+        aux.append(a)
+    D = torch.cat(Ds)
+    N = torch.cat(Ns)
+    merged = {k: torch.cat([a[k] for a in aux]) for k in aux[0]}
+    return D, N, merged
+
+
+def render(center, quat, radii, cam, lam, prm: OracleParams = OracleParams(), tiles=None, chunk: int = 4096):
+    """Full image: depth [H, W] and normal [3, H, W] (camera frame).
+
+    With tiles=(tw, th) the "tiled mode" is used: a plane is a candidate for
+    the pixels of a tile only if its expanded footprint (footprint_tiles)
+    touches the tile; the result must be identical to the untiled one."""
+    W, H = cam.width, cam.height
+    pix = torch.arange(W * H)
+    cand = None
+    if tiles is not None:
+        tw, th = tiles
+        rects = footprint_tiles(center, quat, radii, cam, lam, prm, tw, th)
+        ti = (pix % W) // tw
+        tj = (pix // W) // th
+        r = torch.as_tensor(rects)
+        cand = ((ti[:, None] >= r[None, :, 0]) & (ti[:, None] <= r[None, :, 2])
+                & (tj[:, None] >= r[None, :, 1]) & (tj[:, None] <= r[None, :, 3]))
+    D, N, aux = render_pixels(center, quat, radii, cam, lam, pix, prm, chunk, cand=cand)
+    aux = {k: v.reshape(H, W, *v.shape[1:]) for k, v in aux.items()}
+    return D.reshape(H, W), N.T.reshape(3, H, W), aux
+
+
+def footprint_tiles(center, quat, radii, cam, lam, prm: OracleParams, tw: int, th: int):
+    """Inclusive tile rectangle [tx0, ty0, tx1, ty1] per plane that contains
+    every pixel whose ray can give w >= tau, or an empty rectangle.
+
+    w >= tau holds exactly when -(r^{x-} + delta) <= P_X <= r^{x+} + delta and
+    likewise for P_Y (delta = fringe_margin), i.e. inside the rectangle grown
+    by delta.  The grown rectangle is clipped to z > z_near in the camera frame,
+    projected, and its bounding box (plus one pixel) is converted to tiles."""
+    center = _t(center).detach().numpy()
+    vx, vy, _ = (a.detach().numpy() for a in quat_to_frame(_t(quat)))
+    radii = _t(radii).detach().numpy()
+    Rcw = np.asarray(cam.R, np.float64)
+    tcw = np.asarray(cam.t, np.float64)
+    dl = fringe_margin(lam, prm)
+    ntx = (cam.width + tw - 1) // tw
+    nty = (cam.height + th - 1) // th
+    out = np.zeros((center.shape[0], 4), np.int64)
+    for k in range(center.shape[0]):
+        xp, xm, yp, ym = radii[k] + dl
+        corners = [center[k] + a * vx[k] + b * vy[k] for a, b in ((xp, yp), (-xm, yp), (-xm, -ym), (xp, -ym))]
+        cc = [Rcw @ c + tcw for c in corners]
+        poly = []
+        for a, b in zip(cc, cc[1:] + cc[:1]):       # clip the polygon to z >= z_near
+            ina, inb = a[2] >= prm.z_near, b[2] >= prm.z_near
+            if ina:
+                poly.append(a)
+            if ina != inb:
+                s = (prm.z_near - a[2]) / (b[2] - a[2])
+                poly.append(a + s * (b - a))
+        if not poly:
+            out[k] = [1, 1, 0, 0]
+            continue
+        us = [cam.fx * p[0] / p[2] + cam.cx for p in poly]
+        vs = [cam.fy * p[1] / p[2] + cam.cy for p in poly]
+        # pixel i is inside when u0 <= i + 1/2 <= u1; one pixel of guard
+        i0 = max(0, math.floor(min(us) - 0.5) - 1)
+        i1 = min(cam.width - 1, math.ceil(max(us) - 0.5) + 1)
+        j0 = max(0, math.floor(min(vs) - 0.5) - 1)
+        j1 = min(cam.height - 1, math.ceil(max(vs) - 0.5) + 1)
+        if i0 > i1 or j0 > j1:
+            out[k] = [1, 1, 0, 0]
+            continue
+        out[k] = [i0 // tw, j0 // th, min(i1 // tw, ntx - 1), min(j1 // th, nty - 1)]
+    return out

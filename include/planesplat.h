@@ -1,0 +1,204 @@
+/*
+ * planesplat.h -- C ABI of the MI355X (gfx950) splatting library for
+ * rectangular plane primitives (PlanarSplatting, arXiv 2412.03451).
+ *
+ * What the library computes.  A plane primitive is a rectangle with center
+ * p in R^3, rotation quaternion q = (w, x, y, z) and four radii
+ * (r^{x+}, r^{x-}, r^{y+}, r^{y-}) (Sec. 3.1, Eq. 1-3).  For every pixel ray of
+ * a pinhole camera, every plane is intersected (Eq. 4), the intersection gets
+ * the rectangle splat weight w (Eq. 6-9, steepness lambda of Eq. 10), hits
+ * with w >= tau are ordered near to far, the first M are composited front to
+ * back into a depth and a normal map (Eq. 11-13), the maps are compared with
+ * targets by the loss of Eq. 14, gradients flow back to (p, q, r) and an Adam
+ * step updates them (Sec. 3.3).
+ *
+ * Readings where the paper is silent or garbled (shared with the tests):
+ *   - Eq. 4 is read as t = ((p - o) . n) / (d . n);
+ *   - the ray of pixel (i, j) passes through (i + 1/2, j + 1/2); its camera
+ *     frame direction has z = 1, so t is the camera z-depth;
+ *   - weight_mode 0: w = min(1, 2 sigmoid(5 lambda a*)) (the printed 2 sigma,
+ *     clamped: the rectangle interior is opaque); weight_mode 1:
+ *     w = sigmoid(5 lambda a*); a* = min(a_X, a_Y), a_X = r^{x+/-} - |P_X|;
+ *   - a hit needs |d . n| > 1e-12 |d| and t > z_near;
+ *   - per-ray order: depth rounded to float32, ties by plane index;
+ *   - the rendered normal is the camera-frame plane normal flipped to face
+ *     the camera (two_sided = 1) or R(q) e_z as is (two_sided = 0);
+ *   - a pixel without hits renders depth 0 and normal 0.
+ *
+ * Conventions for every call.
+ *   - Pointers documented "device" are device memory the caller owns; the
+ *     library never allocates or frees.  Scratch lives in one caller-owned
+ *     workspace of ps_layout.ws_bytes bytes (256-byte aligned).
+ *   - `stream` is a hipStream_t passed as void*.  Calls are asynchronous on it
+ *     and capturable in a HIP graph, except where a call says it synchronises.
+ *   - Return value: PS_OK, or an error code with a message from
+ *     ps_last_error() (thread-local).  Invalid arguments are rejected before
+ *     any launch.
+ *   - Float arrays are float32.  Plane parameters are row-major [K][3]
+ *     (center), [K][4] (quat, w first), [K][4] (radii: x+, x-, y+, y-).
+ *   - A "job" (ps_slot) renders the planes [plane_begin, plane_end) with one
+ *     camera into one image.  Several jobs form a batch (several views of one
+ *     scene, or several scenes).  Depth of job s occupies
+ *     depth[pix_off, pix_off + H*W) row-major; its normal occupies
+ *     normal[3*pix_off, 3*pix_off + 3*H*W) as three [H][W] planes (x, y, z).
+ */
+#ifndef PLANESPLAT_H
+#define PLANESPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PS_OK 0
+#define PS_ERR_INVALID 1   /* bad argument (null pointer, bad size, bad tile shape) */
+#define PS_ERR_CAPACITY 2  /* more (tile, plane) pairs than the workspace holds   */
+#define PS_ERR_HIP 3       /* a HIP runtime call failed                            */
+
+/* Pinhole camera; x_cam = R x_world + t, OpenCV axes (x right, y down,
+ * z forward), pixel (i, j) center at (i + 1/2, j + 1/2).  80 bytes. */
+typedef struct ps_camera {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9]; /* row-major world->camera rotation */
+  float t[3];
+  int32_t pad[2];
+} ps_camera;
+
+/* Method constants (Sec. 3.2).  Paper values: M = 30, tau = 1e-4. */
+typedef struct ps_params {
+  int32_t M;           /* nearest hits composited per ray, 1..30 */
+  float tau;           /* weight filter, 0 < tau < 1 */
+  float z_near;        /* near clip in metres, > 0 */
+  int32_t weight_mode; /* 0: min(1, 2 sigmoid), 1: sigmoid */
+  int32_t two_sided;   /* 1: normals face the camera */
+  int32_t flags;       /* bit 0: force the exact fallback ordering path (testing) */
+} ps_params;
+
+/* One render job.  The caller fills the first block; ps_layout_init fills
+ * the second.  64 bytes. */
+typedef struct ps_slot {
+  int32_t plane_begin, plane_end; /* planes [begin, end) of the plane arrays */
+  int32_t cam;                    /* camera index of the job */
+  int32_t width, height;          /* image size of the job's camera */
+  int32_t tile_w, tile_h;         /* binning tile: 8x8, 16x16 or 32x8 */
+  int32_t scene;                  /* scene index (loss is reported per job) */
+  int32_t tiles_x, tiles_y;       /* filled: tiles per row / column */
+  int32_t rec_begin;              /* filled: first projection record */
+  int32_t tile_begin;             /* filled: first tile */
+  int32_t item_begin;             /* filled: first 8x8 render item */
+  int32_t pad;
+  int64_t pix_off;                /* filled: first pixel of the job */
+} ps_slot;
+
+/* Sizes and workspace carving of a batch of jobs (host struct). */
+#define PS_NUM_REGIONS 16
+typedef struct ps_layout {
+  int32_t n_slots;
+  int32_t n_records;   /* sum of (plane_end - plane_begin) */
+  int32_t n_tiles;
+  int32_t n_items;     /* 8x8 pixel blocks */
+  int64_t n_pixels;
+  int64_t pair_capacity;
+  int32_t max_sub;     /* 8x8 blocks per tile, maximum over jobs */
+  int32_t n_planes;    /* planes referenced: max plane_end */
+  size_t region[PS_NUM_REGIONS]; /* byte offsets inside the workspace */
+  size_t ws_bytes;
+} ps_layout;
+
+/* Fill the derived fields of slots[0..n_slots) (host array, modified in
+ * place) and compute the layout for at most pair_capacity (tile, plane)
+ * pairs.  Tile shapes must be 8x8, 16x16 or 32x8; sizes must be positive. */
+int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity, ps_layout* out);
+
+/* Workspace bytes for a layout (same as out->ws_bytes). */
+size_t ps_workspace_bytes(const ps_layout* L);
+
+/* Copy the slot table into the device workspace `ws` (ps_layout.ws_bytes
+ * bytes, device, 256-byte aligned) and clear its counters.  Call once per
+ * workspace, and again after changing the host slots. */
+int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void* ws, void* stream);
+
+/* Device-side change of the camera of every job: cam[s] = view_of_slot[s]
+ * (device int array of n_slots), for captured fitting steps. */
+int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_of_slot, void* stream);
+
+/* plane_project (Sec. 3.1 Eq. 2-3, Sec. 3.2 Eq. 4 and 6): per (plane, job)
+ * record in the job's camera frame: normalised rotation, plane offset, the
+ * three affine-in-pixel numerators/denominator of t, P_X, P_Y (float64), the
+ * camera-facing normal, and the screen footprint of the rectangle grown by
+ * the fringe margin delta(lambda) outside which w < tau.
+ *   center [K][3], quat [K][4], radii [K][4]: device, K >= layout.n_planes;
+ *   cams: device array of n_cams ps_camera; lambda: device float scalar;
+ *   prm: host struct.  Result lives in the workspace. */
+int plane_project(const ps_layout* L, void* ws, const float* center, const float* quat,
+                  const float* radii, int K, const ps_camera* cams, int n_cams,
+                  const float* lambda, const ps_params* prm, void* stream);
+
+/* tile_bin: (tile, plane) pairs of every job, each pair keyed by a depth
+ * lower bound of the plane over the tile, sorted per tile by (bound, record).
+ * Steps: per-record tile count -> wave64 prefix scan of tile and record
+ * counts -> key emission -> per-tile sort (LDS bitonic).  If pairs_needed is
+ * non-null the call synchronises the stream, stores the number of pairs and
+ * returns PS_ERR_CAPACITY when it exceeds layout.pair_capacity (the binning
+ * is then incomplete and the render calls write nothing).  A tile may hold at
+ * most 4096 pairs.  Without pairs_needed the overflow is only flagged on the
+ * device (ps_read_counters). */
+int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, void* stream);
+
+/* plane_render_fwd (Eq. 4, 6-9, 11-13): depth [n_pixels] and normal
+ * [3*n_pixels] (device, overwritten, layout above).  trans [n_pixels] (final
+ * transmittance) and count [n_pixels] (hits composited) are optional
+ * diagnostics (device or NULL).  The per-ray order is exact: hits are
+ * committed only once no later candidate of the tile list can be nearer, with
+ * an exact per-pixel selection fallback.  cams as for plane_project; the
+ * jobs' camera indices must be < n_cams. */
+int plane_render_fwd(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,
+                     const float* lambda, const ps_params* prm, float* depth, float* normal,
+                     float* trans, int32_t* count, void* stream);
+
+/* loss_depth_normal (Eq. 14): per pixel a_cos |1 - N.N^| + a_nl1 ||N - N^||_1
+ * + a_d |D - D^| with its gradient g_depth [n_pixels], g_normal [3*n_pixels]
+ * (device, overwritten; sgn(0) = 0).  mask: device uint8 [n_pixels] or NULL.
+ * loss: device float [n_slots][4] = the three weighted sums and the plain sum
+ * of |D - D^| per job (deterministic). */
+int loss_depth_normal(const ps_layout* L, void* ws, const float* depth, const float* normal,
+                      const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
+                      float a_cos, float a_nl1, float a_d, float* loss, float* g_depth,
+                      float* g_normal, void* stream);
+
+/* plane_render_bwd: gradient of sum_px g_depth*D + g_normal.N with respect to
+ * center, quat, radii (device [K][3], [K][4], [K][4], overwritten; summed
+ * over the jobs that use a plane).  Recomputes each pixel's ordered hit list
+ * (no per-pixel list is stored between calls), walks it back to front for the
+ * compositing adjoint, reduces per (tile, plane) and chains to (p, q, r) in a
+ * fixed order (bitwise deterministic).  Inputs as for plane_project. */
+int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const float* quat,
+                     const float* radii, int K, const ps_camera* cams, int n_cams,
+                     const float* lambda, const ps_params* prm, const float* g_depth,
+                     const float* g_normal, float* g_center, float* g_quat, float* g_radii,
+                     void* stream);
+
+/* adam_step_planes (Sec. 3.3): bias-corrected Adam on the K planes.
+ * m, v: device [11*K] laid out as center (3K) | quat (4K) | radii (4K).
+ * step: device int, the 1-based step number read by the kernel.  After the
+ * update radii are clamped to >= r_min.  Quaternions are not renormalised. */
+int adam_step_planes(float* center, float* quat, float* radii, const float* g_center,
+                     const float* g_quat, const float* g_radii, float* m, float* v, int K,
+                     const int32_t* step, float lr_center, float lr_quat, float lr_radii,
+                     float beta1, float beta2, float eps, float r_min, void* stream);
+
+/* Counters of the last binning/render (synchronises the stream):
+ * out[0] pairs needed, out[1] overflow flag, out[2] largest tile list,
+ * out[3] pixels that took the exact fallback ordering path. */
+int ps_read_counters(const ps_layout* L, void* ws, int64_t out[4], void* stream);
+
+/* Message of the last error on this thread. */
+const char* ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLANESPLAT_H */

@@ -109,15 +109,23 @@ def _pairs(center, quat, radii, cam, lam, pix, prm: OracleParams, cand=None):
     PY = (rel * vy).sum(-1)
     rX = torch.where(PX > 0, radii[..., 0], radii[..., 1])  # Eq. 7: r^{x+} if P_X > 0 else r^{x-}
     rY = torch.where(PY > 0, radii[..., 2], radii[..., 3])  # Eq. 8
+    zX = 5 * lam * (rX - PX.abs())
+    zY = 5 * lam * (rY - PY.abs())
+    # 1 - w is formed from the same argument by an identity instead of a
+    # subtraction (1 - s(z) = s(-z), 1 - 2 s(z) = tanh(-z/2)), so the
+    # transmittance behind a nearly opaque layer keeps its precision.
     if prm.weight_mode == "A":
-        wX = 2 * torch.sigmoid(5 * lam * (rX - PX.abs()))
-        wY = 2 * torch.sigmoid(5 * lam * (rY - PY.abs()))
+        wX, wY = 2 * torch.sigmoid(zX), 2 * torch.sigmoid(zY)
+        oX, oY = torch.tanh(-zX / 2), torch.tanh(-zY / 2)
     else:
-        wX = torch.sigmoid(5 * lam * (rX - PX.abs()))
-        wY = torch.sigmoid(5 * lam * (rY - PY.abs()))
+        wX, wY = torch.sigmoid(zX), torch.sigmoid(zY)
+        oX, oY = torch.sigmoid(-zX), torch.sigmoid(-zY)
     w = torch.where(wX < wY, wX, wY)                      # Eq. 9
+    omw = torch.where(wX < wY, oX, oY)
     if prm.weight_mode == "A":
-        w = torch.where(w < 1, w, torch.ones_like(w))     # solid primitive: weight at most 1
+        opaque = w >= 1
+        w = torch.where(opaque, torch.ones_like(w), w)    # solid primitive: weight at most 1
+        omw = torch.where(opaque, torch.zeros_like(omw), omw)
     keep = valid & (w >= prm.tau)                         # filter (Sec. 3.2)
     if cand is not None:
         keep = keep & cand
@@ -126,7 +134,7 @@ def _pairs(center, quat, radii, cam, lam, pix, prm: OracleParams, cand=None):
     if prm.two_sided:
         s = -torch.sign(num)
         n_cam = n_cam * s[..., None]
-    return dict(t=t, w=w, keep=keep, n=n_cam, PX=PX, PY=PY, rX=rX, rY=rY, num=num, den=den)
+    return dict(t=t, w=w, omw=omw, keep=keep, n=n_cam, PX=PX, PY=PY, rX=rX, rY=rY, num=num, den=den)
 
 
 def _composite(q, prm: OracleParams):
@@ -140,6 +148,7 @@ def _composite(q, prm: OracleParams):
     sel = order[:, :Msel]
     ks = keep.gather(1, sel)
     w_s = torch.where(ks, w.gather(1, sel), torch.zeros((), dtype=F64))
+    o_s = torch.where(ks, q["omw"].gather(1, sel), torch.ones((), dtype=F64))   # 1 - w_s
     t_s = torch.where(ks, t.gather(1, sel), torch.zeros((), dtype=F64))
     if n.shape[0] == 1:
         n = n.expand(P, K, 3)
@@ -153,7 +162,7 @@ def _composite(q, prm: OracleParams):
         D = D + Tw * t_s[:, j]                            # Eq. 11
         N = N + Tw[:, None] * n_s[:, j]                   # Eq. 12
         cov = cov + Tw
-        T = T * (1 - w_s[:, j])                           # Eq. 13
+        T = T * o_s[:, j]                                 # Eq. 13, (1 - w_j)
     ids = torch.where(ks, sel, torch.full_like(sel, -1))
     return D, N, dict(count=ks.sum(1), coverage=cov.detach(), ids=ids, T=T.detach())
 

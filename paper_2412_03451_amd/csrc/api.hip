@@ -1,0 +1,154 @@
+// Host-side plumbing of the C ABI: error messages, batch layout, workspace.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "ps_internal.h"
+
+static thread_local char g_err[512] = "";
+
+extern "C" int ps_set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+extern "C" const char* ps_last_error(void) { return g_err; }
+
+static bool tile_ok(int tw, int th) {
+  return (tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8);
+}
+
+extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity, ps_layout* out) {
+  if (!slots || !out || n_slots <= 0)
+    return ps_set_error(PS_ERR_INVALID, "ps_layout_init: null pointer or n_slots <= 0");
+  if (pair_capacity < 1 || pair_capacity > (int64_t(1) << 31) - 1)
+    return ps_set_error(PS_ERR_INVALID, "ps_layout_init: pair_capacity %lld out of range",
+                        (long long)pair_capacity);
+  memset(out, 0, sizeof(*out));
+  int64_t rec = 0, tiles = 0, items = 0, pix = 0;
+  int max_sub = 1, n_planes = 0;
+  for (int s = 0; s < n_slots; ++s) {
+    ps_slot& sl = slots[s];
+    if (sl.plane_begin < 0 || sl.plane_end < sl.plane_begin)
+      return ps_set_error(PS_ERR_INVALID, "slot %d: bad plane range [%d, %d)", s, sl.plane_begin,
+                          sl.plane_end);
+    if (sl.width <= 0 || sl.height <= 0 || sl.width > 32767 || sl.height > 32767)
+      return ps_set_error(PS_ERR_INVALID, "slot %d: bad image size %dx%d", s, sl.width, sl.height);
+    if (!tile_ok(sl.tile_w, sl.tile_h))
+      return ps_set_error(PS_ERR_INVALID, "slot %d: tile %dx%d not one of 8x8, 16x16, 32x8", s,
+                          sl.tile_w, sl.tile_h);
+    if (sl.cam < 0) return ps_set_error(PS_ERR_INVALID, "slot %d: negative camera index", s);
+    sl.tiles_x = (sl.width + sl.tile_w - 1) / sl.tile_w;
+    sl.tiles_y = (sl.height + sl.tile_h - 1) / sl.tile_h;
+    const int sub = (sl.tile_w / 8) * (sl.tile_h / 8);
+    if (sub > max_sub) max_sub = sub;
+    sl.rec_begin = (int32_t)rec;
+    sl.tile_begin = (int32_t)tiles;
+    sl.item_begin = (int32_t)items;
+    sl.pix_off = pix;
+    sl.pad = 0;
+    rec += sl.plane_end - sl.plane_begin;
+    tiles += (int64_t)sl.tiles_x * sl.tiles_y;
+    items += (int64_t)sl.tiles_x * sl.tiles_y * sub;
+    pix += (int64_t)sl.width * sl.height;
+    if (sl.plane_end > n_planes) n_planes = sl.plane_end;
+  }
+  if (rec >= (int64_t(1) << 31) || tiles >= (int64_t(1) << 30) || items >= (int64_t(1) << 31))
+    return ps_set_error(PS_ERR_INVALID, "ps_layout_init: batch too large");
+  out->n_slots = n_slots;
+  out->n_records = (int32_t)rec;
+  out->n_tiles = (int32_t)tiles;
+  out->n_items = (int32_t)items;
+  out->n_pixels = pix;
+  out->pair_capacity = pair_capacity;
+  out->max_sub = max_sub;
+  out->n_planes = n_planes;
+  const size_t R = (size_t)rec, T = (size_t)tiles, C = (size_t)pair_capacity;
+  const size_t sizes[PS_NUM_REGIONS] = {
+      sizeof(ps_slot) * n_slots,       // R_SLOTS
+      sizeof(ps::Rec) * (R + 1),       // R_REC
+      sizeof(ps::BinRec) * (R + 1),    // R_BINREC
+      4 * (R + 1),                     // R_REC_CNT
+      4 * (R + 1),                     // R_REC_OFF
+      4 * (T + 1),                     // R_TILE_CNT
+      4 * (T + 1),                     // R_TILE_OFF
+      4 * (T + 1),                     // R_TILE_CUR
+      8 * C,                           // R_KEYS_U
+      4 * C,                           // R_EMIT_U
+      8 * C,                           // R_KEYS_S
+      4 * C,                           // R_EMIT_S
+      8 * 64,                          // R_COUNTERS
+      64 * C * (size_t)max_sub,        // R_PARTIAL
+      32 * ((size_t)items + 1),        // R_LOSS
+      4 * (T + 1),                     // R_BIGTILES
+  };
+  size_t off = 0;
+  for (int i = 0; i < PS_NUM_REGIONS; ++i) {
+    out->region[i] = off;
+    off = ps::align256(off + sizes[i]);
+  }
+  out->ws_bytes = off;
+  return PS_OK;
+}
+
+extern "C" size_t ps_workspace_bytes(const ps_layout* L) { return L ? L->ws_bytes : 0; }
+
+__global__ void ps_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void ps_set_cams_kernel(ps_slot* slots, int S, const int32_t* view) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S) slots[s].cam = view[s];
+}
+
+int ps_check_ws(const ps_layout* L, const void* ws, const char* who) {
+  if (!L || !ws) return ps_set_error(PS_ERR_INVALID, "%s: null layout or workspace", who);
+  if (((uintptr_t)ws) & 255) return ps_set_error(PS_ERR_INVALID, "%s: workspace not 256-byte aligned", who);
+  if (L->n_slots <= 0 || L->ws_bytes == 0) return ps_set_error(PS_ERR_INVALID, "%s: empty layout", who);
+  return PS_OK;
+}
+
+extern "C" int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void* ws, void* stream) {
+  int rc = ps_check_ws(L, ws, "ps_workspace_init");
+  if (rc) return rc;
+  if (!slots) return ps_set_error(PS_ERR_INVALID, "ps_workspace_init: null slots");
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  PS_HIP_CHECK(hipMemcpyAsync(base + L->region[ps::R_SLOTS], slots, sizeof(ps_slot) * L->n_slots,
+                              hipMemcpyHostToDevice, st));
+  const int64_t n = 2 * 64;  // counters as int32 words
+  hipLaunchKernelGGL(ps_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st,
+                     (int32_t*)(base + L->region[ps::R_COUNTERS]), n, 0);
+  PS_HIP_CHECK(hipGetLastError());
+  return PS_OK;
+}
+
+extern "C" int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_of_slot, void* stream) {
+  int rc = ps_check_ws(L, ws, "ps_set_cameras");
+  if (rc) return rc;
+  if (!view_of_slot) return ps_set_error(PS_ERR_INVALID, "ps_set_cameras: null view array");
+  char* base = (char*)ws;
+  hipLaunchKernelGGL(ps_set_cams_kernel, dim3((L->n_slots + 63) / 64), dim3(64), 0,
+                     (hipStream_t)stream, (ps_slot*)(base + L->region[ps::R_SLOTS]), L->n_slots,
+                     view_of_slot);
+  PS_HIP_CHECK(hipGetLastError());
+  return PS_OK;
+}
+
+extern "C" int ps_read_counters(const ps_layout* L, void* ws, int64_t out[4], void* stream) {
+  int rc = ps_check_ws(L, ws, "ps_read_counters");
+  if (rc) return rc;
+  if (!out) return ps_set_error(PS_ERR_INVALID, "ps_read_counters: null output");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t tmp[8];
+  PS_HIP_CHECK(hipMemcpyAsync(tmp, (char*)ws + L->region[ps::R_COUNTERS], sizeof(tmp),
+                              hipMemcpyDeviceToHost, st));
+  PS_HIP_CHECK(hipStreamSynchronize(st));
+  for (int i = 0; i < 4; ++i) out[i] = tmp[i];
+  return PS_OK;
+}

@@ -1,0 +1,321 @@
+// tile_bin: (tile, plane) pairs keyed by a per-tile depth lower bound.
+//
+//   count  (one thread per record): tiles of the record's footprint that pass
+//          a separating-axis test against the projected grown rectangle and
+//          have a hit in front of the camera; per-tile counts by atomics.
+//   scan   (one 1024-thread workgroup): exclusive prefix sums of the per-tile
+//          and per-record counts with wave64 shuffles plus one LDS pass per
+//          4096-element block; capacity and per-tile limits are checked here.
+//   emit   (one thread per record): key = (depth bound bits << 32 | record),
+//          value = emit index (record-major), scattered into tile segments.
+//   sort   (one workgroup per tile): bitonic sort of the tile's keys in LDS;
+//          keys are unique, so the order is deterministic.
+//
+// The depth bound of a record over a tile is the larger of (a) the minimum
+// camera z of its grown, near-clipped rectangle and (b) the minimum over the
+// tile's extreme pixel centers of h / den: den is affine in the pixel, so
+// t = h / den is smallest at a corner of the pixel-center rectangle.  It is
+// rounded down to float32 and lowered by one ulp, so the float32 depth of
+// every hit in the tile is >= its key.  The render loops rely on that to
+// commit hits in exact per-ray depth order.
+#include "ps_internal.h"
+
+using namespace ps;
+
+int ps_check_ws(const ps_layout* L, const void* ws, const char* who);
+__global__ void ps_fill_i32(int32_t* p, int64_t n, int32_t v);
+
+namespace {
+
+struct BinArgs {
+  const ps_slot* slots;
+  int S, R, T;
+  const Rec* recs;
+  const BinRec* brecs;
+  int* rec_cnt;
+  int* rec_off;
+  int* tile_cnt;
+  int* tile_off;
+  int* tile_cur;
+  uint64_t* keys_u;
+  uint32_t* emit_u;
+  uint64_t* keys_s;
+  uint32_t* emit_s;
+  long long* counters;
+  int* bigtiles;
+  long long capacity;
+};
+
+__device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot& sl, int tx, int ty,
+                                 float& key_t) {
+  int x0 = tx * sl.tile_w, y0 = ty * sl.tile_h;
+  int x1 = min(x0 + sl.tile_w, sl.width) - 1, y1 = min(y0 + sl.tile_h, sl.height) - 1;
+  x0 = max(x0, (int)rec.px0); x1 = min(x1, (int)rec.px1);
+  y0 = max(y0, (int)rec.py0); y1 = min(y1, (int)rec.py1);
+  if (x0 > x1 || y0 > y1) return false;
+  const double cu[4] = {x0 + 0.5, x1 + 0.5, x1 + 0.5, x0 + 0.5};
+  const double cv[4] = {y0 + 0.5, y0 + 0.5, y1 + 0.5, y1 + 0.5};
+  if (br.npoly >= 3) {
+    for (int e = 0; e < br.npoly; ++e) {
+      const float2 A = br.poly[e];
+      const float2 B = br.poly[(e + 1 == br.npoly) ? 0 : e + 1];
+      const double ex = (double)B.x - A.x, ey = (double)B.y - A.y;
+      const double len = sqrt(ex * ex + ey * ey);
+      double m = -1e300;
+      for (int c = 0; c < 4; ++c) m = fmax(m, ex * (cv[c] - A.y) - ey * (cu[c] - A.x));
+      if (m < -1.0 * len) return false;  // all corners more than one pixel outside this edge
+    }
+  }
+  double tmin = 1e300;
+  bool any = false;
+  for (int c = 0; c < 4; ++c) {
+    const double den = fma(rec.Du, cu[c], fma(rec.Dv, cv[c], rec.D0));
+    if (rec.h * den > 0.0) {
+      tmin = fmin(tmin, rec.h / den);
+      any = true;
+    }
+  }
+  if (!any) return false;
+  const float f = __double2float_rd(fmax((double)br.tlb, tmin));
+  key_t = __uint_as_float(__float_as_uint(f) - 1u);  // f > 0: one ulp towards zero
+  return true;
+}
+
+__global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.R) return;
+  const BinRec br = a.brecs[r];
+  int cnt = 0;
+  if (br.npoly != 0) {
+    const Rec rec = a.recs[r];
+    const ps_slot sl = a.slots[br.slot];
+    for (int ty = br.ty0; ty <= br.ty1; ++ty)
+      for (int tx = br.tx0; tx <= br.tx1; ++tx) {
+        float kt;
+        if (tile_test(rec, br, sl, tx, ty, kt)) {
+          ++cnt;
+          atomicAdd(&a.tile_cnt[sl.tile_begin + ty * sl.tiles_x + tx], 1);
+        }
+      }
+  }
+  a.rec_cnt[r] = cnt;
+}
+
+// Exclusive scan of in[0, n) into out[0, n], out[n] = total, by one
+// 1024-thread workgroup: blocks of 4096 elements, 4 per thread, wave64
+// inclusive scans by shuffles, wave totals through LDS, running carry.
+__device__ long long block_scan(const int* __restrict__ in, int* __restrict__ out, int n, int* lds_wave,
+                                int& maxv) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  long long carry = 0;
+  int mx = 0;
+  for (int base = 0; base < n; base += 4096) {
+    int v[4];
+    int local = 0;
+    for (int j = 0; j < 4; ++j) {
+      const int idx = base + tid * 4 + j;
+      v[j] = idx < n ? in[idx] : 0;
+      mx = max(mx, v[j]);
+      local += v[j];
+    }
+    int incl = local;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) lds_wave[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+      int x = lane < 16 ? lds_wave[lane] : 0;
+      int xi = x;
+      for (int o = 1; o < 16; o <<= 1) {
+        const int y = __shfl_up(xi, o, 64);
+        if (lane >= o) xi += y;
+      }
+      if (lane < 16) lds_wave[16 + lane] = xi - x;   // exclusive wave offsets
+      if (lane == 15) lds_wave[32] = xi;             // block total
+    }
+    __syncthreads();
+    int run = (int)carry + lds_wave[16 + wid] + (incl - local);
+    for (int j = 0; j < 4; ++j) {
+      const int idx = base + tid * 4 + j;
+      if (idx < n) out[idx] = run;
+      run += v[j];
+    }
+    carry += lds_wave[32];
+    __syncthreads();
+  }
+  // max over the workgroup
+  for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) lds_wave[wid] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    int m = 0;
+    for (int w = 0; w < 16; ++w) m = max(m, lds_wave[w]);
+    lds_wave[33] = m;
+  }
+  __syncthreads();
+  maxv = lds_wave[33];
+  if (tid == 0) out[n] = (int)carry;
+  __syncthreads();
+  return carry;
+}
+
+__global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
+  __shared__ int lds[40];
+  int mx_t = 0, mx_r = 0;
+  const long long total = block_scan(a.tile_cnt, a.tile_off, a.T, lds, mx_t);
+  block_scan(a.rec_cnt, a.rec_off, a.R, lds, mx_r);
+  // scatter cursors, big-tile list
+  __shared__ int nbig;
+  if (threadIdx.x == 0) nbig = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < a.T; t += blockDim.x) {
+    a.tile_cur[t] = 0;
+    const int c = a.tile_cnt[t];
+    if (c > kSmallSort && c <= kBigSort) {
+      const int slot = atomicAdd(&nbig, 1);
+      a.bigtiles[slot] = t;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.counters[C_PAIRS] = total;
+    a.counters[C_MAXTILE] = mx_t;
+    a.counters[C_NBIG] = nbig;
+    a.counters[C_OVERFLOW] = (total > a.capacity || mx_t > kBigSort) ? 1 : 0;
+    a.counters[C_SLOW] = 0;
+    a.counters[C_BWD_PASSES] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.R) return;
+  if (a.counters[C_OVERFLOW]) return;
+  const BinRec br = a.brecs[r];
+  if (br.npoly == 0) return;
+  const Rec rec = a.recs[r];
+  const ps_slot sl = a.slots[br.slot];
+  int j = 0;
+  const int e0 = a.rec_off[r];
+  for (int ty = br.ty0; ty <= br.ty1; ++ty)
+    for (int tx = br.tx0; tx <= br.tx1; ++tx) {
+      float kt;
+      if (tile_test(rec, br, sl, tx, ty, kt)) {
+        const int gt = sl.tile_begin + ty * sl.tiles_x + tx;
+        const int idx = a.tile_off[gt] + atomicAdd(&a.tile_cur[gt], 1);
+        a.keys_u[idx] = ((uint64_t)__float_as_uint(kt) << 32) | (uint32_t)r;
+        a.emit_u[idx] = (uint32_t)(e0 + j);
+        ++j;
+      }
+    }
+}
+
+template <int CAP, int NT>
+__device__ void lds_bitonic(uint64_t* k, uint32_t* v, int n, const uint64_t* __restrict__ kin,
+                            const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                            uint32_t* __restrict__ vout) {
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += NT) {
+    k[i] = i < n ? kin[i] : ~0ull;
+    v[i] = i < n ? vin[i] : 0u;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (n2 >> 1); i += NT) {
+        const int lo = ((i / stride) * 2 * stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t a = k[lo], b = k[hi];
+        if ((a > b) == up) {
+          k[lo] = b; k[hi] = a;
+          const uint32_t t = v[lo]; v[lo] = v[hi]; v[hi] = t;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += NT) {
+    kout[i] = k[i];
+    vout[i] = v[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
+  __shared__ uint64_t k[kSmallSort];
+  __shared__ uint32_t v[kSmallSort];
+  if (a.counters[C_OVERFLOW]) return;
+  const int t = blockIdx.x;
+  const int n = a.tile_cnt[t];
+  if (n == 0 || n > kSmallSort) return;
+  const int off = a.tile_off[t];
+  lds_bitonic<kSmallSort, 256>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off);
+}
+
+__global__ __launch_bounds__(1024) void bin_sort_big_kernel(BinArgs a) {
+  extern __shared__ unsigned char smem[];
+  uint64_t* k = (uint64_t*)smem;
+  uint32_t* v = (uint32_t*)(smem + 8 * kBigSort);
+  if (a.counters[C_OVERFLOW]) return;
+  const int nbig = (int)a.counters[C_NBIG];
+  for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
+    const int t = a.bigtiles[b];
+    const int n = a.tile_cnt[t];
+    const int off = a.tile_off[t];
+    lds_bitonic<kBigSort, 1024>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, void* stream) {
+  int rc = ps_check_ws(L, ws, "tile_bin");
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)ws;
+  BinArgs a;
+  a.slots = (const ps_slot*)(base + L->region[R_SLOTS]);
+  a.S = L->n_slots; a.R = L->n_records; a.T = L->n_tiles;
+  a.recs = (const Rec*)(base + L->region[R_REC]);
+  a.brecs = (const BinRec*)(base + L->region[R_BINREC]);
+  a.rec_cnt = (int*)(base + L->region[R_REC_CNT]);
+  a.rec_off = (int*)(base + L->region[R_REC_OFF]);
+  a.tile_cnt = (int*)(base + L->region[R_TILE_CNT]);
+  a.tile_off = (int*)(base + L->region[R_TILE_OFF]);
+  a.tile_cur = (int*)(base + L->region[R_TILE_CUR]);
+  a.keys_u = (uint64_t*)(base + L->region[R_KEYS_U]);
+  a.emit_u = (uint32_t*)(base + L->region[R_EMIT_U]);
+  a.keys_s = (uint64_t*)(base + L->region[R_KEYS_S]);
+  a.emit_s = (uint32_t*)(base + L->region[R_EMIT_S]);
+  a.counters = (long long*)(base + L->region[R_COUNTERS]);
+  a.bigtiles = (int*)(base + L->region[R_BIGTILES]);
+  a.capacity = L->pair_capacity;
+  hipLaunchKernelGGL(ps_fill_i32, dim3((a.T + 1 + 255) / 256), dim3(256), 0, st, a.tile_cnt,
+                     (int64_t)a.T + 1, 0);
+  if (a.R > 0)
+    hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 255) / 256), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, a);
+  if (a.R > 0)
+    hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + 255) / 256), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(bin_sort_small_kernel, dim3(a.T), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(bin_sort_big_kernel, dim3(32), dim3(1024), 12 * kBigSort, st, a);
+  PS_HIP_CHECK(hipGetLastError());
+  if (pairs_needed) {
+    long long c[2];
+    PS_HIP_CHECK(hipMemcpyAsync(c, a.counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    PS_HIP_CHECK(hipStreamSynchronize(st));
+    *pairs_needed = c[C_PAIRS];
+    if (c[C_OVERFLOW]) {
+      if (c[C_PAIRS] > L->pair_capacity)
+        return ps_set_error(PS_ERR_CAPACITY, "tile_bin: %lld pairs exceed capacity %lld",
+                            (long long)c[C_PAIRS], (long long)L->pair_capacity);
+      return ps_set_error(PS_ERR_CAPACITY, "tile_bin: a tile holds more than %d pairs; use smaller tiles",
+                          kBigSort);
+    }
+  }
+  return PS_OK;
+}

@@ -1,0 +1,257 @@
+// Internal definitions shared by the HIP kernels of the plane splatting library.
+// Device-side record layouts, workspace regions and wave64 helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "planesplat.h"
+
+namespace ps {
+
+// ---------------------------------------------------------------------------
+// Projection record: one per (plane, job).
+//
+// With the camera-frame pixel ray d_c(u, v) = ((u - cx)/fx, (v - cy)/fy, 1)
+// (pixel center (u, v) = (i + 1/2, j + 1/2)) and the quantities of Frame
+// below, the ray parameter of Eq. 4 and the in-plane coordinates of Eq. 6 are
+//   t   = h / den,        den = d_c . nc          (d_c has z = 1: z-depth)
+//   P_X = AX / den,       AX  = d_c . (h vxc - pvx nc)
+//   P_Y = AY / den,       AY  = d_c . (h vyc - pvy nc)
+// and den, AX, AY are affine in (u, v).  Their coefficients are kept in
+// float64: the fringe of a rectangle is a few millimetres wide at
+// lambda = 300 (sigmoid slope 1500 / m) while the ray meets it metres away, so
+// float32 positions would already move fringe weights by ~1e-4.
+// 128 bytes: two 64-byte scalar loads per candidate in the render loops.
+struct alignas(16) Rec {
+  double D0, Du, Dv;          // den(u, v) = D0 + Du u + Dv v
+  double X0, Xu, Xv;          // AX(u, v)
+  double Y0, Yu, Yv;          // AY(u, v)
+  double h;                   // (p - o) . n
+  float rxp, rxm, ryp, rym;   // radii (Eq. 1)
+  float nx, ny, nz;           // rendered normal: R n, facing the camera
+  int32_t cull;               // 1: no pixel of the job can see this record
+  int16_t px0, py0, px1, py1; // inclusive pixel box of the grown footprint
+  float pvx, pvy;             // (p - o) . vx, (p - o) . vy (backward only)
+};
+static_assert(sizeof(Rec) == 128, "Rec must stay 128 bytes");
+
+// Binning view of a record: the projected, near-clipped footprint polygon of
+// the rectangle grown by the fringe margin, and a depth lower bound.
+struct alignas(16) BinRec {
+  float2 poly[5];   // convex polygon, counter-clockwise in pixel coordinates
+  int32_t npoly;    // 0: culled; 3..5 vertices; -1: degenerate, box test only
+  float tlb;        // min camera z over the clipped grown rectangle (rounded down)
+  int32_t tx0, ty0, tx1, ty1;  // inclusive tile rectangle
+  int32_t slot;
+  int32_t pad[3];
+};
+static_assert(sizeof(BinRec) == 80, "BinRec size");
+
+// Workspace regions (byte offsets in ps_layout.region).
+enum Region {
+  R_SLOTS = 0,   // ps_slot[S]
+  R_REC,         // Rec[R]
+  R_BINREC,      // BinRec[R]
+  R_REC_CNT,     // int[R + 1]   tiles per record
+  R_REC_OFF,     // int[R + 1]   exclusive scan of R_REC_CNT (emit index base)
+  R_TILE_CNT,    // int[T + 1]   records per tile
+  R_TILE_OFF,    // int[T + 1]   exclusive scan of R_TILE_CNT
+  R_TILE_CUR,    // int[T]       scatter cursors
+  R_KEYS_U,      // uint64[C]    unsorted (depth bound, record) keys
+  R_EMIT_U,      // uint32[C]    unsorted emit indices
+  R_KEYS_S,      // uint64[C]    keys sorted per tile
+  R_EMIT_S,      // uint32[C]    emit indices in sorted order
+  R_COUNTERS,    // int64[64]
+  R_PARTIAL,     // float[C][max_sub][16]  backward partials per (pair, 8x8 block)
+  R_LOSS,        // double[n_items][4]     loss partials per 8x8 block
+  R_BIGTILES,    // int[T]       tiles whose list exceeds the small sort
+};
+
+enum Counter {
+  C_PAIRS = 0,     // pairs needed
+  C_OVERFLOW = 1,  // nonzero: pairs exceed capacity or a tile exceeds the sort limit
+  C_MAXTILE = 2,   // largest tile list
+  C_SLOW = 3,      // pixels that took the exact fallback ordering path
+  C_NBIG = 4,      // number of big tiles
+  C_BWD_PASSES = 5 // extra backward recompute passes taken
+};
+
+constexpr int kMaxM = 30;
+constexpr int kSmallSort = 1024;  // tile lists up to this size sort in one small-LDS pass
+constexpr int kBigSort = 4096;    // hard limit of one tile list (48 KB of LDS)
+
+inline __host__ __device__ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Job lookup: largest s with slots[s].<field> <= x (slots sorted by field).
+__device__ inline int find_slot_by_item(const ps_slot* __restrict__ sl, int S, int item) {
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sl[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int find_slot_by_rec(const ps_slot* __restrict__ sl, int S, int rec) {
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sl[mid].rec_begin <= rec) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// float64 reciprocal: hardware estimate refined by two Newton steps.
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Fringe margin: w >= tau  <=>  a* >= -delta (closed form of the weight).
+__device__ __host__ inline double fringe_margin(double lam, double tau, int mode) {
+  const double z = (mode == 0) ? log(2.0 / tau - 1.0) : log(1.0 / tau - 1.0);
+  return z / (5.0 * lam);
+}
+
+// Splat weight from a* (Eq. 7-9; mode 0 clamps the printed 2 sigmoid at 1)
+// and omw = 1 - w formed from the same argument by an identity
+// (1 - 2 s(z) = tanh(-z/2) = expm1(-z) / (expm1(-z) + 2), 1 - s(z) = s(-z)),
+// not by a subtraction: behind a nearly opaque layer the transmittance keeps
+// its relative precision.
+__device__ inline float splat_weight(float a, float lam5, int mode, float& omw) {
+  const float z = lam5 * a;
+  if (mode == 0) {
+    if (a >= 0.f) {
+      omw = 0.f;
+      return 1.f;
+    }
+    const float em = expm1f(-z);  // > 0
+    const float d = em + 2.f;
+    omw = em / d;
+    return 2.f / d;
+  }
+  const float e = expf(-z);
+  const float d = 1.f + e;
+  omw = e / d;
+  return 1.f / d;
+}
+// dw/da* (0 on the opaque side of mode 0).
+__device__ inline float splat_weight_grad(float a, float w, float omw, float lam5, int mode) {
+  if (mode == 0) return (a >= 0.f) ? 0.f : lam5 * w * (1.f - 0.5f * w);
+  return lam5 * w * omw;
+}
+
+// Per-lane ray-plane evaluation in float64 (Eq. 4, 6, 7-9 up to a*).
+struct PairGeom {
+  double den, PX, PY, t;
+  double a;        // a* = min(a_X, a_Y)
+  bool ok;         // valid hit in front of the near plane with w >= tau
+  bool xbranch;    // a_X < a_Y: Eq. 9 takes w_X (tie -> w_Y)
+};
+
+__device__ inline PairGeom eval_pair(const Rec& r, double u, double v, double eps_den, double z_near,
+                                     double delta) {
+  PairGeom g;
+  g.den = fma(r.Du, u, fma(r.Dv, v, r.D0));
+  const double ax = fma(r.Xu, u, fma(r.Xv, v, r.X0));
+  const double ay = fma(r.Yu, u, fma(r.Yv, v, r.Y0));
+  const bool okd = fabs(g.den) > eps_den;
+  const double rd = rcp64(okd ? g.den : 1.0);
+  g.t = r.h * rd;
+  g.PX = ax * rd;
+  g.PY = ay * rd;
+  const double aX = (g.PX > 0.0) ? (double)r.rxp - g.PX : (double)r.rxm + g.PX;
+  const double aY = (g.PY > 0.0) ? (double)r.ryp - g.PY : (double)r.rym + g.PY;
+  g.xbranch = aX < aY;
+  g.a = g.xbranch ? aX : aY;
+  g.ok = okd && (g.t > z_near) && (g.a >= -delta);
+  return g;
+}
+
+// Strict order of hits: float32 depth, then record index (= plane order).
+__device__ inline bool key_less(float ta, int ia, float tb, int ib) {
+  return ta < tb || (ta == tb && ia < ib);
+}
+
+}  // namespace ps
+
+// error plumbing (api.hip)
+extern "C" int ps_set_error(int code, const char* fmt, ...);
+#define PS_HIP_CHECK(expr)                                                      \
+  do {                                                                          \
+    hipError_t _e = (expr);                                                     \
+    if (_e != hipSuccess)                                                       \
+      return ps_set_error(PS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(_e));  \
+  } while (0)
+
+namespace ps {
+
+// Frame of plane k as seen by one camera, float64.  The camera maps world to
+// camera coordinates by x_c = R x + t; the ray of camera direction d_c starts
+// at o = -R^T t with world direction d = R^T d_c (the matrix is float32 input,
+// not exactly orthogonal, so everything is written with these exact
+// identities and never with R^T R = I):
+//   d . n   = d_c . (R n)                    -> nc = R n
+//   (p - o) . n = p . n + t . (R n)          -> h
+//   (p - o) . vx = p . vx + t . (R vx)       -> pvx (likewise pvy)
+// so t = h / (d_c . nc) and P_X = (h (d_c . vxc) - pvx (d_c . nc)) / (d_c . nc).
+struct Frame {
+  double p[3], n[3], vx[3], vy[3];  // world center and local frame (Eq. 2-3)
+  double nc[3], vxc[3], vyc[3];     // R n, R vx, R vy
+  double h, pvx, pvy;
+  double q[4];                      // normalised quaternion (w, x, y, z)
+  double qnorm;                     // |q| before normalisation
+};
+
+__device__ inline bool plane_frame(const float* __restrict__ center, const float* __restrict__ quat,
+                                   int k, const ps_camera& cam, Frame& f) {
+  double w = quat[4 * k + 0], x = quat[4 * k + 1], y = quat[4 * k + 2], z = quat[4 * k + 3];
+  const double qn = sqrt(w * w + x * x + y * y + z * z);
+  f.qnorm = qn;
+  if (!(qn > 1e-30)) return false;
+  w /= qn; x /= qn; y /= qn; z /= qn;
+  f.q[0] = w; f.q[1] = x; f.q[2] = y; f.q[3] = z;
+  // columns of R(q)
+  f.vx[0] = 1 - 2 * (y * y + z * z); f.vx[1] = 2 * (x * y + w * z); f.vx[2] = 2 * (x * z - w * y);
+  f.vy[0] = 2 * (x * y - w * z); f.vy[1] = 1 - 2 * (x * x + z * z); f.vy[2] = 2 * (y * z + w * x);
+  f.n[0] = 2 * (x * z + w * y); f.n[1] = 2 * (y * z - w * x); f.n[2] = 1 - 2 * (x * x + y * y);
+  for (int a = 0; a < 3; ++a) f.p[a] = center[3 * k + a];
+  for (int a = 0; a < 3; ++a) {
+    const double r0 = cam.R[3 * a + 0], r1 = cam.R[3 * a + 1], r2 = cam.R[3 * a + 2];
+    f.nc[a] = r0 * f.n[0] + r1 * f.n[1] + r2 * f.n[2];
+    f.vxc[a] = r0 * f.vx[0] + r1 * f.vx[1] + r2 * f.vx[2];
+    f.vyc[a] = r0 * f.vy[0] + r1 * f.vy[1] + r2 * f.vy[2];
+  }
+  const double t0 = cam.t[0], t1 = cam.t[1], t2 = cam.t[2];
+  f.h = (f.p[0] * f.n[0] + f.p[1] * f.n[1] + f.p[2] * f.n[2]) + (t0 * f.nc[0] + t1 * f.nc[1] + t2 * f.nc[2]);
+  f.pvx = (f.p[0] * f.vx[0] + f.p[1] * f.vx[1] + f.p[2] * f.vx[2]) + (t0 * f.vxc[0] + t1 * f.vxc[1] + t2 * f.vxc[2]);
+  f.pvy = (f.p[0] * f.vy[0] + f.p[1] * f.vy[1] + f.p[2] * f.vy[2]) + (t0 * f.vyc[0] + t1 * f.vyc[1] + t2 * f.vyc[2]);
+  return true;
+}
+
+}  // namespace ps

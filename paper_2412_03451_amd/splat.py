@@ -1,0 +1,219 @@
+"""Python front end of the splatting library: torch tensors in, C ABI calls out.
+
+torch provides device memory and the current HIP stream; every computation
+is a call into libplanesplat.so.  A `Renderer` owns one batch layout and its
+workspace.  Typical use::
+
+    r = Renderer.single_scene(cams, K, tile=(16, 16))
+    depth, normal = r.render(center, quat, radii, lam)
+    loss, gD, gN = r.loss(depth, normal, tgt_depth, tgt_normal)
+    gc, gq, gr = r.backward(center, quat, radii, lam, gD, gN)
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PsCamera, PsLayout, PsParams, PsSlot, check
+
+
+@dataclass
+class SplatParams:
+    """Method constants (Sec. 3.2) and readings; see include/planesplat.h."""
+    M: int = 30
+    tau: float = 1e-4
+    z_near: float = 0.01
+    weight_mode: int = 0   # 0: min(1, 2 sigmoid), 1: sigmoid
+    two_sided: int = 1
+    flags: int = 0         # bit 0: force the exact fallback ordering path
+
+    def c(self) -> PsParams:
+        return PsParams(self.M, self.tau, self.z_near, self.weight_mode, self.two_sided, self.flags)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def pack_cameras(cams, device="cuda") -> torch.Tensor:
+    """Cameras (objects with width, height, fx, fy, cx, cy, R[3x3], t[3]) as a
+    device byte tensor of ps_camera structs."""
+    arr = (PsCamera * len(cams))()
+    for i, cm in enumerate(cams):
+        arr[i].width, arr[i].height = int(cm.width), int(cm.height)
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = float(cm.fx), float(cm.fy), float(cm.cx), float(cm.cy)
+        R = np.asarray(cm.R, np.float32).reshape(9)
+        t = np.asarray(cm.t, np.float32).reshape(3)
+        for j in range(9):
+            arr[i].R[j] = float(R[j])
+        for j in range(3):
+            arr[i].t[j] = float(t[j])
+    buf = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    return buf.to(device)
+
+
+@dataclass
+class Job:
+    plane_begin: int
+    plane_end: int
+    cam: int
+    width: int
+    height: int
+    tile: tuple = (16, 16)
+    scene: int = 0
+
+
+class Renderer:
+    """One batch of render jobs (views / scenes) with its device workspace."""
+
+    def __init__(self, jobs: Sequence[Job], cams, device="cuda", pair_capacity: int | None = None,
+                 params: SplatParams | None = None):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.jobs = list(jobs)
+        self.params = params or SplatParams()
+        self.cams_host = list(cams) if not isinstance(cams, torch.Tensor) else None
+        self.cams = cams if isinstance(cams, torch.Tensor) else pack_cameras(cams, self.device)
+        self.n_cams = self.cams.numel() // C.sizeof(PsCamera)
+        if pair_capacity is None:
+            pair_capacity = 1 << 16
+        self._make_layout(int(pair_capacity))
+        self.last_pairs = 0
+
+    @classmethod
+    def single_scene(cls, cams, K: int, tile=(16, 16), **kw):
+        jobs = [Job(0, K, i, int(c.width), int(c.height), tile) for i, c in enumerate(cams)]
+        return cls(jobs, cams, **kw)
+
+    # ------------------------------------------------------------------ layout
+    def _make_layout(self, capacity: int):
+        S = len(self.jobs)
+        slots = (PsSlot * S)()
+        for i, j in enumerate(self.jobs):
+            s = slots[i]
+            s.plane_begin, s.plane_end, s.cam = j.plane_begin, j.plane_end, j.cam
+            s.width, s.height = j.width, j.height
+            s.tile_w, s.tile_h = j.tile
+            s.scene = j.scene
+        L = PsLayout()
+        check(self.lib.ps_layout_init(slots, S, capacity, C.byref(L)))
+        self.slots = slots
+        self.L = L
+        self.ws = torch.empty(int(L.ws_bytes), dtype=torch.uint8, device=self.device)
+        check(self.lib.ps_workspace_init(C.byref(L), slots, _ptr(self.ws), _stream()))
+        # offsets of each job's outputs
+        self.pix_off = [int(slots[i].pix_off) for i in range(S)]
+
+    @property
+    def n_pixels(self) -> int:
+        return int(self.L.n_pixels)
+
+    @property
+    def n_planes(self) -> int:
+        return int(self.L.n_planes)
+
+    def region(self, i: int, dtype, count: int) -> torch.Tensor:
+        """View of workspace region i (for tests and diagnostics)."""
+        off = int(self.L.region[i])
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        return self.ws[off:off + count * itemsize].view(dtype)
+
+    # ------------------------------------------------------------------ steps
+    def project(self, center, quat, radii, lam):
+        self._inputs = (center, quat, radii, lam)
+        prm = self.params.c()
+        check(self.lib.plane_project(C.byref(self.L), _ptr(self.ws), _ptr(center), _ptr(quat), _ptr(radii),
+                                     int(center.shape[0]), _ptr(self.cams), self.n_cams, _ptr(lam),
+                                     C.byref(prm), _stream()))
+
+    def bin(self, check_capacity: bool = True, grow: float = 1.5):
+        if not check_capacity:
+            check(self.lib.tile_bin(C.byref(self.L), _ptr(self.ws), None, _stream()))
+            return
+        need = C.c_int64(0)
+        rc = self.lib.tile_bin(C.byref(self.L), _ptr(self.ws), C.byref(need), _stream())
+        if rc == _lib.PS_ERR_CAPACITY and need.value > self.L.pair_capacity:
+            self._make_layout(int(need.value * grow) + 1024)
+            self.project(*self._inputs)
+            rc = self.lib.tile_bin(C.byref(self.L), _ptr(self.ws), C.byref(need), _stream())
+        check(rc)
+        self.last_pairs = int(need.value)
+
+    def forward(self, diagnostics: bool = False):
+        """Depth [n_pixels] and normal [3 n_pixels]; with diagnostics also the
+        final transmittance and the number of composited hits per pixel."""
+        depth = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
+        normal = torch.empty(3 * self.n_pixels, dtype=torch.float32, device=self.device)
+        trans = count = None
+        if diagnostics:
+            trans = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
+            count = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
+        prm = self.params.c()
+        _, _, _, lam = self._inputs
+        check(self.lib.plane_render_fwd(C.byref(self.L), _ptr(self.ws), _ptr(self.cams), self.n_cams, _ptr(lam),
+                                        C.byref(prm), _ptr(depth), _ptr(normal), _ptr(trans), _ptr(count),
+                                        _stream()))
+        if diagnostics:
+            return depth, normal, trans, count
+        return depth, normal
+
+    def render(self, center, quat, radii, lam):
+        self.project(center, quat, radii, lam)
+        self.bin()
+        return self.forward()
+
+    def loss(self, depth, normal, tgt_depth, tgt_normal, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0):
+        loss = torch.empty(len(self.jobs), 4, dtype=torch.float32, device=self.device)
+        gD = torch.empty_like(depth)
+        gN = torch.empty_like(normal)
+        check(self.lib.loss_depth_normal(C.byref(self.L), _ptr(self.ws), _ptr(depth), _ptr(normal),
+                                         _ptr(tgt_depth), _ptr(tgt_normal), _ptr(mask), a_cos, a_nl1, a_d,
+                                         _ptr(loss), _ptr(gD), _ptr(gN), _stream()))
+        return loss, gD, gN
+
+    def backward(self, center, quat, radii, lam, g_depth, g_normal):
+        K = int(center.shape[0])
+        gc = torch.empty(K, 3, dtype=torch.float32, device=self.device)
+        gq = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        gr = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        prm = self.params.c()
+        check(self.lib.plane_render_bwd(C.byref(self.L), _ptr(self.ws), _ptr(center), _ptr(quat), _ptr(radii), K,
+                                        _ptr(self.cams), self.n_cams, _ptr(lam), C.byref(prm),
+                                        _ptr(g_depth.contiguous()), _ptr(g_normal.contiguous()),
+                                        _ptr(gc), _ptr(gq), _ptr(gr), _stream()))
+        return gc, gq, gr
+
+    def counters(self):
+        out = (C.c_int64 * 4)()
+        check(self.lib.ps_read_counters(C.byref(self.L), _ptr(self.ws), out, _stream()))
+        return dict(pairs=out[0], overflow=out[1], max_tile=out[2], slow_pixels=out[3])
+
+    # ------------------------------------------------------------------ image views
+    def job_depth(self, depth, s):
+        j = self.jobs[s]
+        o = self.pix_off[s]
+        return depth[o:o + j.width * j.height].view(j.height, j.width)
+
+    def job_normal(self, normal, s):
+        j = self.jobs[s]
+        o = self.pix_off[s]
+        return normal[3 * o:3 * (o + j.width * j.height)].view(3, j.height, j.width)
+
+
+def adam_step(center, quat, radii, g_center, g_quat, g_radii, m, v, step, lr=(1e-3, 1e-3, 1e-3),
+              betas=(0.9, 0.999), eps=1e-8, r_min=1e-4):
+    """In-place Adam on the plane parameters (adam_step_planes)."""
+    lib = _lib.load()
+    check(lib.adam_step_planes(_ptr(center), _ptr(quat), _ptr(radii), _ptr(g_center), _ptr(g_quat),
+                               _ptr(g_radii), _ptr(m), _ptr(v), int(center.shape[0]), _ptr(step),
+                               lr[0], lr[1], lr[2], betas[0], betas[1], eps, r_min, _stream()))

@@ -49,6 +49,12 @@ class Camera:
     R: np.ndarray = field(default_factory=lambda: np.eye(3, dtype=np.float32))  # world->camera
     t: np.ndarray = field(default_factory=lambda: np.zeros(3, dtype=np.float32))
 
+    def __post_init__(self):
+        # every consumer (float64 oracle, float32 kernels) sees the same values
+        self.fx, self.fy, self.cx, self.cy = (float(np.float32(v)) for v in (self.fx, self.fy, self.cx, self.cy))
+        self.R = np.asarray(self.R, np.float32).reshape(3, 3)
+        self.t = np.asarray(self.t, np.float32).reshape(3)
+
     def center(self) -> np.ndarray:
         return -(self.R.astype(np.float64).T @ self.t.astype(np.float64))
 

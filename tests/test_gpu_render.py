@@ -1,0 +1,274 @@
+"""GPU parity of plane_project + tile_bin + plane_render_fwd against the
+float64 oracle, element by element (run on an MI355X).
+
+Bar: depth within 1e-5 * max(|ref|, 1 m) and normal components within 1e-5
+on every pixel, at lambda(0) and at lambda = 300, for both weight readings,
+all three tile shapes, ragged image sizes, several views, and the forced
+exact-fallback ordering path.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import depth_err, f32, normal_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def _render_gpu(ps, cams, lam, tile=(16, 16), params=None, capacity=None):
+    from paper_2412_03451_amd.splat import Renderer, SplatParams
+    r = Renderer.single_scene(cams, ps.K, tile=tile, params=params or SplatParams(), pair_capacity=capacity)
+    c, q, rr = _dev(ps.center), _dev(ps.quat), _dev(ps.radii)
+    lt = torch.tensor([lam], dtype=torch.float32, device="cuda")
+    D, N = r.render(c, q, rr, lt)
+    torch.cuda.synchronize()
+    return r, D, N
+
+
+def _check_views(r, D, N, ps, cams, lam, prm=oracle.OracleParams(), label=""):
+    worst = 0.0
+    for s, cam in enumerate(cams):
+        Dg = r.job_depth(D, s).cpu().numpy()
+        Ng = r.job_normal(N, s).cpu().numpy()
+        Dr, Nr, aux = oracle.render(ps.center, ps.quat, ps.radii, cam, f32(lam), prm)
+        ed = depth_err(Dg, Dr.numpy())
+        en = normal_err(Ng, Nr.numpy())
+        worst = max(worst, float(ed.max()), float(en.max()))
+        print(f"{label} view {s}: hits {int((aux['count'] > 0).sum())} max depth err {ed.max():.3g} "
+              f"max normal err {en.max():.3g} (units of 1e-5)", flush=True)
+        assert ed.max() <= 1.0, np.unravel_index(np.argmax(ed), ed.shape)
+        assert en.max() <= 1.0
+    return worst
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("lam", [oracle.lambda_at(0), 300.0])
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8)])
+def test_forward_tiny_scene(mode, lam, tile):
+    from paper_2412_03451_amd.splat import SplatParams
+    ps = synth.random_planes(64, seed=0)
+    cam = synth.tiny_camera()
+    r, D, N = _render_gpu(ps, [cam], lam, tile, SplatParams(weight_mode=mode))
+    prm = oracle.OracleParams(weight_mode="A" if mode == 0 else "B")
+    _check_views(r, D, N, ps, [cam], lam, prm, f"mode {mode} lam {lam:.3g} tile {tile}")
+
+
+def test_forward_fallback_path_matches():
+    """flags bit 0 sends every pixel through the exact per-pixel selection."""
+    from paper_2412_03451_amd.splat import SplatParams
+    ps = synth.random_planes(64, seed=1, independent_radii=True)
+    cam = synth.tiny_camera()
+    lam = 20.0
+    r, D, N = _render_gpu(ps, [cam], lam, (16, 16), SplatParams(flags=1))
+    assert r.counters()["slow_pixels"] == cam.width * cam.height
+    _check_views(r, D, N, ps, [cam], lam, label="fallback")
+    r2, D2, N2 = _render_gpu(ps, [cam], lam, (16, 16), SplatParams())
+    # both paths commit the same hits in the same order: identical bits
+    assert torch.equal(D, D2) and torch.equal(N, N2)
+
+
+def test_forward_small_M_and_dense_overlap():
+    """Many overlapping planes in front of each other exercise the first-M cut
+    and the pending-hit buffer."""
+    from paper_2412_03451_amd.splat import SplatParams
+    ps = synth.random_planes(200, seed=2, center_range=0.4, extent_range=(0.3, 0.8))
+    cam = synth.tiny_camera()
+    for M, lam in ((30, oracle.lambda_at(0)), (5, 30.0), (1, 300.0)):
+        r, D, N = _render_gpu(ps, [cam], lam, (16, 16), SplatParams(M=M))
+        _check_views(r, D, N, ps, [cam], lam, oracle.OracleParams(M=M), f"M={M}")
+        print("counters", r.counters(), flush=True)
+
+
+def _rot(ax, ang):
+    c, s = math.cos(ang), math.sin(ang)
+    if ax == 0:
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    if ax == 1:
+        return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+def test_forward_ragged_multi_view():
+    ps = synth.random_planes(96, seed=3, independent_radii=True)
+    cams = []
+    for i, (W, H, f) in enumerate(((100, 75, 80.0), (37, 29, 30.0), (130, 97, 110.0))):
+        R = _rot(1, 0.25 * (i - 1)) @ _rot(0, 0.1 * i)
+        c = synth.Camera(W, H, f, f * 1.05, W / 2 + 3.3, H / 2 - 2.1, R.astype(np.float32),
+                         np.array([0.05 * i, -0.1, 3.0 + 0.2 * i], np.float32))
+        cams.append(c)
+    from paper_2412_03451_amd.splat import Job, Renderer
+    for tile in ((8, 8), (16, 16), (32, 8)):
+        jobs = [Job(0, ps.K, i, c.width, c.height, tile) for i, c in enumerate(cams)]
+        r = Renderer(jobs, cams)
+        lt = torch.tensor([15.0], device="cuda")
+        D, N = r.render(_dev(ps.center), _dev(ps.quat), _dev(ps.radii), lt)
+        torch.cuda.synchronize()
+        _check_views(r, D, N, ps, cams, 15.0, label=f"ragged {tile}")
+
+
+def test_binning_is_a_superset_and_sorted():
+    """Every (pixel, plane) pair the oracle keeps is in the pixel's tile list,
+    each tile list is sorted by its key, and every hit's float32 depth is at
+    least its key's depth bound."""
+    from paper_2412_03451_amd.splat import Renderer
+    ps = synth.random_planes(64, seed=4, independent_radii=True)
+    cam = synth.tiny_camera()
+    lam = oracle.lambda_at(0)
+    for tile in ((8, 8), (16, 16), (32, 8)):
+        r = Renderer.single_scene([cam], ps.K, tile=tile)
+        r.render(_dev(ps.center), _dev(ps.quat), _dev(ps.radii), torch.tensor([lam], device="cuda"))
+        torch.cuda.synchronize()
+        L = r.L
+        T = L.n_tiles
+        pairs = r.counters()["pairs"]
+        off = r.region(6, torch.int32, T + 1).cpu().numpy()
+        keys = r.region(10, torch.int64, pairs).cpu().numpy().view(np.uint64)
+        assert off[-1] == pairs
+        tl = (keys >> np.uint64(32)).astype(np.uint32).view(np.float32)
+        rec = (keys & np.uint64(0xffffffff)).astype(np.int64)
+        from oracle.render import _pairs
+        pix = torch.arange(cam.width * cam.height)
+        c, q, rr = (torch.as_tensor(x, dtype=torch.float64) for x in (ps.center, ps.quat, ps.radii))
+        qq = _pairs(c, q, rr, cam, lam, pix, oracle.OracleParams())
+        keep = qq["keep"].numpy()
+        t32 = qq["t"].numpy().astype(np.float32)
+        tiles_x = (cam.width + tile[0] - 1) // tile[0]
+        for t in range(T):
+            seg = slice(off[t], off[t + 1])
+            ks = keys[seg]
+            assert np.all(ks[1:] > ks[:-1])
+            members = set(rec[seg].tolist())
+            tx, ty = t % tiles_x, t // tiles_x
+            for j in range(ty * tile[1], min(cam.height, (ty + 1) * tile[1])):
+                for i in range(tx * tile[0], min(cam.width, (tx + 1) * tile[0])):
+                    p = j * cam.width + i
+                    for k in np.flatnonzero(keep[p]):
+                        assert k in members, (tile, t, i, j, k)
+                        pos = off[t] + list(rec[seg]).index(k)
+                        assert t32[p, k] >= tl[pos]
+
+
+def test_room_view_sampled_pixels():
+    """Full-size room view (640x480, ~2000 planes): oracle on sampled pixels."""
+    gt, info = synth.room_planes(seed=0, target_K=2000)
+    init = synth.room_init_planes(gt, seed=1)
+    cams = synth.room_trajectory(seed=0, n_views=4, info=info)
+    from paper_2412_03451_amd.splat import Renderer
+    for lam in (oracle.lambda_at(0), 300.0):
+        r = Renderer.single_scene(cams, init.K, tile=(16, 16))
+        r.project(_dev(init.center), _dev(init.quat), _dev(init.radii), torch.tensor([lam], device="cuda"))
+        r.bin()
+        D, N, T, cnt = r.forward(diagnostics=True)
+        torch.cuda.synchronize()
+        print("room counters", r.counters(), flush=True)
+        rng = np.random.default_rng(5)
+        for s, cam in enumerate(cams[:2]):
+            pix = rng.choice(cam.width * cam.height, size=600, replace=False)
+            Dr, Nr, aux = oracle.render_pixels(init.center, init.quat, init.radii, cam, f32(lam), pix)
+            Dg = r.job_depth(D, s).reshape(-1).cpu().numpy()[pix]
+            Ng = r.job_normal(N, s).reshape(3, -1).cpu().numpy()[:, pix]
+            o = r.pix_off[s]
+            Tg = T[o:o + cam.width * cam.height].cpu().numpy()[pix]
+            cg = cnt[o:o + cam.width * cam.height].cpu().numpy()[pix]
+            ed = depth_err(Dg, Dr.numpy())
+            en = normal_err(Ng, Nr.numpy().T)
+            same_count = np.mean(cg == aux["count"].numpy())
+            print(f"room lam {lam:.3g} view {s}: max depth err {ed.max():.3g} normal {en.max():.3g} "
+                  f"count agreement {same_count:.4f} max |T - T_ref| {np.abs(Tg - aux['T'].numpy()).max():.3g}",
+                  flush=True)
+            worst = np.argsort(-(ed + en.max(0)))[:3]
+            for w in worst:
+                print(f"  pixel {pix[w]}: D {Dg[w]:.7g} ref {Dr[w].item():.7g} N {Ng[:, w]} ref {Nr[w].numpy()} "
+                      f"count {cg[w]} ref {aux['count'][w].item()} T {Tg[w]:.4g} ref {aux['T'][w].item():.4g} "
+                      f"ids {aux['ids'][w][aux['ids'][w] >= 0].tolist()}", flush=True)
+            assert ed.max() <= 1.0 and en.max() <= 1.0
+
+
+def test_empty_scene_and_all_culled():
+    """No planes in view: depth and normal are exactly zero."""
+    ps = synth.random_planes(16, seed=6)
+    ps.center[:, 2] = -10.0   # all behind the camera
+    cam = synth.tiny_camera()
+    r, D, N = _render_gpu(ps, [cam], 50.0)
+    assert float(D.abs().max()) == 0.0 and float(N.abs().max()) == 0.0
+    assert r.counters()["pairs"] == 0
+
+
+def test_capacity_growth():
+    """A too-small pair capacity is detected and the binning is redone."""
+    ps = synth.random_planes(64, seed=0)
+    cam = synth.tiny_camera()
+    r, D, N = _render_gpu(ps, [cam], oracle.lambda_at(0), capacity=16)
+    assert r.L.pair_capacity >= r.counters()["pairs"] > 16
+    _check_views(r, D, N, ps, [cam], oracle.lambda_at(0), label="regrown")
+
+
+def _check_bounds(r, ps, cams, lam, n_tiles_sample=None, seed=0):
+    """For sampled tiles: every pair the oracle keeps is listed in the tile and
+    its float32 depth is >= the tile key's depth bound."""
+    from oracle.render import _pairs
+    pairs = r.counters()["pairs"]
+    L = r.L
+    off = r.region(6, torch.int32, L.n_tiles + 1).cpu().numpy()
+    keys = r.region(10, torch.int64, pairs).cpu().numpy().view(np.uint64)
+    tl = (keys >> np.uint64(32)).astype(np.uint32).view(np.float32)
+    rec = (keys & np.uint64(0xffffffff)).astype(np.int64)
+    c, q, rr = (torch.as_tensor(x, dtype=torch.float64) for x in (ps.center, ps.quat, ps.radii))
+    rng = np.random.default_rng(seed)
+    bad = 0
+    for s, cam in enumerate(cams):
+        job = r.jobs[s]
+        tw, th = job.tile
+        tx_n = (cam.width + tw - 1) // tw
+        ty_n = (cam.height + th - 1) // th
+        tiles = np.arange(tx_n * ty_n)
+        if n_tiles_sample is not None and n_tiles_sample < tiles.size:
+            tiles = rng.choice(tiles, n_tiles_sample, replace=False)
+        tb = int(r.slots[s].tile_begin)
+        rb = int(r.slots[s].rec_begin)
+        for t in tiles:
+            tx, ty = t % tx_n, t // tx_n
+            xs = np.arange(tx * tw, min(cam.width, (tx + 1) * tw))
+            ys = np.arange(ty * th, min(cam.height, (ty + 1) * th))
+            pix = torch.as_tensor((ys[:, None] * cam.width + xs[None, :]).ravel())
+            qq = _pairs(c, q, rr, cam, f32(lam), pix, oracle.OracleParams())
+            keep = qq["keep"].numpy()
+            t32 = qq["t"].numpy().astype(np.float32)
+            seg = slice(off[tb + t], off[tb + t + 1])
+            members = {int(k) - rb: i for i, k in enumerate(rec[seg])}
+            ks = keys[seg]
+            assert np.all(ks[1:] > ks[:-1])
+            for pi, k in zip(*np.nonzero(keep)):
+                if k not in members:
+                    bad += 1
+                    if bad < 5:
+                        print(f"missing pair: view {s} tile {t} pixel {int(pix[pi])} plane {k}", flush=True)
+                    continue
+                bound = tl[off[tb + t] + members[k]]
+                if not t32[pi, k] >= bound:
+                    bad += 1
+                    if bad < 5:
+                        print(f"bound violated: view {s} tile {t} pixel {int(pix[pi])} plane {k} "
+                              f"t {t32[pi, k]!r} bound {bound!r}", flush=True)
+    assert bad == 0, bad
+
+
+def test_binning_bounds_room_and_oblique_cameras():
+    gt, info = synth.room_planes(seed=0, target_K=2000)
+    init = synth.room_init_planes(gt, seed=1)
+    cams = synth.room_trajectory(seed=0, n_views=2, info=info)
+    from paper_2412_03451_amd.splat import Renderer
+    for lam in (oracle.lambda_at(0), 300.0):
+        r = Renderer.single_scene(cams, init.K, tile=(16, 16))
+        r.render(_dev(init.center), _dev(init.quat), _dev(init.radii), torch.tensor([lam], device="cuda"))
+        torch.cuda.synchronize()
+        _check_bounds(r, init, cams, lam, n_tiles_sample=60)

@@ -343,3 +343,25 @@ def test_behind_camera_and_near_clip():
     opaque = aux["coverage"] == 1.0
     assert int(opaque.sum()) > 100
     assert float(D[opaque].min()) > 0.01
+
+
+def test_transmittance_behind_nearly_opaque_layers():
+    """Mode B: behind two layers the transmittance is sigmoid(-z1) sigmoid(-z2)
+    with full relative precision, although 1 - w is below 1e-12."""
+    lam = 40.0
+    c = np.asarray([[0.0, 0.0, 0.2], [0.0, 0.0, 0.9]], np.float32)
+    q = np.asarray([[1, 0, 0, 0], [1, 0, 0, 0]], np.float32)
+    r = np.asarray([[0.25, 0.25, 0.25, 0.25], [0.3, 0.3, 0.3, 0.3]], np.float32)
+    cam = synth.tiny_camera()
+    D, N, aux = oracle.render(c, q, r, cam, lam, OracleParams(weight_mode="B"))
+    j, i = cam.height // 2, cam.width // 2          # pixel (64, 48): ray offset (0.005, 0.005)
+    u = (i + 0.5 - cam.cx) / cam.fx
+    v = (j + 0.5 - cam.cy) / cam.fy
+    T = 1.0
+    for k in range(2):
+        t = float(c[k, 2]) + 3.0
+        a = min(float(r[k, 0]) - abs(t * u), float(r[k, 2]) - abs(t * v))
+        z = 5 * lam * a
+        T *= 1.0 / (1.0 + math.exp(z))           # sigmoid(-z)
+    assert T < 1e-15
+    assert float(aux["T"][j, i]) == pytest.approx(T, rel=1e-12)

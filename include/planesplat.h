@@ -190,10 +190,13 @@ int adam_step_planes(float* center, float* quat, float* radii, const float* g_ce
                      const int32_t* step, float lr_center, float lr_quat, float lr_radii,
                      float beta1, float beta2, float eps, float r_min, void* stream);
 
-/* Counters of the last binning/render (synchronises the stream):
+/* Counters of the last binning and renders (synchronises the stream):
  * out[0] pairs needed, out[1] overflow flag, out[2] largest tile list,
- * out[3] pixels that took the exact fallback ordering path. */
-int ps_read_counters(const ps_layout* L, void* ws, int64_t out[4], void* stream);
+ * out[3] pixels that took the exact fallback ordering path, out[4] tiles
+ * sorted by the large-list pass, out[5] extra backward recompute passes,
+ * out[6] (pixel, candidate) pairs evaluated and out[7] hits composited by
+ * the forward walks since the last tile_bin. */
+int ps_read_counters(const ps_layout* L, void* ws, int64_t out[8], void* stream);
 
 /* Message of the last error on this thread. */
 const char* ps_last_error(void);

@@ -140,7 +140,7 @@ extern "C" int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_
   return PS_OK;
 }
 
-extern "C" int ps_read_counters(const ps_layout* L, void* ws, int64_t out[4], void* stream) {
+extern "C" int ps_read_counters(const ps_layout* L, void* ws, int64_t out[8], void* stream) {
   int rc = ps_check_ws(L, ws, "ps_read_counters");
   if (rc) return rc;
   if (!out) return ps_set_error(PS_ERR_INVALID, "ps_read_counters: null output");
@@ -149,6 +149,6 @@ extern "C" int ps_read_counters(const ps_layout* L, void* ws, int64_t out[4], vo
   PS_HIP_CHECK(hipMemcpyAsync(tmp, (char*)ws + L->region[ps::R_COUNTERS], sizeof(tmp),
                               hipMemcpyDeviceToHost, st));
   PS_HIP_CHECK(hipStreamSynchronize(st));
-  for (int i = 0; i < 4; ++i) out[i] = tmp[i];
+  for (int i = 0; i < 8; ++i) out[i] = tmp[i];
   return PS_OK;
 }

@@ -1,12 +1,12 @@
 // tile_bin: (tile, plane) pairs keyed by a per-tile depth lower bound.
 //
-//   count  (one thread per record): tiles of the record's footprint that pass
+//   count  (one wave per record): tiles of the record's footprint that pass
 //          a separating-axis test against the projected grown rectangle and
 //          have a hit in front of the camera; per-tile counts by atomics.
 //   scan   (one 1024-thread workgroup): exclusive prefix sums of the per-tile
 //          and per-record counts with wave64 shuffles plus one LDS pass per
 //          4096-element block; capacity and per-tile limits are checked here.
-//   emit   (one thread per record): key = (depth bound bits << 32 | record),
+//   emit   (one wave per record): key = (depth bound bits << 32 | record),
 //          value = emit index (record-major), scattered into tile segments.
 //   sort   (one workgroup per tile): bitonic sort of the tile's keys in LDS;
 //          keys are unique, so the order is deterministic.
@@ -55,16 +55,12 @@ __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot
   if (x0 > x1 || y0 > y1) return false;
   const double cu[4] = {x0 + 0.5, x1 + 0.5, x1 + 0.5, x0 + 0.5};
   const double cv[4] = {y0 + 0.5, y0 + 0.5, y1 + 0.5, y1 + 0.5};
-  if (br.npoly >= 3) {
-    for (int e = 0; e < br.npoly; ++e) {
-      const float2 A = br.poly[e];
-      const float2 B = br.poly[(e + 1 == br.npoly) ? 0 : e + 1];
-      const double ex = (double)B.x - A.x, ey = (double)B.y - A.y;
-      const double len = sqrt(ex * ex + ey * ey);
-      double m = -1e300;
-      for (int c = 0; c < 4; ++c) m = fmax(m, ex * (cv[c] - A.y) - ey * (cu[c] - A.x));
-      if (m < -1.0 * len) return false;  // all corners more than one pixel outside this edge
-    }
+  for (int e = 0; e < br.nedge; ++e) {
+    // largest signed distance over the pixel-center rectangle: at the corner
+    // picked by the signs of the edge normal
+    const double nx = br.edge[e][0], ny = br.edge[e][1];
+    const double m = nx * (nx > 0.0 ? cu[1] : cu[0]) + ny * (ny > 0.0 ? cv[2] : cv[0]) + br.edge[e][2];
+    if (m < -1.0) return false;  // every pixel center more than one pixel outside this edge
   }
   double tmin = 1e300;
   bool any = false;
@@ -81,24 +77,33 @@ __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot
   return true;
 }
 
+// One wave per record: the 64 lanes test the record's candidate tiles in
+// row-major order, 64 at a time (a plane near the camera can cover every
+// tile of the image, so one thread per record would serialise it).
 __global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (r >= a.R) return;
-  const BinRec br = a.brecs[r];
+  const BinRec& br = a.brecs[r];
   int cnt = 0;
-  if (br.npoly != 0) {
-    const Rec rec = a.recs[r];
-    const ps_slot sl = a.slots[br.slot];
-    for (int ty = br.ty0; ty <= br.ty1; ++ty)
-      for (int tx = br.tx0; tx <= br.tx1; ++tx) {
+  if (br.nedge != 0) {
+    const Rec& rec = a.recs[r];
+    const ps_slot& sl = a.slots[br.slot];
+    const int nx = br.tx1 - br.tx0 + 1;
+    const int n = nx * (br.ty1 - br.ty0 + 1);
+    for (int base = 0; base < n; base += 64) {
+      const int idx = base + lane;
+      bool pass = false;
+      if (idx < n) {
+        const int tx = br.tx0 + idx % nx, ty = br.ty0 + idx / nx;
         float kt;
-        if (tile_test(rec, br, sl, tx, ty, kt)) {
-          ++cnt;
-          atomicAdd(&a.tile_cnt[sl.tile_begin + ty * sl.tiles_x + tx], 1);
-        }
+        pass = tile_test(rec, br, sl, tx, ty, kt);
+        if (pass) atomicAdd(&a.tile_cnt[sl.tile_begin + ty * sl.tiles_x + tx], 1);
       }
+      cnt += __popcll(ballot(pass));
+    }
   }
-  a.rec_cnt[r] = cnt;
+  if (lane == 0) a.rec_cnt[r] = cnt;
 }
 
 // Exclusive scan of in[0, n) into out[0, n], out[n] = total, by one
@@ -186,30 +191,45 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
     a.counters[C_OVERFLOW] = (total > a.capacity || mx_t > kBigSort) ? 1 : 0;
     a.counters[C_SLOW] = 0;
     a.counters[C_BWD_PASSES] = 0;
+    a.counters[C_EVALS] = 0;
+    a.counters[C_COMMITS] = 0;
   }
 }
 
+// One wave per record, same tile order as bin_count_kernel: the j-th passing
+// tile of record r gets emit index rec_off[r] + j (ballot prefix count).
 __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (r >= a.R) return;
   if (a.counters[C_OVERFLOW]) return;
-  const BinRec br = a.brecs[r];
-  if (br.npoly == 0) return;
-  const Rec rec = a.recs[r];
-  const ps_slot sl = a.slots[br.slot];
-  int j = 0;
-  const int e0 = a.rec_off[r];
-  for (int ty = br.ty0; ty <= br.ty1; ++ty)
-    for (int tx = br.tx0; tx <= br.tx1; ++tx) {
-      float kt;
-      if (tile_test(rec, br, sl, tx, ty, kt)) {
-        const int gt = sl.tile_begin + ty * sl.tiles_x + tx;
-        const int idx = a.tile_off[gt] + atomicAdd(&a.tile_cur[gt], 1);
-        a.keys_u[idx] = ((uint64_t)__float_as_uint(kt) << 32) | (uint32_t)r;
-        a.emit_u[idx] = (uint32_t)(e0 + j);
-        ++j;
-      }
+  const BinRec& br = a.brecs[r];
+  if (br.nedge == 0) return;
+  const Rec& rec = a.recs[r];
+  const ps_slot& sl = a.slots[br.slot];
+  const int nx = br.tx1 - br.tx0 + 1;
+  const int n = nx * (br.ty1 - br.ty0 + 1);
+  int j = a.rec_off[r];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int base = 0; base < n; base += 64) {
+    const int idx = base + lane;
+    bool pass = false;
+    float kt = 0.f;
+    int tx = 0, ty = 0;
+    if (idx < n) {
+      tx = br.tx0 + idx % nx;
+      ty = br.ty0 + idx / nx;
+      pass = tile_test(rec, br, sl, tx, ty, kt);
     }
+    const uint64_t m = ballot(pass);
+    if (pass) {
+      const int gt = sl.tile_begin + ty * sl.tiles_x + tx;
+      const int slot = a.tile_off[gt] + atomicAdd(&a.tile_cur[gt], 1);
+      a.keys_u[slot] = ((uint64_t)__float_as_uint(kt) << 32) | (uint32_t)r;
+      a.emit_u[slot] = (uint32_t)(j + __popcll(m & below));
+    }
+    j += __popcll(m);
+  }
 }
 
 template <int CAP, int NT>
@@ -297,10 +317,10 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   hipLaunchKernelGGL(ps_fill_i32, dim3((a.T + 1 + 255) / 256), dim3(256), 0, st, a.tile_cnt,
                      (int64_t)a.T + 1, 0);
   if (a.R > 0)
-    hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 3) / 4), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, a);
   if (a.R > 0)
-    hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + 3) / 4), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_sort_small_kernel, dim3(a.T), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_sort_big_kernel, dim3(32), dim3(1024), 12 * kBigSort, st, a);
   PS_HIP_CHECK(hipGetLastError());

@@ -86,17 +86,25 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a) {
   }
 }
 
-__global__ __launch_bounds__(64) void loss_reduce_kernel(LossArgs a) {
+// One 256-thread workgroup per job: strided partial sums, wave sums, then the
+// four wave results added in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void loss_reduce_kernel(LossArgs a) {
+  __shared__ double lds[4][4];
   const int s = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int i0 = a.slots[s].item_begin;
   const int i1 = (s + 1 < a.S) ? a.slots[s + 1].item_begin : a.n_items;
   double acc[4] = {0, 0, 0, 0};
-  for (int i = i0 + lane; i < i1; i += 64)
-    for (int q = 0; q < 4; ++q) acc[q] += a.part[4 * (size_t)i + q];
+  for (int i = i0 + tid; i < i1; i += 256) {
+    const double4 p = *reinterpret_cast<const double4*>(a.part + 4 * (size_t)i);
+    acc[0] += p.x; acc[1] += p.y; acc[2] += p.z; acc[3] += p.w;
+  }
   for (int q = 0; q < 4; ++q) acc[q] = wave_sum_d(acc[q]);
   if (lane == 0)
-    for (int q = 0; q < 4; ++q) a.loss[4 * s + q] = (float)acc[q];
+    for (int q = 0; q < 4; ++q) lds[wid][q] = acc[q];
+  __syncthreads();
+  if (tid == 0)
+    for (int q = 0; q < 4; ++q) a.loss[4 * s + q] = (float)(((lds[0][q] + lds[1][q]) + lds[2][q]) + lds[3][q]);
 }
 
 }  // namespace
@@ -122,7 +130,7 @@ extern "C" int loss_depth_normal(const ps_layout* L, void* ws, const float* dept
   hipStream_t st = (hipStream_t)stream;
   if (a.n_items > 0)
     hipLaunchKernelGGL(loss_kernel, dim3((a.n_items + 3) / 4), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(loss_reduce_kernel, dim3(a.S), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(a.S), dim3(256), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }

@@ -36,7 +36,7 @@ __device__ inline void store_culled(Rec* recs, BinRec* brecs, int r, int slot) {
   z.px0 = 1; z.px1 = 0; z.py0 = 1; z.py1 = 0;
   recs[r] = z;
   BinRec b = {};
-  b.npoly = 0;
+  b.nedge = 0;
   b.tx0 = 1; b.tx1 = 0; b.ty0 = 1; b.ty1 = 0;
   b.slot = slot;
   brecs[r] = b;
@@ -153,16 +153,25 @@ __global__ __launch_bounds__(256) void project_kernel(ProjArgs a) {
     const int d = (c + 1 == np) ? 0 : c + 1;
     area += pu[c] * pv[d] - pu[d] * pv[c];
   }
+  for (int e = 0; e < 5; ++e) b.edge[e][0] = b.edge[e][1] = b.edge[e][2] = 0.0;
   if (np >= 3 && fabs(area) > 1e-3) {
-    b.npoly = np;
-    for (int c = 0; c < np; ++c) {
-      const int src = area > 0 ? c : np - 1 - c;
-      b.poly[c] = make_float2((float)pu[src], (float)pv[src]);
+    // signed distance to each edge, positive inside the counter-clockwise polygon
+    b.nedge = np;
+    for (int e = 0; e < np; ++e) {
+      const int ia = area > 0 ? e : np - 1 - e;
+      const int ib = area > 0 ? (e + 1 == np ? 0 : e + 1) : (e + 1 == np ? np - 1 : np - 2 - e);
+      const double ex = pu[ib] - pu[ia], ey = pv[ib] - pv[ia];
+      const double len = sqrt(ex * ex + ey * ey);
+      if (!(len > 0.0)) {  // repeated vertex: no constraint
+        b.edge[e][0] = 0.0; b.edge[e][1] = 0.0; b.edge[e][2] = 1.0;
+        continue;
+      }
+      b.edge[e][0] = -ey / len;
+      b.edge[e][1] = ex / len;
+      b.edge[e][2] = (ey * pu[ia] - ex * pv[ia]) / len;
     }
-    for (int c = np; c < 5; ++c) b.poly[c] = make_float2(0.f, 0.f);
   } else {
-    b.npoly = -1;
-    for (int c = 0; c < 5; ++c) b.poly[c] = make_float2(0.f, 0.f);
+    b.nedge = -1;
   }
   // depth lower bound over the grown, clipped rectangle, rounded down.  The
   // ray parameter of a hit equals its camera z only up to the float32

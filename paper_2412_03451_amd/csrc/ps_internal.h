@@ -36,17 +36,37 @@ struct alignas(16) Rec {
 };
 static_assert(sizeof(Rec) == 128, "Rec must stay 128 bytes");
 
-// Binning view of a record: the projected, near-clipped footprint polygon of
-// the rectangle grown by the fringe margin, and a depth lower bound.
+// The first 96 bytes of a Rec: everything the per-pixel evaluation reads.
+struct RecHead {
+  double D0, Du, Dv, X0, Xu, Xv, Y0, Yu, Yv, h;
+  float rxp, rxm, ryp, rym;
+};
+static_assert(sizeof(RecHead) == 96 && offsetof(Rec, rxp) == offsetof(RecHead, rxp), "RecHead layout");
+
+// LDS staging of one batch of 64 candidates of a tile list (one wave):
+// head[k][lane] is the k-th 16-byte chunk of the lane's candidate record (the
+// RecHead, then the rendered normal), so the lanes' stores are conflict-free
+// and the walk reads one candidate with seven wave-uniform 16-byte reads.
+struct StageLds {
+  float4 head[7][64];
+  float tlb[64];
+  int rec[64];
+};
+static_assert(offsetof(Rec, nx) == 96, "normal follows the head");
+
+// Binning view of a record: the edges of the projected, near-clipped
+// footprint polygon of the rectangle grown by the fringe margin, as signed
+// distance lines (nx u + ny v + c >= 0 inside, |(nx, ny)| = 1, pixel units),
+// and a depth lower bound.
 struct alignas(16) BinRec {
-  float2 poly[5];   // convex polygon, counter-clockwise in pixel coordinates
-  int32_t npoly;    // 0: culled; 3..5 vertices; -1: degenerate, box test only
+  double edge[5][3];
+  int32_t nedge;    // 0: culled; 3..5 edges; -1: degenerate polygon, box test only
   float tlb;        // min camera z over the clipped grown rectangle (rounded down)
   int32_t tx0, ty0, tx1, ty1;  // inclusive tile rectangle
   int32_t slot;
   int32_t pad[3];
 };
-static_assert(sizeof(BinRec) == 80, "BinRec size");
+static_assert(sizeof(BinRec) == 160, "BinRec size");
 
 // Workspace regions (byte offsets in ps_layout.region).
 enum Region {
@@ -74,7 +94,11 @@ enum Counter {
   C_MAXTILE = 2,   // largest tile list
   C_SLOW = 3,      // pixels that took the exact fallback ordering path
   C_NBIG = 4,      // number of big tiles
-  C_BWD_PASSES = 5 // extra backward recompute passes taken
+  C_BWD_PASSES = 5, // extra backward recompute passes taken
+  C_EVALS = 6,     // (pixel, candidate) pairs evaluated by the forward walk
+  C_COMMITS = 7,   // hits composited by the forward walk
+  C_ITERS = 8,     // candidate steps of the forward walk, summed over waves
+  C_MAXITER = 9    // candidate steps of the longest forward wave
 };
 
 constexpr int kMaxM = 30;
@@ -174,7 +198,8 @@ struct PairGeom {
   bool xbranch;    // a_X < a_Y: Eq. 9 takes w_X (tie -> w_Y)
 };
 
-__device__ inline PairGeom eval_pair(const Rec& r, double u, double v, double eps_den, double z_near,
+template <class R>
+__device__ inline PairGeom eval_pair(const R& r, double u, double v, double eps_den, double z_near,
                                      double delta) {
   PairGeom g;
   g.den = fma(r.Du, u, fma(r.Dv, v, r.D0));

@@ -76,6 +76,7 @@ struct ItemCtx {
   int64_t pix;       // index of the pixel in the depth array
   int64_t pix_off, HW;
   ps_camera cam;
+  StageLds* stage;   // LDS staging buffer of the wave
 };
 
 // 0: block inside the image; 1: block entirely outside (partial tile); 2: bad camera
@@ -116,13 +117,34 @@ __device__ inline int item_setup(const RenderArgs& a, int item, ItemCtx& c) {
 }
 
 // Sorted buffer of pending hits (ascending (t, record)), in registers.  Each
-// entry keeps the float32 a* of the hit; weights are formed at commit time.
-template <int P>
+// entry keeps the float32 a* of the hit (weights are formed at commit time),
+// its list position and NP payload floats that the sink needs at commit time
+// (the normal for the forward, c = gD t + gN.n for the backward), so a commit
+// never waits on memory.
+template <int P, int NP>
 struct Pending {
   float t[P];
   int r[P];
   float a[P];
   int pos[P];
+  // payload as separate 1-D arrays (NP <= 3): small arrays stay in registers
+  float p0[P], p1[P], p2[P];
+  __device__ __forceinline__ void plmove(int dst, int src) {
+    if constexpr (NP > 0) p0[dst] = p0[src];
+    if constexpr (NP > 1) p1[dst] = p1[src];
+    if constexpr (NP > 2) p2[dst] = p2[src];
+  }
+  __device__ __forceinline__ void plset(int k, const float* v) {
+    if constexpr (NP > 0) p0[k] = v[0];
+    if constexpr (NP > 1) p1[k] = v[1];
+    if constexpr (NP > 2) p2[k] = v[2];
+  }
+  __device__ __forceinline__ void plget(int k, float* v) const {
+    if constexpr (NP > 0) v[0] = p0[k];
+    if constexpr (NP > 1) v[1] = p1[k];
+    if constexpr (NP > 2) v[2] = p2[k];
+  }
+  static_assert(NP <= 3, "payload of at most 3 floats");
   int n;
   float ot; int orr;   // key of the opaque pending hit, +inf if none
   float tt; int tr;    // key of the last pending hit
@@ -133,15 +155,16 @@ struct Pending {
     tt = -INFINITY; tr = -1;
   }
 
-  // false: the buffer is full and the hit may still be among the first M
-  __device__ bool insert(float nt, int nr, float na, bool opq, int npos, int committed, int M) {
+  // Keep the `cap` nearest hits (cap = hits still allowed by M, or fewer).
+  // false: the buffer is full and the hit may still be among the nearest cap.
+  __device__ bool insert(float nt, int nr, float na, bool opq, int npos, const float* npl, int cap) {
     if (key_less(ot, orr, nt, nr)) return true;              // behind an opaque hit
-    const bool fullm = committed + n >= M;
-    if (fullm && (n == 0 || !key_less(nt, nr, tt, tr))) return true;  // beyond the first M
-    if (!fullm && n == P) return false;
-    if (fullm) {                                             // the old last entry leaves the first M
-      n -= 1;
+    if (n >= cap) {
+      if (n == 0 || !key_less(nt, nr, tt, tr)) return true;  // not among the nearest cap
+      n -= 1;                                                // the old last entry drops out
       ot = INFINITY; orr = 0x7fffffff;                       // an opaque hit is always the last entry
+    } else if (n == P) {
+      return false;
     }
     int at = 0;
 #pragma unroll
@@ -151,10 +174,14 @@ struct Pending {
     for (int k = P - 1; k >= 1; --k)
       if (k > at && k <= n) {
         t[k] = t[k - 1]; r[k] = r[k - 1]; a[k] = a[k - 1]; pos[k] = pos[k - 1];
+        plmove(k, k - 1);
       }
 #pragma unroll
     for (int k = 0; k < P; ++k)
-      if (k == at) { t[k] = nt; r[k] = nr; a[k] = na; pos[k] = npos; }
+      if (k == at) {
+        t[k] = nt; r[k] = nr; a[k] = na; pos[k] = npos;
+        plset(k, npl);
+      }
     n += 1;
     if (opq) {   // everything behind an opaque hit is hidden
       n = at + 1;
@@ -166,10 +193,14 @@ struct Pending {
     return true;
   }
 
-  __device__ void pop(float& ft, int& fr, float& fa, int& fpos) {
+  __device__ void pop(float& ft, int& fr, float& fa, int& fpos, float* fpl) {
     ft = t[0]; fr = r[0]; fa = a[0]; fpos = pos[0];
+    plget(0, fpl);
 #pragma unroll
-    for (int k = 0; k + 1 < P; ++k) { t[k] = t[k + 1]; r[k] = r[k + 1]; a[k] = a[k + 1]; pos[k] = pos[k + 1]; }
+    for (int k = 0; k + 1 < P; ++k) {
+      t[k] = t[k + 1]; r[k] = r[k + 1]; a[k] = a[k + 1]; pos[k] = pos[k + 1];
+      plmove(k, k + 1);
+    }
     n -= 1;
     if (n == 0) { tt = -INFINITY; tr = -1; ot = INFINITY; orr = 0x7fffffff; }
   }
@@ -177,92 +208,195 @@ struct Pending {
 
 // Walk the tile list of one 8x8 block and hand every committed hit, in exact
 // per-ray order, to sink.commit(t, record, a*, list position).
+// Stage the batch [base, base + 64) of the tile list: each lane fetches one
+// candidate (coalesced vector loads: one memory latency per batch) into LDS.
+// Returns the mask of candidates whose pixel box overlaps the 8x8 block.
+__device__ inline uint64_t stage_batch(const RenderArgs& a, const ItemCtx& c, int base) {
+  StageLds& S = *c.stage;
+  const int lane = threadIdx.x;
+  const int i = base + lane;
+  bool ov = false;
+  if (i < c.e) {
+    const uint64_t key = a.keys[i];
+    const int ri = (int)(uint32_t)key;
+    const Rec& rr = a.recs[ri];
+    ov = !(rr.px1 < c.bx0 || rr.px0 > c.bx1 || rr.py1 < c.by0 || rr.py0 > c.by1);
+    if (ov) {
+      const float4* src = reinterpret_cast<const float4*>(&rr);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) S.head[k][lane] = src[k];
+    }
+    S.tlb[lane] = __uint_as_float((uint32_t)(key >> 32));
+    S.rec[lane] = ri;
+  }
+  const uint64_t m = ballot(ov);
+  __syncthreads();
+  return m;
+}
+
+__device__ inline double dbl(float lo, float hi) {
+  return __hiloint2double(__float_as_int(hi), __float_as_int(lo));
+}
+
+__device__ inline void staged(const StageLds& S, int j, RecHead& rec, float n[3]) {
+  const float4 h0 = S.head[0][j], h1 = S.head[1][j], h2 = S.head[2][j], h3 = S.head[3][j];
+  const float4 h4 = S.head[4][j], h5 = S.head[5][j], h6 = S.head[6][j];
+  rec.D0 = dbl(h0.x, h0.y); rec.Du = dbl(h0.z, h0.w);
+  rec.Dv = dbl(h1.x, h1.y); rec.X0 = dbl(h1.z, h1.w);
+  rec.Xu = dbl(h2.x, h2.y); rec.Xv = dbl(h2.z, h2.w);
+  rec.Y0 = dbl(h3.x, h3.y); rec.Yu = dbl(h3.z, h3.w);
+  rec.Yv = dbl(h4.x, h4.y); rec.h = dbl(h4.z, h4.w);
+  rec.rxp = h5.x; rec.rxm = h5.y; rec.ryp = h5.z; rec.rym = h5.w;
+  n[0] = h6.x; n[1] = h6.y; n[2] = h6.z;
+}
+
+// Commit the pending hits nearer than `bound` (no later candidate can precede them).
+template <class PD, class Sink>
+__device__ __forceinline__ void drain(PD& pd, Sink& sink, int M, float bound, bool& done, float& lt, int& lr,
+                                      float* fpl) {
+  bool want = !done && pd.n > 0 && pd.t[0] < bound;
+  if (ballot(want)) {
+    while (want) {
+      float ft, fa; int fr, fp;
+      pd.pop(ft, fr, fa, fp, fpl);
+      sink.commit(ft, fa, fp, fpl);
+      lt = ft; lr = fr;
+      if (sink.finished(M)) { done = true; break; }
+      want = pd.n > 0 && pd.t[0] < bound;
+    }
+  }
+}
+
 template <int P, class Sink>
-__device__ void walk(const RenderArgs& a, const ItemCtx& c, Sink& sink, float lam5, double delta) {
-  Pending<P> pd;
+__device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink& sink, float lam5,
+                                     double delta, long long& evals) {
+  constexpr int NP = Sink::NP;
+  Pending<P, NP> pd;
   pd.reset();
   bool slow = (a.flags & 1) && c.inimg;
   bool done = !c.inimg || slow || sink.finished(a.M);
   float lt = -INFINITY;
   int lr = -1;
-  for (int i = c.b; i < c.e; ++i) {
-    if (ballot(!done) == 0) break;
-    const uint64_t key = a.keys[i];
-    const int ri = (int)(uint32_t)key;
-    const float tlb_next = (i + 1 < c.e) ? __uint_as_float((uint32_t)(a.keys[i + 1] >> 32)) : INFINITY;
-    const Rec& rec = a.recs[ri];
-    const bool overlap = !(rec.px1 < c.bx0 || rec.px0 > c.bx1 || rec.py1 < c.by0 || rec.py0 > c.by1);
-    if (overlap) {
+  StageLds& S = *c.stage;
+  float fpl[NP];
+  bool stop = ballot(!done) == 0;
+  for (int base = c.b; base < c.e && !stop; base += 64) {
+    uint64_t ovm = stage_batch(a, c, base);
+    // bound of every candidate after this batch
+    const float tlb_after = (base + 64 < c.e) ? __uint_as_float((uint32_t)(a.keys[base + 64] >> 32)) : INFINITY;
+    while (ovm) {
+      const int j = __ffsll((unsigned long long)ovm) - 1;
+      ovm &= ovm - 1;
+      // only candidates overlapping this block can hit its pixels, so the next
+      // one's bound (or the bound after the batch) limits every remaining hit
+      const float tlb_next = ovm ? S.tlb[__ffsll((unsigned long long)ovm) - 1] : tlb_after;
+      RecHead rec;
+      float nrm[3];
+      staged(S, j, rec, nrm);
+      const int ri = S.rec[j];
+      evals += __popcll(ballot(!done));
       const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
       const bool hit = g.ok && !done;
       if (ballot(hit)) {
         if (hit) {
           const float t32 = (float)g.t;
           const float a32 = (float)g.a;
-          if (!pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, i - c.b, sink.count, a.M)) {
+          float pl[NP];
+          sink.payload(t32, nrm, pl);
+          if (!pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, pl, a.M - sink.count)) {
             slow = true;
             done = true;
           }
         }
       }
-    }
-    bool want = !done && pd.n > 0 && pd.t[0] < tlb_next;
-    if (ballot(want)) {
-      while (want) {
-        float ft, fa; int fr, fp;
-        pd.pop(ft, fr, fa, fp);
-        sink.commit(a, c, ft, fr, fa, fp);
-        lt = ft; lr = fr;
-        if (sink.finished(a.M)) { done = true; break; }
-        want = pd.n > 0 && pd.t[0] < tlb_next;
+      drain(pd, sink, a.M, tlb_next, done, lt, lr, fpl);
+      if (ballot(!done) == 0) {
+        stop = true;
+        break;
       }
     }
+    // pending hits below the bound of everything after this batch
+    if (!stop) {
+      drain(pd, sink, a.M, tlb_after, done, lt, lr, fpl);
+      stop = ballot(!done) == 0;
+    }
+    __syncthreads();
   }
   const uint64_t slow_mask = ballot(slow);
   if (slow_mask && threadIdx.x == 0)
     atomicAdd((unsigned long long*)&a.counters[C_SLOW], (unsigned long long)__popcll(slow_mask));
-  if (slow) {
-    // exact fallback: repeatedly select the nearest hit after the last committed one
-    while (!sink.finished(a.M)) {
-      float bt = INFINITY, ba = 0.f;
-      int br = 0x7fffffff, bp = -1;
-      for (int j = c.b; j < c.e; ++j) {
-        const uint64_t key = a.keys[j];
-        if (__uint_as_float((uint32_t)(key >> 32)) > bt) break;
-        const int rj = (int)(uint32_t)key;
-        const Rec& rec = a.recs[rj];
-        if (c.px < rec.px0 || c.px > rec.px1 || c.py < rec.py0 || c.py > rec.py1) continue;
+  // Exact continuation for lanes whose buffer overflowed: rounds that each
+  // collect the P nearest hits after the last committed one in one scan of
+  // the list (a candidate whose bound exceeds the P-th collected depth cannot
+  // contribute, so the scan stops once every such lane is saturated), then
+  // commit them in order.  At most ceil(M / P) rounds.
+  while (ballot(slow && !sink.finished(a.M))) {
+    const bool act = slow && !sink.finished(a.M);
+    pd.reset();
+    const int cap = min(P, a.M - sink.count);
+    bool stop2 = false;
+    for (int base = c.b; base < c.e && !stop2; base += 64) {
+      uint64_t ovm = stage_batch(a, c, base);
+      while (ovm) {
+        const int j = __ffsll((unsigned long long)ovm) - 1;
+        ovm &= ovm - 1;
+        const float tj = S.tlb[j];
+        const bool sat = (pd.n >= cap || pd.ot != INFINITY) && pd.tt < tj;
+        const bool need = act && !sat;
+        if (ballot(need) == 0) {
+          stop2 = true;
+          break;
+        }
+        RecHead rec;
+        float nrm[3];
+        staged(S, j, rec, nrm);
+        const int ri = S.rec[j];
+        evals += __popcll(ballot(need));
         const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
-        if (!g.ok) continue;
-        const float t32 = (float)g.t;
-        if (key_less(lt, lr, t32, rj) && key_less(t32, rj, bt, br)) {
-          bt = t32; br = rj; bp = j - c.b;
-          ba = (float)g.a;
+        if (need && g.ok) {
+          const float t32 = (float)g.t;
+          const float a32 = (float)g.a;
+          if (key_less(lt, lr, t32, ri)) {
+            float pl[NP];
+            sink.payload(t32, nrm, pl);
+            pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, pl, cap);
+          }
         }
       }
-      if (bp < 0) break;
-      sink.commit(a, c, bt, br, ba, bp);
-      lt = bt; lr = br;
+      __syncthreads();
+    }
+    if (act) {
+      const bool exhausted = pd.n < cap && pd.ot == INFINITY;
+      while (pd.n > 0 && !sink.finished(a.M)) {
+        float ft, fa; int fr, fp;
+        pd.pop(ft, fr, fa, fp, fpl);
+        sink.commit(ft, fa, fp, fpl);
+        lt = ft; lr = fr;
+      }
+      if (exhausted) slow = false;
     }
   }
 }
 
 // ------------------------------------------------------------------ forward
 struct FwdSink {
+  static constexpr int NP = 3;   // payload: rendered normal of the hit
   float T, D, N0, N1, N2;
   int count;
   float lam5;
   int mode;
   __device__ bool finished(int M) const { return T == 0.f || count >= M; }
-  __device__ void commit(const RenderArgs& a, const ItemCtx&, float t, int r, float as, int) {
-    const Rec& rec = a.recs[r];
+  __device__ void payload(float, const float n[3], float* pl) const {
+    pl[0] = n[0]; pl[1] = n[1]; pl[2] = n[2];
+  }
+  __device__ void commit(float t, float as, int, const float* n) {
     float omw;
     const float w = splat_weight(as, lam5, mode, omw);
     const float Tw = T * w;
     D = fmaf(Tw, t, D);                 // Eq. 11
-    N0 = fmaf(Tw, rec.nx, N0);          // Eq. 12
-    N1 = fmaf(Tw, rec.ny, N1);
-    N2 = fmaf(Tw, rec.nz, N2);
+    N0 = fmaf(Tw, n[0], N0);            // Eq. 12
+    N1 = fmaf(Tw, n[1], N1);
+    N2 = fmaf(Tw, n[2], N2);
     T = T * omw;                        // Eq. 13
     ++count;
   }
@@ -270,14 +404,23 @@ struct FwdSink {
 
 template <int P>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
+  __shared__ StageLds stage;
   if (a.counters[C_OVERFLOW]) return;
   ItemCtx c;
   if (item_setup(a, blockIdx.x, c) != 0) return;
+  c.stage = &stage;
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
   const double delta = fringe_margin((double)lam, (double)a.tau, a.mode);
   FwdSink s{1.f, 0.f, 0.f, 0.f, 0.f, 0, lam5, a.mode};
-  walk<P>(a, c, s, lam5, delta);
+  long long evals = 0;
+  walk<P>(a, c, s, lam5, delta, evals);
+  int commits = s.count;
+  for (int o = 32; o >= 1; o >>= 1) commits += __shfl_xor(commits, o, 64);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)&a.counters[C_EVALS], (unsigned long long)evals);
+    atomicAdd((unsigned long long*)&a.counters[C_COMMITS], (unsigned long long)commits);
+  }
   if (c.inimg) {
     a.depth[c.pix] = s.D;
     if (a.trans) a.trans[c.pix] = s.T;
@@ -300,6 +443,7 @@ struct BwdLds {
 };
 
 struct BwdSink {
+  static constexpr int NP = 1;   // payload: c = gD t + gN . n of the hit
   float T;
   int count;
   int c0;
@@ -309,11 +453,14 @@ struct BwdSink {
   int mode;
   BwdLds* L;
   __device__ bool finished(int M) const { return T == 0.f || count >= M; }
-  __device__ void commit(const RenderArgs& a, const ItemCtx&, float t, int r, float as, int pos) {
-    const Rec& rec = a.recs[r];
+  __device__ void payload(float t, const float n[3], float* pl) const {
+    // explicit fma chain: the same bits whichever path commits the hit
+    pl[0] = fmaf(gD, t, fmaf(gN0, n[0], fmaf(gN1, n[1], gN2 * n[2])));
+  }
+  __device__ void commit(float t, float as, int pos, const float* pl) {
     float omw;
     const float w = splat_weight(as, lam5, mode, omw);
-    const float cv = gD * t + (gN0 * rec.nx + gN1 * rec.ny + gN2 * rec.nz);
+    const float cv = pl[0];
     const int j = count - c0;
     const int lane = threadIdx.x;
     if (j >= 0 && j < kChunk) {
@@ -333,10 +480,12 @@ struct BwdSink {
 template <int P>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   __shared__ BwdLds L;
+  __shared__ StageLds stage;
   if (a.counters[C_OVERFLOW]) return;
   ItemCtx c;
   const int st = item_setup(a, blockIdx.x, c);
   if (st == 2) return;
+  c.stage = &stage;
   const int lane = threadIdx.x;
   // clear this block's partial rows of the tile list (blocks outside the
   // image too: the per-record sums read every block of a tile)
@@ -361,7 +510,8 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   int passes = 1;
   for (int pass = 0; pass < passes; ++pass) {
     BwdSink s{1.f, 0, pass * kChunk, 1.f, 0.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
-    walk<P>(a, c, s, lam5, delta);
+    long long evals = 0;
+    walk<P>(a, c, s, lam5, delta, evals);
     if (pass == 0) {
       const int jmax = wave_max_int(s.count);
       passes = (jmax + kChunk - 1) / kChunk;
@@ -528,7 +678,17 @@ __global__ __launch_bounds__(64) void bwd_reduce_kernel(RenderArgs a) {
   }
 }
 
-constexpr int kPending = 6;
+// Pending-hit buffer size: ps_params.flags bits 4-5 select 6 (default), 4, 8 or 12.
+// A larger buffer sends fewer pixels to the round-based continuation at the
+// cost of registers (occupancy); the autotuner picks it with the tile shape.
+inline int pending_of(int flags) {
+  switch ((flags >> 4) & 3) {
+    case 1: return 4;
+    case 2: return 8;
+    case 3: return 12;
+    default: return 6;
+  }
+}
 
 int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, const float* lambda,
               const ps_params* prm, RenderArgs& a, const char* who) {
@@ -575,7 +735,12 @@ extern "C" int plane_render_fwd(const ps_layout* L, void* ws, const ps_camera* c
   a.trans = trans;
   a.count = count;
   if (a.n_items == 0) return PS_OK;
-  hipLaunchKernelGGL(render_fwd_kernel<kPending>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a);
+  switch (pending_of(a.flags)) {
+    case 4: hipLaunchKernelGGL(render_fwd_kernel<4>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
+    case 8: hipLaunchKernelGGL(render_fwd_kernel<8>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
+    case 12: hipLaunchKernelGGL(render_fwd_kernel<12>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
+    default: hipLaunchKernelGGL(render_fwd_kernel<6>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
+  }
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
@@ -595,8 +760,14 @@ extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* cente
   a.center = center; a.quat = quat; a.K = K;
   a.g_center = g_center; a.g_quat = g_quat; a.g_radii = g_radii;
   hipStream_t st = (hipStream_t)stream;
-  if (a.n_items > 0)
-    hipLaunchKernelGGL(render_bwd_kernel<kPending>, dim3(a.n_items), dim3(64), 0, st, a);
+  if (a.n_items > 0) {
+    switch (pending_of(a.flags)) {
+      case 4: hipLaunchKernelGGL(render_bwd_kernel<4>, dim3(a.n_items), dim3(64), 0, st, a); break;
+      case 8: hipLaunchKernelGGL(render_bwd_kernel<8>, dim3(a.n_items), dim3(64), 0, st, a); break;
+      case 12: hipLaunchKernelGGL(render_bwd_kernel<12>, dim3(a.n_items), dim3(64), 0, st, a); break;
+      default: hipLaunchKernelGGL(render_bwd_kernel<6>, dim3(a.n_items), dim3(64), 0, st, a); break;
+    }
+  }
   if (K > 0) hipLaunchKernelGGL(bwd_reduce_kernel, dim3(K), dim3(64), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;

@@ -194,9 +194,10 @@ class Renderer:
         return gc, gq, gr
 
     def counters(self):
-        out = (C.c_int64 * 4)()
+        out = (C.c_int64 * 8)()
         check(self.lib.ps_read_counters(C.byref(self.L), _ptr(self.ws), out, _stream()))
-        return dict(pairs=out[0], overflow=out[1], max_tile=out[2], slow_pixels=out[3])
+        return dict(pairs=out[0], overflow=out[1], max_tile=out[2], slow_pixels=out[3], big_tiles=out[4],
+                    bwd_extra_passes=out[5], evals=out[6], commits=out[7])
 
     # ------------------------------------------------------------------ image views
     def job_depth(self, depth, s):

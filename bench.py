@@ -6,13 +6,15 @@ split into ~2000 ground-truth rectangles; the fitted planes start from the
 ground truth with center noise 0.1 m, rotation noise 10 deg and radii scaled
 U[0.7, 1.3]; 100 views of 640 x 480 px (f = 577) on a random path; targets are
 the ground truth rendered at lambda = 300.  One step = one fitting iteration
-on `--views` views: plane_project -> tile_bin -> plane_render_fwd ->
-loss_depth_normal -> plane_render_bwd -> adam_step_planes, lambda(ite) from
-Eq. 10, every view used once per 100/views steps (shuffled cycle).
+on `--views` views: ps_fit_schedule (device-side lambda of Eq. 10, Adam step,
+view of the step from a shuffled cycle) -> plane_project -> tile_bin ->
+plane_render_fwd -> loss_depth_normal_cam -> plane_render_bwd ->
+adam_step_planes, captured once in a HIP graph and replayed.
 
 Metric: fwd+bwd Mpixel.planes/s = (pixels of the step) * K / step time / 1e6,
-with the whole step (Adam included) inside the timed region and all inputs
-resident in HBM.  Prints one JSON line.
+with the whole replayed step (Adam included) inside the timed region and all
+inputs resident in HBM.  Per-kernel durations come from the same steps run
+eagerly with events between the phases.  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -91,7 +93,7 @@ def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--views", type=int, default=1, help="views per fitting step")
     ap.add_argument("--tile", type=int, nargs=2, default=(16, 16))
@@ -100,6 +102,8 @@ def main():
                     help="pending-hit buffer size of the render kernels")
     ap.add_argument("--force-rounds", action="store_true",
                     help="send every pixel through the exact round-based ordering path")
+    ap.add_argument("--phase-steps", type=int, default=50,
+                    help="eager steps timed phase by phase (per-kernel durations)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -109,20 +113,15 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2412_03451_amd.splat import Job, Renderer, SplatParams, adam_step
-    import oracle  # noqa: F401  (only for lambda_at and the cpu baseline leg)
-    from oracle import lambda_at
+    from paper_2412_03451_amd.fit import FitConfig, SceneFit
+    from paper_2412_03451_amd.splat import Job, Renderer, SplatParams
 
     n_views = 100
     V = args.views
-    assert n_views % V == 0
     log(f"building room workload ({n_views} views)")
     gt, init, cams, info = build_workload(n_views)
     K = init.K
     W, H = cams[0].width, cams[0].height
-    rng = np.random.default_rng(0)
-    order = rng.permutation(n_views)
-    cams_sched = [cams[i] for i in order]
     dev = torch.device("cuda")
 
     def T(x):
@@ -130,106 +129,62 @@ def main():
 
     # targets: ground truth rendered at lambda = 300 by the parity-tested forward
     log("rendering targets")
-    tr = Renderer([Job(0, K, i, W, H, tuple(args.tile)) for i in range(n_views)], cams_sched,
-                  pair_capacity=1 << 22)
-    lam300 = torch.tensor([300.0], device=dev)
-    tgt_d, tgt_n = tr.render(T(gt.center), T(gt.quat), T(gt.radii), lam300)
-    tgt_d = tgt_d.view(n_views, H * W)
-    tgt_n = tgt_n.view(n_views, 3 * H * W)
+    tr = Renderer([Job(0, K, i, W, H, tuple(args.tile)) for i in range(n_views)], cams, pair_capacity=1 << 22)
+    tgt_d, tgt_n = tr.render(T(gt.center), T(gt.quat), T(gt.radii), torch.tensor([300.0], device=dev))
     del tr
 
-    # fitting state
-    c, q, r = T(init.center), T(init.quat), T(init.radii)
-    m = torch.zeros(11 * K, device=dev)
-    v = torch.zeros(11 * K, device=dev)
-    step_t = torch.zeros(1, dtype=torch.int32, device=dev)
-    lam_t = torch.zeros(1, device=dev)
-    view_t = torch.zeros(V, dtype=torch.int32, device=dev)
-    sched = torch.arange(n_views, dtype=torch.int32, device=dev)
-    rend = Renderer([Job(0, K, s, W, H, tuple(args.tile)) for s in range(V)], cams_sched,
-                    pair_capacity=1 << 20,
-                    params=SplatParams(flags=({6: 0, 4: 1, 8: 2, 12: 3}[args.pending] << 4)
-                                       | (1 if args.force_rounds else 0)))
-    lib = rend.lib
-    import ctypes as C
-    from paper_2412_03451_amd.splat import _ptr, _stream
+    params = SplatParams(flags=({6: 0, 4: 1, 8: 2, 12: 3}[args.pending] << 4) | (1 if args.force_rounds else 0))
+    cfg = FitConfig(tile=tuple(args.tile), views_per_step=V, check_every=max(1, args.warmup))
+    fit = SceneFit(init.center, init.quat, init.radii, cams, tgt_d.view(n_views, -1), tgt_n.view(n_views, -1),
+                   cfg=cfg, params=params, device=dev)
+    fit.ite.fill_(args.start_ite)
+    log(f"pair capacity {fit.rend.L.pair_capacity}")
+    start_state = fit.state()
 
-    ev = {k: [] for k in ("project", "bin", "fwd", "loss", "bwd", "adam")}
+    # warm-up (eager step, graph capture, replays; grows the lists if needed)
+    log(f"warmup {args.warmup} steps (graph capture)")
+    fit.run(max(1, args.warmup), graph=True)
+    fit.restore(start_state)
 
-    def one_step(it, timed):
-        blk = (it * V) % n_views
-        view_t.copy_(sched[blk:blk + V])
-        lam_t.fill_(lambda_at(args.start_ite + it))
-        step_t.fill_(it + 1)
-        lib.ps_set_cameras(C.byref(rend.L), _ptr(rend.ws), _ptr(view_t), _stream())
-        marks = []
-
-        def mark():
-            if timed:
-                e = torch.cuda.Event(enable_timing=True)
-                e.record()
-                marks.append(e)
-        mark()
-        rend.project(c, q, r, lam_t)
-        mark()
-        rend.bin(check_capacity=False)
-        mark()
-        D, N = rend.forward()
-        mark()
-        loss, gD, gN = rend.loss(D, N, tgt_d[blk:blk + V].reshape(-1), tgt_n[blk:blk + V].reshape(-1))
-        mark()
-        gc, gq, gr = rend.backward(c, q, r, lam_t, gD, gN)
-        mark()
-        adam_step(c, q, r, gc, gq, gr, m, v, step_t)
-        mark()
-        return marks, loss
-
-    # capacity: size the pair buffers once (the first step checks and grows)
-    view_t.copy_(sched[0:V])
-    lib.ps_set_cameras(C.byref(rend.L), _ptr(rend.ws), _ptr(view_t), _stream())
-    lam_t.fill_(lambda_at(args.start_ite))
-    rend.project(c, q, r, lam_t)
-    rend.bin(check_capacity=True, grow=2.0)
-    log(f"pairs {rend.last_pairs}, capacity {rend.L.pair_capacity}")
-
-    log(f"warmup {args.warmup} steps")
-    for it in range(args.warmup):
-        one_step(it, False)
-    torch.cuda.synchronize()
-    cnt = rend.counters()
-    if cnt["overflow"]:
-        raise RuntimeError(f"pair capacity exceeded during warmup: {cnt}")
-    # reset the fit so the timed steps start at the same state
-    c.copy_(T(init.center)); q.copy_(T(init.quat)); r.copy_(T(init.radii))
-    m.zero_(); v.zero_()
-
-    log(f"timing {args.steps} steps")
+    # timed: K replays of the captured step
+    log(f"timing {args.steps} graph-replayed steps")
+    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    all_marks = []
-    start.record()
-    for it in range(args.steps):
-        marks, loss = one_step(it, True)
-        all_marks.append(marks)
-    end.record()
+    start.record(stream)
+    for _ in range(args.steps):
+        fit.graph.replay()
+    end.record(stream)
     torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
-    ms_step = total_ms / args.steps
-    names = list(ev)
-    for marks in all_marks:
+    ms_step = start.elapsed_time(end) / args.steps
+    if fit.overflowed():
+        raise RuntimeError("pair capacity exceeded during the timed steps")
+    final_loss = fit._graph_loss.sum(0).cpu().tolist()
+
+    # per-phase durations: the same steps run eagerly with events between the
+    # phases (on the stream the kernels are launched on)
+    fit.restore(start_state)
+    names = ("project", "bin", "fwd", "loss", "bwd", "adam")
+    ev = {n: [] for n in names}
+    log(f"timing {args.phase_steps} eager steps phase by phase")
+    for _ in range(args.phase_steps):
+        marks = []
+
+        def mark():
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            marks.append(e)
+        fit._step(mark=mark)
+        torch.cuda.synchronize()
         for i, n in enumerate(names):
             ev[n].append(marks[i].elapsed_time(marks[i + 1]))
     phase_ms = {n: float(np.mean(x)) for n, x in ev.items()}
-    cnt = rend.counters()
-    if cnt["overflow"]:
-        raise RuntimeError(f"pair capacity exceeded: {cnt}")
+    eager_ms = float(np.mean([sum(ev[n][k] for n in names) for k in range(args.phase_steps)]))
 
-    # diagnostics pass (untimed): composited hits of the last step's views
-    D, N, Tr, Cn = rend.forward(diagnostics=True)
-    torch.cuda.synchronize()
-    hits = int(Cn.sum().item())
-    cnt = rend.counters()
+    # diagnostics (untimed): walk statistics of the next views
+    cnt = fit.diagnose()
+    hits = int(cnt["composited_hits"])
     evals = int(cnt["evals"])
 
     pix = V * W * H
@@ -246,9 +201,11 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved / MI355X_FP64_VECTOR_TFLOPS, 5),
         "traffic": None,
+        "launch_ms": round(phase_ms[dom], 4),
         "algorithmic_units": f"{hits} composited hits x {per_hit} flops",
         "pairs_evaluated": evals,
     }
+    n_items = max(1, int(fit.rend.L.n_items))
     out = {
         "metric": "fwd+bwd Mpixel*planes/s",
         "value": round(value, 1),
@@ -262,19 +219,31 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (f64 ray-plane geometry)",
         "data": "synthetic",
-        "config": {"workload": f"single room, K={K} planes, {V} view(s)/step of 640x480, f=577, "
-                               f"tile {args.tile[0]}x{args.tile[1]}, lambda from ite {args.start_ite}",
+        "config": {"workload": f"single room, K={K} planes, {V} view(s)/step of {W}x{H}, f=577, "
+                               f"tile {args.tile[0]}x{args.tile[1]}, lambda from ite {args.start_ite}, "
+                               f"graph-replayed fitting step",
                    "planes": K, "views_per_step": V, "width": W, "height": H,
                    "pairs_per_step": int(cnt["pairs"])},
+        "eager_ms_per_step": round(eager_ms, 4),
         "phase_ms": {k: round(x, 4) for k, x in phase_ms.items()},
+        "final_loss": [round(x, 3) for x in final_loss[:3]],
         "render_stats": {"pending": args.pending, "composited_hits": hits, "pairs_evaluated": evals,
                          "round_path_pixels": int(cnt["slow_pixels"]),
-                         "bwd_extra_passes": int(cnt["bwd_extra_passes"])},
+                         "bwd_extra_passes": int(cnt["bwd_extra_passes"]),
+                         "walk_steps": int(cnt["steps"]), "walk_steps_max_block": int(cnt["max_steps"]),
+                         "block_us_mean": round(cnt["wave_ticks"] / 100.0 / n_items, 3),
+                         "block_us_max": round(cnt["max_wave_ticks"] / 100.0, 3),
+                         "blocks": n_items,
+                         "bwd_block_us_mean": {k: round(cnt["bwd_ticks_" + k] / 100.0 / n_items, 3)
+                                               for k in ("setup", "walk", "sort", "grad")},
+                         "bwd_grad_candidates": int(cnt["bwd_grad_candidates"]),
+                         "bwd_grad_groups": int(cnt["bwd_grad_groups"])},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (float64 oracle on a pixel sample)")
-        out["cpu_baseline"] = cpu_baseline(init, cams, lambda_at(args.start_ite), args.cpu_seconds)
+        import oracle
+        out["cpu_baseline"] = cpu_baseline(init, cams, oracle.lambda_at(args.start_ite), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

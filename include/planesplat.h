@@ -74,7 +74,12 @@ typedef struct ps_params {
   float z_near;        /* near clip in metres, > 0 */
   int32_t weight_mode; /* 0: min(1, 2 sigmoid), 1: sigmoid */
   int32_t two_sided;   /* 1: normals face the camera */
-  int32_t flags;       /* bit 0: force the exact fallback ordering path (testing) */
+  int32_t flags;       /* bit 0: force the exact fallback ordering path (testing);
+                          bits 4-5: pending hits kept per lane by the render
+                          walks, 0: 6, 1: 4, 2: 8, 3: 12 (a tuning knob, the
+                          result does not depend on it);
+                          bit 6: record forward walk statistics in the
+                          counters (ps_read_counters out[6..11]) */
 } ps_params;
 
 /* One render job.  The caller fills the first block; ps_layout_init fills
@@ -94,7 +99,7 @@ typedef struct ps_slot {
 } ps_slot;
 
 /* Sizes and workspace carving of a batch of jobs (host struct). */
-#define PS_NUM_REGIONS 16
+#define PS_NUM_REGIONS 24
 typedef struct ps_layout {
   int32_t n_slots;
   int32_t n_records;   /* sum of (plane_end - plane_begin) */
@@ -124,6 +129,17 @@ int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void* ws, void* 
 /* Device-side change of the camera of every job: cam[s] = view_of_slot[s]
  * (device int array of n_slots), for captured fitting steps. */
 int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_of_slot, void* stream);
+
+/* Device-side bookkeeping of one iteration of the fitting loop (Sec. 3.3,
+ * Eq. 10), so that whole steps can be captured in a graph and replayed with
+ * no host work.  Reads the iteration counter *ite (device int32, 0-based),
+ * writes lambda[0] = min(20 exp(-(1 - 0.001 ite)), 300) (Eq. 10, device
+ * float), step[0] = ite + 1 (device int32, the 1-based Adam step) and the
+ * camera of every job, cam[s] = table[(ite mod n_rows) * n_slots + s]
+ * (device int32 [n_rows][n_slots], the view schedule), then increments *ite.
+ * Call before plane_project. */
+int ps_fit_schedule(const ps_layout* L, void* ws, int32_t* ite, const int32_t* table, int n_rows,
+                    float* lambda, int32_t* step, void* stream);
 
 /* plane_project (Sec. 3.1 Eq. 2-3, Sec. 3.2 Eq. 4 and 6): per (plane, job)
  * record in the job's camera frame: normalised rotation, plane offset, the
@@ -169,6 +185,18 @@ int loss_depth_normal(const ps_layout* L, void* ws, const float* depth, const fl
                       float a_cos, float a_nl1, float a_d, float* loss, float* g_depth,
                       float* g_normal, void* stream);
 
+/* loss_depth_normal_cam: as loss_depth_normal, with the targets of every
+ * camera in one array, for fitting loops whose view schedule lives on the
+ * device (ps_fit_schedule): job s with camera c reads tgt_depth[tgt_off[c] +
+ * p] and tgt_normal[3 tgt_off[c] + k H W + p] (p = y W + x, channel k) and
+ * mask[tgt_off[c] + p]; the target of camera c has the size of the jobs that
+ * use it.  tgt_off: device int64 [n_cams].  A job whose camera index is out
+ * of range gets zero loss and gradient. */
+int loss_depth_normal_cam(const ps_layout* L, void* ws, const float* depth, const float* normal,
+                          const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
+                          const int64_t* tgt_off, int n_cams, float a_cos, float a_nl1, float a_d,
+                          float* loss, float* g_depth, float* g_normal, void* stream);
+
 /* plane_render_bwd: gradient of sum_px g_depth*D + g_normal.N with respect to
  * center, quat, radii (device [K][3], [K][4], [K][4], overwritten; summed
  * over the jobs that use a plane).  Recomputes each pixel's ordered hit list
@@ -193,10 +221,20 @@ int adam_step_planes(float* center, float* quat, float* radii, const float* g_ce
 /* Counters of the last binning and renders (synchronises the stream):
  * out[0] pairs needed, out[1] overflow flag, out[2] largest tile list,
  * out[3] pixels that took the exact fallback ordering path, out[4] tiles
- * sorted by the large-list pass, out[5] extra backward recompute passes,
- * out[6] (pixel, candidate) pairs evaluated and out[7] hits composited by
- * the forward walks since the last tile_bin. */
-int ps_read_counters(const ps_layout* L, void* ws, int64_t out[8], void* stream);
+ * sorted by the large-list pass, out[5] extra backward recompute passes.
+ * Forward walks run with flags bit 6 add, since the last tile_bin:
+ * out[6] (pixel, candidate) pairs evaluated, out[7] hits composited,
+ * out[8] candidate steps summed over 8x8 blocks, out[9] the most steps of one
+ * block, out[10] block run time summed and out[11] its maximum, in ticks of
+ * the 100 MHz device wall clock.  Backward walks run with flags bit 6 add
+ * out[12..15] the blocks' time spent in set-up, recompute walks, the
+ * back-to-front pass with its sort and the gradient pass (ticks, summed),
+ * out[16] the candidates visited and out[17] the candidate groups fetched by
+ * the gradient pass.  out[18] is nonzero once any tile_bin since
+ * ps_workspace_init overflowed (steps replayed from a graph check it after a
+ * run of steps).  PS_N_COUNTERS values are written. */
+#define PS_N_COUNTERS 19
+int ps_read_counters(const ps_layout* L, void* ws, int64_t out[PS_N_COUNTERS], void* stream);
 
 /* Message of the last error on this thread. */
 const char* ps_last_error(void);

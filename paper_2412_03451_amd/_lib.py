@@ -37,7 +37,7 @@ class PsSlot(C.Structure):
                 ("pad", C.c_int32), ("pix_off", C.c_int64)]
 
 
-PS_NUM_REGIONS = 16
+PS_NUM_REGIONS = 24
 
 
 class PsLayout(C.Structure):
@@ -62,10 +62,13 @@ _EXPORTS = {
                                    _P]),
     "loss_depth_normal": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, _P, _P, C.c_float, C.c_float,
                                     C.c_float, _P, _P, _P, _P]),
+    "loss_depth_normal_cam": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, _P, _P, _P, C.c_int, C.c_float,
+                                        C.c_float, C.c_float, _P, _P, _P, _P]),
     "plane_render_bwd": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,
                                    C.POINTER(PsParams), _P, _P, _P, _P, _P, _P]),
     "adam_step_planes": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, C.c_int, _P, C.c_float, C.c_float,
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
+    "ps_fit_schedule": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, C.c_int, _P, _P, _P]),
     "ps_read_counters": (C.c_int, [C.POINTER(PsLayout), _P, C.POINTER(C.c_int64), _P]),
     "ps_last_error": (C.c_char_p, []),
 }

@@ -84,6 +84,8 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
       64 * C * (size_t)max_sub,        // R_PARTIAL
       32 * ((size_t)items + 1),        // R_LOSS
       4 * (T + 1),                     // R_BIGTILES
+      sizeof(ps::ItemDesc) * ((size_t)items + 1),  // R_ITEMS
+      sizeof(ps::Rec) * C,             // R_RECS_S
   };
   size_t off = 0;
   for (int i = 0; i < PS_NUM_REGIONS; ++i) {
@@ -140,15 +142,43 @@ extern "C" int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_
   return PS_OK;
 }
 
-extern "C" int ps_read_counters(const ps_layout* L, void* ws, int64_t out[8], void* stream) {
+// One fitting iteration's device-side bookkeeping (captured with the step).
+__global__ void ps_sched_kernel(ps_slot* slots, int S, int32_t* ite, const int32_t* table, int n_rows,
+                                float* lambda, int32_t* step) {
+  const int it = *ite;
+  const int row = it % n_rows;
+  for (int s = threadIdx.x; s < S; s += blockDim.x) slots[s].cam = table[(size_t)row * S + s];
+  if (threadIdx.x == 0) {
+    // Eq. 10, iteration counted from 0
+    lambda[0] = (float)fmin(20.0 * exp(-(1.0 - 0.001 * it)), 300.0);
+    step[0] = it + 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *ite = it + 1;
+}
+
+extern "C" int ps_fit_schedule(const ps_layout* L, void* ws, int32_t* ite, const int32_t* table, int n_rows,
+                               float* lambda, int32_t* step, void* stream) {
+  int rc = ps_check_ws(L, ws, "ps_fit_schedule");
+  if (rc) return rc;
+  if (!ite || !table || !lambda || !step) return ps_set_error(PS_ERR_INVALID, "ps_fit_schedule: null pointer");
+  if (n_rows <= 0) return ps_set_error(PS_ERR_INVALID, "ps_fit_schedule: n_rows <= 0");
+  char* base = (char*)ws;
+  hipLaunchKernelGGL(ps_sched_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream,
+                     (ps_slot*)(base + L->region[ps::R_SLOTS]), L->n_slots, ite, table, n_rows, lambda, step);
+  PS_HIP_CHECK(hipGetLastError());
+  return PS_OK;
+}
+
+extern "C" int ps_read_counters(const ps_layout* L, void* ws, int64_t out[PS_N_COUNTERS], void* stream) {
   int rc = ps_check_ws(L, ws, "ps_read_counters");
   if (rc) return rc;
   if (!out) return ps_set_error(PS_ERR_INVALID, "ps_read_counters: null output");
   hipStream_t st = (hipStream_t)stream;
-  int64_t tmp[8];
+  int64_t tmp[PS_N_COUNTERS];
   PS_HIP_CHECK(hipMemcpyAsync(tmp, (char*)ws + L->region[ps::R_COUNTERS], sizeof(tmp),
                               hipMemcpyDeviceToHost, st));
   PS_HIP_CHECK(hipStreamSynchronize(st));
-  for (int i = 0; i < 8; ++i) out[i] = tmp[i];
+  for (int i = 0; i < PS_N_COUNTERS; ++i) out[i] = tmp[i];
   return PS_OK;
 }

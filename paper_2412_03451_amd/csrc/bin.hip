@@ -9,7 +9,10 @@
 //   emit   (one wave per record): key = (depth bound bits << 32 | record),
 //          value = emit index (record-major), scattered into tile segments.
 //   sort   (one workgroup per tile): bitonic sort of the tile's keys in LDS;
-//          keys are unique, so the order is deterministic.
+//          keys are unique, so the order is deterministic.  The sort also
+//          writes the records in list order (one contiguous, coalesced run
+//          per tile for the render loops) and the descriptors of the tile's
+//          8x8 render items.
 //
 // The depth bound of a record over a tile is the larger of (a) the minimum
 // camera z of its grown, near-clipped rectangle and (b) the minimum over the
@@ -44,6 +47,8 @@ struct BinArgs {
   long long* counters;
   int* bigtiles;
   long long capacity;
+  Rec* recs_s;        // record copies in sorted order
+  ItemDesc* items;
 };
 
 __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot& sl, int tx, int ty,
@@ -189,10 +194,10 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
     a.counters[C_MAXTILE] = mx_t;
     a.counters[C_NBIG] = nbig;
     a.counters[C_OVERFLOW] = (total > a.capacity || mx_t > kBigSort) ? 1 : 0;
+    if (a.counters[C_OVERFLOW]) a.counters[C_STICKY] = 1;
     a.counters[C_SLOW] = 0;
     a.counters[C_BWD_PASSES] = 0;
-    a.counters[C_EVALS] = 0;
-    a.counters[C_COMMITS] = 0;
+    for (int k = C_EVALS; k < C_STICKY; ++k) a.counters[k] = 0;
   }
 }
 
@@ -235,7 +240,8 @@ __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
 template <int CAP, int NT>
 __device__ void lds_bitonic(uint64_t* k, uint32_t* v, int n, const uint64_t* __restrict__ kin,
                             const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-                            uint32_t* __restrict__ vout) {
+                            uint32_t* __restrict__ vout, const Rec* __restrict__ recs,
+                            Rec* __restrict__ rout) {
   int n2 = 1;
   while (n2 < n) n2 <<= 1;
   for (int i = threadIdx.x; i < n2; i += NT) {
@@ -262,17 +268,47 @@ __device__ void lds_bitonic(uint64_t* k, uint32_t* v, int n, const uint64_t* __r
     kout[i] = k[i];
     vout[i] = v[i];
   }
+  // record copies in list order, eight lanes per 128-byte record
+  for (int i = threadIdx.x; i < 8 * n; i += NT) {
+    const int e = i >> 3, q = i & 7;
+    const int ri = (int)(uint32_t)k[e];
+    reinterpret_cast<float4*>(&rout[e])[q] = reinterpret_cast<const float4*>(&recs[ri])[q];
+  }
 }
 
 __global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
   __shared__ uint64_t k[kSmallSort];
   __shared__ uint32_t v[kSmallSort];
-  if (a.counters[C_OVERFLOW]) return;
   const int t = blockIdx.x;
   const int n = a.tile_cnt[t];
-  if (n == 0 || n > kSmallSort) return;
   const int off = a.tile_off[t];
-  lds_bitonic<kSmallSort, 256>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off);
+  // render items (8x8 blocks) of this tile
+  if (threadIdx.x < 16) {
+    const int s = find_slot_by_tile(a.slots, a.S, t);
+    const ps_slot& sl = a.slots[s];
+    const int sub_w = sl.tile_w >> 3;
+    const int sub_per = sub_w * (sl.tile_h >> 3);
+    const int sub = threadIdx.x;
+    if (sub < sub_per) {
+      const int lt = t - sl.tile_begin;
+      ItemDesc d;
+      d.b = off;
+      d.e = off + n;
+      d.ox = (int16_t)((lt % sl.tiles_x) * sl.tile_w + (sub % sub_w) * 8);
+      d.oy = (int16_t)((lt / sl.tiles_x) * sl.tile_h + (sub / sub_w) * 8);
+      d.width = (int16_t)sl.width;
+      d.height = (int16_t)sl.height;
+      d.cam = sl.cam;
+      d.sub = (int16_t)sub;
+      d.pad = 0;
+      d.pix_off = sl.pix_off;
+      a.items[sl.item_begin + lt * sub_per + sub] = d;
+    }
+  }
+  if (a.counters[C_OVERFLOW]) return;
+  if (n == 0 || n > kSmallSort) return;
+  lds_bitonic<kSmallSort, 256>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off,
+                               a.recs, a.recs_s + off);
 }
 
 __global__ __launch_bounds__(1024) void bin_sort_big_kernel(BinArgs a) {
@@ -285,7 +321,8 @@ __global__ __launch_bounds__(1024) void bin_sort_big_kernel(BinArgs a) {
     const int t = a.bigtiles[b];
     const int n = a.tile_cnt[t];
     const int off = a.tile_off[t];
-    lds_bitonic<kBigSort, 1024>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off);
+    lds_bitonic<kBigSort, 1024>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off,
+                                a.recs, a.recs_s + off);
     __syncthreads();
   }
 }
@@ -314,6 +351,8 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   a.counters = (long long*)(base + L->region[R_COUNTERS]);
   a.bigtiles = (int*)(base + L->region[R_BIGTILES]);
   a.capacity = L->pair_capacity;
+  a.recs_s = (Rec*)(base + L->region[R_RECS_S]);
+  a.items = (ItemDesc*)(base + L->region[R_ITEMS]);
   hipLaunchKernelGGL(ps_fill_i32, dim3((a.T + 1 + 255) / 256), dim3(256), 0, st, a.tile_cnt,
                      (int64_t)a.T + 1, 0);
   if (a.R > 0)

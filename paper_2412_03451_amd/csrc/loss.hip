@@ -23,6 +23,8 @@ struct LossArgs {
   const float* Dt;
   const float* Nt;
   const uint8_t* mask;
+  const int64_t* tgt_off;   // null: targets laid out like the jobs; else per-camera pixel offsets
+  int n_cams;
   float a_cos, a_nl1, a_d;
   float* gD;
   float* gN;
@@ -50,16 +52,22 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a) {
   const int px = (tile % sl.tiles_x) * sl.tile_w + (sub % sub_w) * 8 + (lane & 7);
   const int py = (tile / sl.tiles_x) * sl.tile_h + (sub / sub_w) * 8 + (lane >> 3);
   double l0 = 0, l1 = 0, l2 = 0, l3 = 0;
-  if (px < sl.width && py < sl.height) {
+  // targets of a camera: its own image at tgt_off[cam] (a camera whose
+  // index is out of range contributes nothing)
+  const bool valid = !a.tgt_off || (sl.cam >= 0 && sl.cam < a.n_cams);
+  if (px < sl.width && py < sl.height && valid) {
     const int64_t HW = (int64_t)sl.width * sl.height;
-    const int64_t p = sl.pix_off + (int64_t)py * sl.width + px;
-    const int64_t nb = 3 * sl.pix_off + (p - sl.pix_off);
-    const float m = a.mask ? (a.mask[p] ? 1.f : 0.f) : 1.f;
-    const float D = a.D[p], Dt = a.Dt[p];
+    const int64_t local = (int64_t)py * sl.width + px;
+    const int64_t p = sl.pix_off + local;
+    const int64_t nb = 3 * sl.pix_off + local;
+    const int64_t tp = a.tgt_off ? a.tgt_off[sl.cam] + local : p;
+    const int64_t tnb = a.tgt_off ? 3 * a.tgt_off[sl.cam] + local : nb;
+    const float m = a.mask ? (a.mask[tp] ? 1.f : 0.f) : 1.f;
+    const float D = a.D[p], Dt = a.Dt[tp];
     float N[3], Nt[3];
     for (int c = 0; c < 3; ++c) {
       N[c] = a.N[nb + c * HW];
-      Nt[c] = a.Nt[nb + c * HW];
+      Nt[c] = a.Nt[tnb + c * HW];
     }
     const double dot = (double)N[0] * Nt[0] + (double)N[1] * Nt[1] + (double)N[2] * Nt[2];
     const double e1 = 1.0 - dot;
@@ -78,6 +86,12 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a) {
       l3 = fabs((double)D - (double)Dt);
       l2 = a.a_d * l3;
     }
+  } else if (px < sl.width && py < sl.height) {
+    const int64_t HW = (int64_t)sl.width * sl.height;
+    const int64_t p = sl.pix_off + (int64_t)py * sl.width + px;
+    const int64_t nb = 3 * sl.pix_off + (p - sl.pix_off);
+    a.gD[p] = 0.f;
+    for (int c = 0; c < 3; ++c) a.gN[nb + c * HW] = 0.f;
   }
   l0 = wave_sum_d(l0); l1 = wave_sum_d(l1); l2 = wave_sum_d(l2); l3 = wave_sum_d(l3);
   if (lane == 0) {
@@ -109,20 +123,21 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(LossArgs a) {
 
 }  // namespace
 
-extern "C" int loss_depth_normal(const ps_layout* L, void* ws, const float* depth, const float* normal,
-                                 const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
-                                 float a_cos, float a_nl1, float a_d, float* loss, float* g_depth,
-                                 float* g_normal, void* stream) {
-  int rc = ps_check_ws(L, ws, "loss_depth_normal");
+static int loss_launch(const ps_layout* L, void* ws, const float* depth, const float* normal,
+                       const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
+                       const int64_t* tgt_off, int n_cams, float a_cos, float a_nl1,
+                       float a_d, float* loss, float* g_depth, float* g_normal, void* stream, const char* who) {
+  int rc = ps_check_ws(L, ws, who);
   if (rc) return rc;
   if (!depth || !normal || !tgt_depth || !tgt_normal || !loss || !g_depth || !g_normal)
-    return ps_set_error(PS_ERR_INVALID, "loss_depth_normal: null pointer");
+    return ps_set_error(PS_ERR_INVALID, "%s: null pointer", who);
   char* base = (char*)ws;
   LossArgs a;
   a.slots = (const ps_slot*)(base + L->region[R_SLOTS]);
   a.S = L->n_slots;
   a.n_items = L->n_items;
   a.D = depth; a.N = normal; a.Dt = tgt_depth; a.Nt = tgt_normal; a.mask = mask;
+  a.tgt_off = tgt_off; a.n_cams = n_cams;
   a.a_cos = a_cos; a.a_nl1 = a_nl1; a.a_d = a_d;
   a.gD = g_depth; a.gN = g_normal;
   a.part = (double*)(base + L->region[R_LOSS]);
@@ -133,4 +148,22 @@ extern "C" int loss_depth_normal(const ps_layout* L, void* ws, const float* dept
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(a.S), dim3(256), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
+}
+
+extern "C" int loss_depth_normal(const ps_layout* L, void* ws, const float* depth, const float* normal,
+                                 const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
+                                 float a_cos, float a_nl1, float a_d, float* loss, float* g_depth,
+                                 float* g_normal, void* stream) {
+  return loss_launch(L, ws, depth, normal, tgt_depth, tgt_normal, mask, nullptr, 0, a_cos, a_nl1, a_d,
+                     loss, g_depth, g_normal, stream, "loss_depth_normal");
+}
+
+extern "C" int loss_depth_normal_cam(const ps_layout* L, void* ws, const float* depth, const float* normal,
+                                     const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
+                                     const int64_t* tgt_off, int n_cams, float a_cos, float a_nl1, float a_d,
+                                     float* loss, float* g_depth, float* g_normal, void* stream) {
+  if (!tgt_off || n_cams <= 0)
+    return ps_set_error(PS_ERR_INVALID, "loss_depth_normal_cam: null tgt_off or n_cams <= 0");
+  return loss_launch(L, ws, depth, normal, tgt_depth, tgt_normal, mask, tgt_off, n_cams, a_cos, a_nl1,
+                     a_d, loss, g_depth, g_normal, stream, "loss_depth_normal_cam");
 }

@@ -51,6 +51,8 @@ struct StageLds {
   float4 head[7][64];
   float tlb[64];
   int rec[64];
+  float2 pv[64];     // (p - o) . vx, (p - o) . vy (backward only)
+  uint32_t em[64];   // emit index of the (record, tile) pair (backward only)
 };
 static_assert(offsetof(Rec, nx) == 96, "normal follows the head");
 
@@ -86,7 +88,24 @@ enum Region {
   R_PARTIAL,     // float[C][max_sub][16]  backward partials per (pair, 8x8 block)
   R_LOSS,        // double[n_items][4]     loss partials per 8x8 block
   R_BIGTILES,    // int[T]       tiles whose list exceeds the small sort
+  R_ITEMS,       // ItemDesc[n_items]  per 8x8 block: list range, pixel origin, camera
+  R_RECS_S,      // Rec[C]       record copies in tile-list order
+  R_NUM_USED     // further regions are reserved (size 0)
 };
+static_assert(R_NUM_USED <= PS_NUM_REGIONS, "region table");
+
+// Render item (one 8x8 pixel block), written by the binning sort so that a
+// render block reaches its list with one load.
+struct alignas(16) ItemDesc {
+  int32_t b, e;              // range of the tile list in keys / record copies
+  int16_t ox, oy;            // pixel origin of the block
+  int16_t width, height;     // image size of the job
+  int32_t cam;               // camera index of the job
+  int16_t sub;               // 8x8 block index inside the tile
+  int16_t pad;
+  int64_t pix_off;           // first pixel of the job
+};
+static_assert(sizeof(ItemDesc) == 32, "ItemDesc size");
 
 enum Counter {
   C_PAIRS = 0,     // pairs needed
@@ -98,8 +117,19 @@ enum Counter {
   C_EVALS = 6,     // (pixel, candidate) pairs evaluated by the forward walk
   C_COMMITS = 7,   // hits composited by the forward walk
   C_ITERS = 8,     // candidate steps of the forward walk, summed over waves
-  C_MAXITER = 9    // candidate steps of the longest forward wave
+  C_MAXITER = 9,   // candidate steps of the longest forward wave
+  C_WTIME = 10,    // forward wave run time (100 MHz ticks), summed
+  C_WTMAX = 11,    // longest forward wave run time
+  C_BT_SETUP = 12, // backward phase times (ticks, summed over blocks)
+  C_BT_WALK = 13,
+  C_BT_SORT = 14,
+  C_BT_GRAD = 15,
+  C_BG_CAND = 16,  // candidates visited by the gradient pass
+  C_BG_GROUPS = 17, // candidate groups fetched by the gradient pass
+  C_STICKY = 18    // nonzero once any tile_bin since ps_workspace_init overflowed
 };
+static_assert(C_STICKY + 1 == PS_N_COUNTERS, "counter count");
+constexpr int kFlagDiag = 64;   // params.flags bit 6: forward walk statistics
 
 constexpr int kMaxM = 30;
 constexpr int kSmallSort = 1024;  // tile lists up to this size sort in one small-LDS pass
@@ -135,6 +165,14 @@ __device__ inline int find_slot_by_item(const ps_slot* __restrict__ sl, int S, i
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (sl[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int find_slot_by_tile(const ps_slot* __restrict__ sl, int S, int tile) {
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sl[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
   }
   return lo;
 }

@@ -36,7 +36,8 @@ struct RenderArgs {
   const ps_slot* slots;
   int S, n_items;
   const Rec* recs;
-  const int* tile_off;
+  const ItemDesc* items;
+  const Rec* recs_s;        // record copies in list order
   const uint64_t* keys;
   const uint32_t* emit;
   const int* rec_cnt;
@@ -65,7 +66,6 @@ struct RenderArgs {
 };
 
 struct ItemCtx {
-  int slot;
   int b, e;          // list range in keys[]
   int sub;           // 8x8 block index inside the tile
   int px, py;        // this lane's pixel
@@ -75,45 +75,35 @@ struct ItemCtx {
   float du, dv;      // camera-frame ray (du, dv, 1)
   int64_t pix;       // index of the pixel in the depth array
   int64_t pix_off, HW;
-  ps_camera cam;
   StageLds* stage;   // LDS staging buffer of the wave
 };
 
 // 0: block inside the image; 1: block entirely outside (partial tile); 2: bad camera
 __device__ inline int item_setup(const RenderArgs& a, int item, ItemCtx& c) {
-  const int s = find_slot_by_item(a.slots, a.S, item);
-  const ps_slot sl = a.slots[s];
-  if (sl.cam < 0 || sl.cam >= a.n_cams) return 2;
-  c.slot = s;
-  const int local = item - sl.item_begin;
-  const int sub_w = sl.tile_w >> 3;
-  const int sub_per = sub_w * (sl.tile_h >> 3);
-  const int tile = local / sub_per;
-  c.sub = local - tile * sub_per;
-  const int tx = tile % sl.tiles_x, ty = tile / sl.tiles_x;
-  const int ox = tx * sl.tile_w + (c.sub % sub_w) * 8;
-  const int oy = ty * sl.tile_h + (c.sub / sub_w) * 8;
-  const int gt = sl.tile_begin + tile;
-  c.b = a.tile_off[gt];
-  c.e = a.tile_off[gt + 1];
+  const ItemDesc d = a.items[item];
+  c.b = d.b;
+  c.e = d.e;
+  c.sub = d.sub;
+  const int ox = d.ox, oy = d.oy, W = d.width, H = d.height;
   const int lane = threadIdx.x;
   c.px = ox + (lane & 7);
   c.py = oy + (lane >> 3);
-  c.inimg = c.px < sl.width && c.py < sl.height;
-  c.bx0 = ox; c.bx1 = min(ox + 7, sl.width - 1);
-  c.by0 = oy; c.by1 = min(oy + 7, sl.height - 1);
-  c.cam = a.cams[sl.cam];
+  c.inimg = c.px < W && c.py < H;
+  c.bx0 = ox; c.bx1 = min(ox + 7, W - 1);
+  c.by0 = oy; c.by1 = min(oy + 7, H - 1);
+  c.pix_off = d.pix_off;
+  c.HW = (int64_t)W * H;
+  c.pix = d.pix_off + (int64_t)c.py * W + c.px;
+  if (d.cam < 0 || d.cam >= a.n_cams) return 2;
+  const ps_camera& cam = a.cams[d.cam];
   c.u = c.px + 0.5;
   c.v = c.py + 0.5;
-  const double du = (c.u - (double)c.cam.cx) / (double)c.cam.fx;
-  const double dv = (c.v - (double)c.cam.cy) / (double)c.cam.fy;
+  const double du = (c.u - (double)cam.cx) / (double)cam.fx;
+  const double dv = (c.v - (double)cam.cy) / (double)cam.fy;
   c.du = (float)du;
   c.dv = (float)dv;
   c.eps = 1e-12 * sqrt(du * du + dv * dv + 1.0);
-  c.pix_off = sl.pix_off;
-  c.HW = (int64_t)sl.width * sl.height;
-  c.pix = sl.pix_off + (int64_t)c.py * sl.width + c.px;
-  return (ox < sl.width && oy < sl.height) ? 0 : 1;
+  return (ox < W && oy < H) ? 0 : 1;
 }
 
 // Sorted buffer of pending hits (ascending (t, record)), in registers.  Each
@@ -206,11 +196,12 @@ struct Pending {
   }
 };
 
-// Walk the tile list of one 8x8 block and hand every committed hit, in exact
-// per-ray order, to sink.commit(t, record, a*, list position).
 // Stage the batch [base, base + 64) of the tile list: each lane fetches one
-// candidate (coalesced vector loads: one memory latency per batch) into LDS.
-// Returns the mask of candidates whose pixel box overlaps the 8x8 block.
+// list entry (its key and the 128-byte record copy: coalesced, one memory
+// latency per batch) and stores the record head in LDS if the record's pixel
+// box overlaps the 8x8 block; the backward also keeps the in-plane offsets and
+// the emit index.  Returns the mask of overlapping candidates.
+template <bool BWD>
 __device__ inline uint64_t stage_batch(const RenderArgs& a, const ItemCtx& c, int base) {
   StageLds& S = *c.stage;
   const int lane = threadIdx.x;
@@ -218,16 +209,22 @@ __device__ inline uint64_t stage_batch(const RenderArgs& a, const ItemCtx& c, in
   bool ov = false;
   if (i < c.e) {
     const uint64_t key = a.keys[i];
-    const int ri = (int)(uint32_t)key;
-    const Rec& rr = a.recs[ri];
-    ov = !(rr.px1 < c.bx0 || rr.px0 > c.bx1 || rr.py1 < c.by0 || rr.py0 > c.by1);
+    const float4* src = reinterpret_cast<const float4*>(&a.recs_s[i]);
+    const float4 h0 = src[0], h1 = src[1], h2 = src[2], h3 = src[3];
+    const float4 h4 = src[4], h5 = src[5], h6 = src[6], h7 = src[7];
+    const uint32_t em = BWD ? a.emit[i] : 0u;
+    const uint32_t b0 = __float_as_uint(h7.x), b1 = __float_as_uint(h7.y);
+    const int px0 = (int16_t)(b0 & 0xffffu), py0 = (int16_t)(b0 >> 16);
+    const int px1 = (int16_t)(b1 & 0xffffu), py1 = (int16_t)(b1 >> 16);
+    ov = !(px1 < c.bx0 || px0 > c.bx1 || py1 < c.by0 || py0 > c.by1);
     if (ov) {
-      const float4* src = reinterpret_cast<const float4*>(&rr);
-#pragma unroll
-      for (int k = 0; k < 7; ++k) S.head[k][lane] = src[k];
+      S.head[0][lane] = h0; S.head[1][lane] = h1; S.head[2][lane] = h2; S.head[3][lane] = h3;
+      S.head[4][lane] = h4; S.head[5][lane] = h5; S.head[6][lane] = h6;
+      if (BWD) S.pv[lane] = make_float2(h7.z, h7.w);
     }
+    if (BWD) S.em[lane] = em;
     S.tlb[lane] = __uint_as_float((uint32_t)(key >> 32));
-    S.rec[lane] = ri;
+    S.rec[lane] = (int)(uint32_t)key;
   }
   const uint64_t m = ballot(ov);
   __syncthreads();
@@ -267,9 +264,11 @@ __device__ __forceinline__ void drain(PD& pd, Sink& sink, int M, float bound, bo
   }
 }
 
+// Walk the tile list of one 8x8 block and hand every committed hit, in exact
+// per-ray order, to sink.commit(t, a*, list position, payload).
 template <int P, class Sink>
 __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink& sink, float lam5,
-                                     double delta, long long& evals) {
+                                     double delta, long long& evals, long long& steps) {
   constexpr int NP = Sink::NP;
   Pending<P, NP> pd;
   pd.reset();
@@ -281,12 +280,13 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
   float fpl[NP];
   bool stop = ballot(!done) == 0;
   for (int base = c.b; base < c.e && !stop; base += 64) {
-    uint64_t ovm = stage_batch(a, c, base);
+    uint64_t ovm = stage_batch<Sink::BWD>(a, c, base);
     // bound of every candidate after this batch
     const float tlb_after = (base + 64 < c.e) ? __uint_as_float((uint32_t)(a.keys[base + 64] >> 32)) : INFINITY;
     while (ovm) {
       const int j = __ffsll((unsigned long long)ovm) - 1;
       ovm &= ovm - 1;
+      ++steps;
       // only candidates overlapping this block can hit its pixels, so the next
       // one's bound (or the bound after the batch) limits every remaining hit
       const float tlb_next = ovm ? S.tlb[__ffsll((unsigned long long)ovm) - 1] : tlb_after;
@@ -336,7 +336,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
     const int cap = min(P, a.M - sink.count);
     bool stop2 = false;
     for (int base = c.b; base < c.e && !stop2; base += 64) {
-      uint64_t ovm = stage_batch(a, c, base);
+      uint64_t ovm = stage_batch<Sink::BWD>(a, c, base);
       while (ovm) {
         const int j = __ffsll((unsigned long long)ovm) - 1;
         ovm &= ovm - 1;
@@ -347,6 +347,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
           stop2 = true;
           break;
         }
+        ++steps;
         RecHead rec;
         float nrm[3];
         staged(S, j, rec, nrm);
@@ -381,6 +382,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
 // ------------------------------------------------------------------ forward
 struct FwdSink {
   static constexpr int NP = 3;   // payload: rendered normal of the hit
+  static constexpr bool BWD = false;
   float T, D, N0, N1, N2;
   int count;
   float lam5;
@@ -406,6 +408,8 @@ template <int P>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   __shared__ StageLds stage;
   if (a.counters[C_OVERFLOW]) return;
+  const bool diag = a.flags & kFlagDiag;
+  const uint64_t t_start = diag ? wall_clock64() : 0;
   ItemCtx c;
   if (item_setup(a, blockIdx.x, c) != 0) return;
   c.stage = &stage;
@@ -413,13 +417,20 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   const float lam5 = 5.f * lam;
   const double delta = fringe_margin((double)lam, (double)a.tau, a.mode);
   FwdSink s{1.f, 0.f, 0.f, 0.f, 0.f, 0, lam5, a.mode};
-  long long evals = 0;
-  walk<P>(a, c, s, lam5, delta, evals);
-  int commits = s.count;
-  for (int o = 32; o >= 1; o >>= 1) commits += __shfl_xor(commits, o, 64);
-  if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&a.counters[C_EVALS], (unsigned long long)evals);
-    atomicAdd((unsigned long long*)&a.counters[C_COMMITS], (unsigned long long)commits);
+  long long evals = 0, steps = 0;
+  walk<P>(a, c, s, lam5, delta, evals, steps);
+  if (diag) {
+    int commits = s.count;
+    for (int o = 32; o >= 1; o >>= 1) commits += __shfl_xor(commits, o, 64);
+    if (threadIdx.x == 0) {
+      const unsigned long long dt = wall_clock64() - t_start;
+      atomicAdd((unsigned long long*)&a.counters[C_EVALS], (unsigned long long)evals);
+      atomicAdd((unsigned long long*)&a.counters[C_COMMITS], (unsigned long long)commits);
+      atomicAdd((unsigned long long*)&a.counters[C_ITERS], (unsigned long long)steps);
+      atomicMax((unsigned long long*)&a.counters[C_MAXITER], (unsigned long long)steps);
+      atomicAdd((unsigned long long*)&a.counters[C_WTIME], dt);
+      atomicMax((unsigned long long*)&a.counters[C_WTMAX], dt);
+    }
   }
   if (c.inimg) {
     a.depth[c.pix] = s.D;
@@ -440,10 +451,35 @@ struct BwdLds {
   float a[kChunk][64];    // a* of the hit
   float T[kChunk][64];    // transmittance in front of the hit
   float cg[kChunk][64];   // c_j, then dL/dw_j after the back-to-front walk
+  int gpos[64];           // a group of candidates of the gradient pass: list positions, ascending
+  uint32_t vis[kBigSort / 32];  // list positions visited by the first gradient pass
 };
+
+// Sum 16 per-lane values over the wave by recursive halving: each exchange
+// step sends half of the values still held, so 17 lane exchanges replace
+// 16 x 6.  On return lane 4 q + r (r < 4) holds the total of value q, summed
+// in a fixed order.
+__device__ __forceinline__ float wave_sum16(float (&v)[16]) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int h = 8, o = 32; h >= 1; h >>= 1, o >>= 1) {
+    const bool up = lane & o;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const float send = up ? v[i] : v[i + h];
+      const float keep = up ? v[i + h] : v[i];
+      v[i] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  float r = v[0];
+  r += __shfl_xor(r, 2, 64);
+  r += __shfl_xor(r, 1, 64);
+  return r;
+}
 
 struct BwdSink {
   static constexpr int NP = 1;   // payload: c = gD t + gN . n of the hit
+  static constexpr bool BWD = true;
   float T;
   int count;
   int c0;
@@ -477,25 +513,41 @@ struct BwdSink {
   }
 };
 
+__device__ inline void zero_row(const RenderArgs& a, uint32_t em, int sub) {
+  float4* row = (float4*)(a.partial + ((size_t)em * a.max_sub + sub) * 16);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  row[0] = z; row[1] = z; row[2] = z; row[3] = z;
+}
+
+// Partial rows: every (list entry, 8x8 block) row of the tile is written by
+// its block, exactly once in the first pass (the gradient of a candidate the
+// block hits, zeros otherwise); further passes add to it.
 template <int P>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   __shared__ BwdLds L;
   __shared__ StageLds stage;
   if (a.counters[C_OVERFLOW]) return;
+  const bool diag = a.flags & kFlagDiag;
+  uint64_t tk = diag ? wall_clock64() : 0;
+  unsigned long long ph[4] = {0, 0, 0, 0}, ncand = 0, ngrp = 0;
+  auto mark = [&](int i) {
+    if (diag) {
+      const uint64_t now = wall_clock64();
+      ph[i] += now - tk;
+      tk = now;
+    }
+  };
   ItemCtx c;
   const int st = item_setup(a, blockIdx.x, c);
   if (st == 2) return;
   c.stage = &stage;
   const int lane = threadIdx.x;
-  // clear this block's partial rows of the tile list (blocks outside the
-  // image too: the per-record sums read every block of a tile)
-  for (int i = lane; i < c.e - c.b; i += 64) {
-    float4* row = (float4*)(a.partial + ((size_t)a.emit[c.b + i] * a.max_sub + c.sub) * 16);
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    row[0] = z; row[1] = z; row[2] = z; row[3] = z;
+  const int n = c.e - c.b;
+  if (st == 1) {   // block outside the image (partial tile): zero rows
+    for (int i = lane; i < n; i += 64) zero_row(a, a.emit[c.b + i], c.sub);
+    return;
   }
-  __threadfence_block();
-  if (st == 1) return;
+  for (int i = lane; i < kBigSort / 32; i += 64) L.vis[i] = 0u;
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
   const double delta = fringe_margin((double)lam, (double)a.tau, a.mode);
@@ -507,17 +559,23 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
     gN1 = a.g_normal[nb + c.HW];
     gN2 = a.g_normal[nb + 2 * c.HW];
   }
+  // a list of at most one batch stays staged in LDS after the walk
+  const bool one_batch = n <= 64;
+  mark(0);
   int passes = 1;
   for (int pass = 0; pass < passes; ++pass) {
     BwdSink s{1.f, 0, pass * kChunk, 1.f, 0.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
-    long long evals = 0;
-    walk<P>(a, c, s, lam5, delta, evals);
+    long long evals = 0, steps = 0;
+    walk<P>(a, c, s, lam5, delta, evals, steps);
     if (pass == 0) {
       const int jmax = wave_max_int(s.count);
       passes = (jmax + kChunk - 1) / kChunk;
       if (passes > 1 && lane == 0)
         atomicAdd((unsigned long long*)&a.counters[C_BWD_PASSES], (unsigned long long)(passes - 1));
+    } else {
+      __threadfence_block();   // rows written by other lanes are read back below
     }
+    mark(1);
     // back-to-front walk over this chunk
     const int nE = max(0, min(kChunk, s.count - pass * kChunk));
     float S = s.Stail;
@@ -543,62 +601,114 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
       L.T[m + 1][lane] = T;
       L.cg[m + 1][lane] = g;
     }
-    // visit the chunk's candidates in list order
+    mark(2);
+    // Visit the chunk's candidates in list order, in groups of up to 64:
+    // gather the next distinct positions (wave minimum of the lanes'
+    // cursors); a one-batch list is still staged, longer lists fetch the
+    // group's records in parallel; then form the per-pair gradients
+    // candidate by candidate.
     int k = 0;
     int npos = nE > 0 ? L.pos[0][lane] : 0x7fffffff;
     while (true) {
-      const int p = uniform_int(wave_min_int(npos));
-      if (p == 0x7fffffff) break;
-      const uint64_t key = a.keys[c.b + p];
-      const int ri = (int)(uint32_t)key;
-      const Rec& rec = a.recs[ri];
-      const bool act = npos == p;
-      float A[13];
-#pragma unroll
-      for (int q = 0; q < 13; ++q) A[q] = 0.f;
-      if (act) {
-        const float T = L.T[k][lane], gw = L.cg[k][lane];
-        const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
-        const float t = (float)g.t, a32 = (float)g.a;
-        const float PX = (float)g.PX, PY = (float)g.PY, den = (float)g.den;
-        float omw;
-        const float w = splat_weight(a32, lam5, a.mode, omw);
-        const float Tw = T * w;
-        const float ga = gw * splat_weight_grad(a32, w, omw, lam5, a.mode);
-        const float gaX = g.xbranch ? ga : 0.f, gaY = g.xbranch ? 0.f : ga;
-        const bool xp = g.PX > 0.0, yp = g.PY > 0.0;
-        const float gPX = xp ? -gaX : gaX;
-        const float gPY = yp ? -gaY : gaY;
-        // d.vx = (P_X + (p - o).vx) / t, d.vy likewise (x = o + t d)
-        const float it = 1.f / t;
-        const float G = Tw * gD + (gPX * (PX + rec.pvx) + gPY * (PY + rec.pvy)) * it;
-        const float Gd = G / den;
-        A[0] = gPX;
-        A[1] = gPY;
-        A[2] = Gd;
-        A[3] = gPX * PY - gPY * PX;
-        A[4] = Gd * PX;
-        A[5] = Gd * PY;
-        A[6] = Tw * gN0;
-        A[7] = Tw * gN1;
-        A[8] = Tw * gN2;
-        A[9] = xp ? gaX : 0.f;
-        A[10] = xp ? 0.f : gaX;
-        A[11] = yp ? gaY : 0.f;
-        A[12] = yp ? 0.f : gaY;
+      int grp = 0, kk = k, np = npos;
+      while (grp < 64) {
+        const int p = uniform_int(wave_min_int(np));
+        if (p == 0x7fffffff) break;
+        if (lane == 0) {
+          L.gpos[grp] = p;
+          if (pass == 0) L.vis[p >> 5] |= 1u << (p & 31);
+        }
+        ++grp;
+        if (np == p) {
+          ++kk;
+          np = kk < nE ? L.pos[kk][lane] : 0x7fffffff;
+        }
       }
+      if (grp == 0) break;
+      ncand += grp;
+      ++ngrp;
+      __syncthreads();
+      if (!one_batch) {
+        if (lane < grp) {
+          const int p = L.gpos[lane];
+          const float4* src = reinterpret_cast<const float4*>(&a.recs_s[c.b + p]);
 #pragma unroll
-      for (int q = 0; q < 13; ++q) A[q] = wave_sum(A[q]);
-      if (lane == 0) {
-        float* row = a.partial + ((size_t)a.emit[c.b + p] * a.max_sub + c.sub) * 16;
+          for (int q = 0; q < 7; ++q) stage.head[q][lane] = src[q];
+          const float4 tail = src[7];
+          stage.pv[lane] = make_float2(tail.z, tail.w);
+          stage.em[lane] = a.emit[c.b + p];
+        }
+        __syncthreads();
+      }
+      for (int gi = 0; gi < grp; ++gi) {
+        const int p = L.gpos[gi];
+        const int j = one_batch ? p : gi;   // staging slot of the candidate
+        const bool act = npos == p;
+        float A[16];
 #pragma unroll
-        for (int q = 0; q < 13; ++q) row[q] += A[q];
+        for (int q = 0; q < 16; ++q) A[q] = 0.f;
+        if (act) {
+          RecHead rec;
+          float nrm[3];
+          staged(stage, j, rec, nrm);
+          const float2 pv = stage.pv[j];
+          const float T = L.T[k][lane], gw = L.cg[k][lane];
+          const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+          const float t = (float)g.t, a32 = (float)g.a;
+          const float PX = (float)g.PX, PY = (float)g.PY, den = (float)g.den;
+          float omw;
+          const float w = splat_weight(a32, lam5, a.mode, omw);
+          const float Tw = T * w;
+          const float ga = gw * splat_weight_grad(a32, w, omw, lam5, a.mode);
+          const float gaX = g.xbranch ? ga : 0.f, gaY = g.xbranch ? 0.f : ga;
+          const bool xp = g.PX > 0.0, yp = g.PY > 0.0;
+          const float gPX = xp ? -gaX : gaX;
+          const float gPY = yp ? -gaY : gaY;
+          // d.vx = (P_X + (p - o).vx) / t, d.vy likewise (x = o + t d)
+          const float it = 1.f / t;
+          const float G = Tw * gD + (gPX * (PX + pv.x) + gPY * (PY + pv.y)) * it;
+          const float Gd = G / den;
+          A[0] = gPX;
+          A[1] = gPY;
+          A[2] = Gd;
+          A[3] = gPX * PY - gPY * PX;
+          A[4] = Gd * PX;
+          A[5] = Gd * PY;
+          A[6] = Tw * gN0;
+          A[7] = Tw * gN1;
+          A[8] = Tw * gN2;
+          A[9] = xp ? gaX : 0.f;
+          A[10] = xp ? 0.f : gaX;
+          A[11] = yp ? gaY : 0.f;
+          A[12] = yp ? 0.f : gaY;
+          ++k;
+          npos = k < nE ? L.pos[k][lane] : 0x7fffffff;
+        }
+        const float tot = wave_sum16(A);
+        // lane 4 q holds accumulator q: one store of the row's 13 values
+        const int q = lane >> 2;
+        if ((lane & 3) == 0 && q < 13) {
+          float* row = a.partial + ((size_t)stage.em[j] * a.max_sub + c.sub) * 16;
+          if (pass == 0)
+            row[q] = tot;
+          else
+            row[q] += tot;
+        }
       }
-      if (act) {
-        ++k;
-        npos = k < nE ? L.pos[k][lane] : 0x7fffffff;
-      }
+      __syncthreads();
     }
+    if (pass == 0) {
+      // rows of the list entries this block does not hit
+      for (int i = lane; i < n; i += 64)
+        if (!((L.vis[i >> 5] >> (i & 31)) & 1u))
+          zero_row(a, one_batch ? stage.em[i] : a.emit[c.b + i], c.sub);
+    }
+    mark(3);
+  }
+  if (diag && lane == 0) {
+    for (int i = 0; i < 4; ++i) atomicAdd((unsigned long long*)&a.counters[C_BT_SETUP + i], ph[i]);
+    atomicAdd((unsigned long long*)&a.counters[C_BG_CAND], ncand);
+    atomicAdd((unsigned long long*)&a.counters[C_BG_GROUPS], ngrp);
   }
 }
 
@@ -705,7 +815,8 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
   a.S = L->n_slots;
   a.n_items = L->n_items;
   a.recs = (const Rec*)(base + L->region[R_REC]);
-  a.tile_off = (const int*)(base + L->region[R_TILE_OFF]);
+  a.items = (const ItemDesc*)(base + L->region[R_ITEMS]);
+  a.recs_s = (const Rec*)(base + L->region[R_RECS_S]);
   a.keys = (const uint64_t*)(base + L->region[R_KEYS_S]);
   a.emit = (const uint32_t*)(base + L->region[R_EMIT_S]);
   a.rec_cnt = (const int*)(base + L->region[R_REC_CNT]);

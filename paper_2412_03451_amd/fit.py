@@ -1,0 +1,297 @@
+"""Fitting loop of the method (Sec. 3.3): Adam on the plane parameters against
+target depth and normal maps, with the loss of Eq. 14 and lambda of Eq. 10.
+
+One iteration is: ps_fit_schedule (device-side iteration counter, lambda,
+Adam step and the view of each job) -> plane_project -> tile_bin ->
+plane_render_fwd -> loss_depth_normal_cam -> plane_render_bwd ->
+adam_step_planes.  Every step runs in the library's kernels and nothing in it
+reads back to the host, so the iteration can be captured once in a HIP graph
+(torch.cuda.CUDAGraph) and replayed.
+
+Pair-list capacity: binning raises a device flag when the (tile, plane) pairs
+exceed the workspace; the flag is sticky until the workspace is re-initialised.
+The loop checks it after every run of `check_every` replays; on overflow it
+restores the state saved before that run, grows the workspace, captures again
+and repeats the run, so no iteration is ever applied with a truncated list.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from ._lib import check
+from .splat import Job, Renderer, SplatParams, _ptr, _stream, adam_step
+
+
+def view_schedule(n_views: int, n_rows: int, per_step: int = 1, seed: int = 0) -> np.ndarray:
+    """[n_rows][per_step] camera indices: concatenated random permutations of
+    the views (every view is used once per epoch)."""
+    rng = np.random.default_rng(seed)
+    need = n_rows * per_step
+    out = []
+    while sum(len(p) for p in out) < need:
+        out.append(rng.permutation(n_views))
+    return np.concatenate(out)[:need].reshape(n_rows, per_step).astype(np.int32)
+
+
+@dataclass
+class FitConfig:
+    tile: tuple = (16, 16)
+    views_per_step: int = 1
+    lr: tuple = (1e-3, 1e-3, 1e-3)     # center, quaternion, radii
+    betas: tuple = (0.9, 0.999)
+    eps: float = 1e-8
+    r_min: float = 1e-4
+    loss_w: tuple = (5.0, 5.0, 1.0)    # alpha_cos, alpha_nl1, alpha_d (Eq. 14)
+    schedule_rows: int = 5000
+    seed: int = 0
+    check_every: int = 100
+    grow: float = 1.5
+
+
+@dataclass
+class Scene:
+    """One scene of a batch: planes (numpy or tensors, [K,3] / [K,4] / [K,4]),
+    its cameras (all of one size) and per-view targets tgt_depth [V, H*W],
+    tgt_normal [V, 3*H*W] (device tensors).  tile and pending (render
+    pending-buffer size) may be set per scene (the autotuner's choice)."""
+    center: object
+    quat: object
+    radii: object
+    cams: list
+    tgt_depth: torch.Tensor
+    tgt_normal: torch.Tensor
+    tile: tuple | None = None
+    mask: torch.Tensor | None = None
+
+
+class BatchFit:
+    """Fit of one or many scenes at once: every step advances all scenes by
+    one iteration (views_per_step views each) in one launch per phase."""
+
+    def __init__(self, scenes, cfg: FitConfig | None = None, params: SplatParams | None = None,
+                 pair_capacity: int | None = None, size_capacity: bool = True, device="cuda"):
+        self.cfg = cfg or FitConfig()
+        self.device = torch.device(device)
+        dev = self.device
+        self.scenes = list(scenes)
+
+        def T(x):
+            return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev).clone()
+
+        cs = [T(sc.center).reshape(-1, 3) for sc in self.scenes]
+        self.c = torch.cat(cs).contiguous()
+        self.q = torch.cat([T(sc.quat).reshape(-1, 4) for sc in self.scenes]).contiguous()
+        self.r = torch.cat([T(sc.radii).reshape(-1, 4) for sc in self.scenes]).contiguous()
+        self.K = int(self.c.shape[0])
+        self.k_off = np.cumsum([0] + [int(x.shape[0]) for x in cs])
+        self.m = torch.zeros(11 * self.K, device=dev)
+        self.v = torch.zeros(11 * self.K, device=dev)
+        self.ite = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.lam = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.step_no = torch.zeros(1, dtype=torch.int32, device=dev)
+        S = self.cfg.views_per_step
+        cams, jobs, tables, tgt_off, tD, tN, masks = [], [], [], [], [], [], []
+        self.v_off = [0]
+        self.size = []
+        pix = 0
+        for si, sc in enumerate(self.scenes):
+            W, H = int(sc.cams[0].width), int(sc.cams[0].height)
+            if any(int(cm.width) != W or int(cm.height) != H for cm in sc.cams):
+                raise ValueError(f"scene {si}: all views must have the same size")
+            V = len(sc.cams)
+            self.size.append((W, H))
+            table = view_schedule(V, self.cfg.schedule_rows, S, self.cfg.seed + si) + self.v_off[-1]
+            tables.append(table)
+            tile = tuple(sc.tile or self.cfg.tile)
+            for j in range(S):
+                jobs.append(Job(int(self.k_off[si]), int(self.k_off[si + 1]), int(table[0, j]), W, H, tile, si))
+            for _ in range(V):
+                tgt_off.append(pix)
+                pix += W * H
+            cams += list(sc.cams)
+            tD.append(sc.tgt_depth.reshape(-1))
+            tN.append(sc.tgt_normal.reshape(-1))
+            masks.append(sc.mask)
+            self.v_off.append(self.v_off[-1] + V)
+        self.table = torch.as_tensor(np.concatenate(tables, axis=1), device=dev).contiguous()
+        self.tgt_depth = torch.cat(tD).contiguous()
+        self.tgt_normal = torch.cat(tN).contiguous()
+        if all(mk is None for mk in masks):
+            self.mask = None
+        else:
+            self.mask = torch.cat([mk.reshape(-1).to(torch.uint8) if mk is not None else
+                                   torch.ones(sc.tgt_depth.numel(), dtype=torch.uint8, device=dev)
+                                   for mk, sc in zip(masks, self.scenes)]).contiguous()
+        self.tgt_off = torch.tensor(tgt_off, dtype=torch.int64, device=dev)
+        self.params = params or SplatParams()
+        self.rend = Renderer(jobs, cams, device=dev, pair_capacity=pair_capacity or (1 << 16), params=self.params)
+        self.graph = None
+        self.last_loss = None
+        if size_capacity:
+            self._size_capacity()
+
+    # ------------------------------------------------------------------ capacity
+    def _size_capacity(self):
+        """Bin the current state (views of the next iteration) and grow the
+        workspace to fit with margin."""
+        lib = self.rend.lib
+        ite = self.ite.clone()
+        check(lib.ps_fit_schedule(C.byref(self.rend.L), _ptr(self.rend.ws), _ptr(ite), _ptr(self.table),
+                                  int(self.table.shape[0]), _ptr(self.lam), _ptr(self.step_no), _stream()))
+        self.rend.project(self.c, self.q, self.r, self.lam)
+        self.rend.bin(check_capacity=True, grow=2.0)
+
+    def _grow(self):
+        cap = int(self.rend.L.pair_capacity * self.cfg.grow) + 1024
+        self.rend._make_layout(cap)
+        self.graph = None
+
+    # ------------------------------------------------------------------ one step
+    def _step(self, mark=None, ite=None):
+        """One iteration; mark() (if given) is called between the phases,
+        ite (if given) replaces the state's iteration counter."""
+        cfg = self.cfg
+        rend = self.rend
+        m = mark or (lambda: None)
+        m()
+        check(rend.lib.ps_fit_schedule(C.byref(rend.L), _ptr(rend.ws), _ptr(self.ite if ite is None else ite),
+                                       _ptr(self.table), int(self.table.shape[0]), _ptr(self.lam),
+                                       _ptr(self.step_no), _stream()))
+        rend.project(self.c, self.q, self.r, self.lam)
+        m()
+        rend.bin(check_capacity=False)
+        m()
+        D, N = rend.forward()
+        m()
+        loss, gD, gN = rend.loss_cam(D, N, self.tgt_depth, self.tgt_normal, self.tgt_off, mask=self.mask,
+                                     a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2])
+        m()
+        gc, gq, gr = rend.backward(self.c, self.q, self.r, self.lam, gD, gN)
+        m()
+        adam_step(self.c, self.q, self.r, gc, gq, gr, self.m, self.v, self.step_no, lr=cfg.lr, betas=cfg.betas,
+                  eps=cfg.eps, r_min=cfg.r_min)
+        m()
+        return loss
+
+    def diagnose(self):
+        """Render statistics of the next iteration's views at the current
+        state (no state change): the render counters with walk statistics,
+        composited hits and the loss."""
+        cfg = self.cfg
+        rend = self.rend
+        ite = self.ite.clone()
+        check(rend.lib.ps_fit_schedule(C.byref(rend.L), _ptr(rend.ws), _ptr(ite), _ptr(self.table),
+                                       int(self.table.shape[0]), _ptr(self.lam), _ptr(self.step_no), _stream()))
+        rend.project(self.c, self.q, self.r, self.lam)
+        rend.bin(check_capacity=False)
+        D, N, Tr, Cn = rend.forward(diagnostics=True)
+        loss, gD, gN = rend.loss_cam(D, N, self.tgt_depth, self.tgt_normal, self.tgt_off, mask=self.mask,
+                                     a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2])
+        rend.backward(self.c, self.q, self.r, self.lam, gD, gN, diagnostics=True)
+        torch.cuda.synchronize()
+        cnt = rend.counters()
+        cnt["composited_hits"] = int(Cn.sum().item())
+        cnt["loss"] = loss.sum(0).cpu().tolist()
+        return cnt
+
+    def _capture(self):
+        # every kernel has run eagerly (capacity sizing, warm-up step) before capture
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._graph_loss = self._step()
+        self.graph = g
+
+    def state(self):
+        return [t.clone() for t in (self.c, self.q, self.r, self.m, self.v, self.ite)]
+
+    def restore(self, st):
+        for dst, src in zip((self.c, self.q, self.r, self.m, self.v, self.ite), st):
+            dst.copy_(src)
+
+    def overflowed(self) -> bool:
+        return bool(self.rend.counters()["overflow_since_init"])
+
+    def run(self, n_steps: int, graph: bool = True, callback=None):
+        """Advance n_steps iterations.  callback(fit, done) runs after every
+        checked run of steps (host side, after a synchronisation)."""
+        done = 0
+        while done < n_steps:
+            chunk = min(self.cfg.check_every, n_steps - done)
+            saved = self.state()
+            if graph and self.graph is None:
+                # one eager step (loads every kernel), then capture
+                self.restore(saved)
+                self._step()
+                torch.cuda.synchronize()
+                if self.overflowed():
+                    self.restore(saved)
+                    self._grow()
+                    continue
+                self.restore(saved)
+                self._capture()
+                self.restore(saved)
+            for _ in range(chunk):
+                if graph:
+                    self.graph.replay()
+                    self.last_loss = self._graph_loss
+                else:
+                    self.last_loss = self._step()
+            torch.cuda.synchronize()
+            if self.overflowed():
+                self.restore(saved)
+                self._grow()
+                continue
+            done += chunk
+            if callback is not None:
+                callback(self, done)
+        return self
+
+    # ------------------------------------------------------------------ evaluation
+    def planes(self, scene: int = 0):
+        a, b = int(self.k_off[scene]), int(self.k_off[scene + 1])
+        return self.c[a:b], self.q[a:b], self.r[a:b]
+
+    def render_view(self, view: int, scene: int = 0, lam: float | None = None):
+        """Depth [H, W] and normal [3, H, W] of one view of a scene at the
+        current state (lambda of the current iteration unless given)."""
+        W, H = self.size[scene]
+        a, b = int(self.k_off[scene]), int(self.k_off[scene + 1])
+        tile = tuple(self.scenes[scene].tile or self.cfg.tile)
+        r = Renderer([Job(a, b, self.v_off[scene] + view, W, H, tile)], self.rend.cams, device=self.device,
+                     pair_capacity=self.rend.L.pair_capacity, params=self.params)
+        lt = torch.tensor([lam if lam is not None else float(self.lam.item())], device=self.device)
+        D, N = r.render(self.c, self.q, self.r, lt)
+        return D.view(H, W), N.view(3, H, W)
+
+    def depth_l1(self, scene: int = 0, views=None, lam: float | None = None) -> float:
+        """Mean |D - D^| over the pixels of the given views of a scene (all by default)."""
+        W, H = self.size[scene]
+        V = self.v_off[scene + 1] - self.v_off[scene]
+        views = range(V) if views is None else views
+        tot, n = 0.0, 0
+        for vi in views:
+            D, _ = self.render_view(vi, scene, lam)
+            o = int(self.tgt_off[self.v_off[scene] + vi].item())
+            Dt = self.tgt_depth[o:o + W * H].view(H, W)
+            tot += float((D - Dt).abs().sum().item())
+            n += W * H
+        return tot / max(n, 1)
+
+
+class SceneFit(BatchFit):
+    """Plain fit of one scene: planes (K), cameras (V views) and per-view
+    targets tgt_depth [V, H*W], tgt_normal [V, 3*H*W] on the device."""
+
+    def __init__(self, center, quat, radii, cams, tgt_depth, tgt_normal, mask=None, cfg: FitConfig | None = None,
+                 params: SplatParams | None = None, pair_capacity: int | None = None, size_capacity: bool = True,
+                 device="cuda"):
+        cams = list(cams)
+        super().__init__([Scene(center, quat, radii, cams, tgt_depth, tgt_normal, mask=mask)], cfg=cfg,
+                         params=params, pair_capacity=pair_capacity, size_capacity=size_capacity, device=device)
+        self.V = len(cams)
+        self.W, self.H = self.size[0]

@@ -31,7 +31,7 @@ class SplatParams:
     z_near: float = 0.01
     weight_mode: int = 0   # 0: min(1, 2 sigmoid), 1: sigmoid
     two_sided: int = 1
-    flags: int = 0         # bit 0: force the exact fallback ordering path
+    flags: int = 0         # bit 0: exact fallback path; bits 4-5: pending size; bit 6: walk statistics
 
     def c(self) -> PsParams:
         return PsParams(self.M, self.tau, self.z_near, self.weight_mode, self.two_sided, self.flags)
@@ -89,6 +89,7 @@ class Renderer:
             pair_capacity = 1 << 16
         self._make_layout(int(pair_capacity))
         self.last_pairs = 0
+        self.generation = 0   # bumped by every project(): identifies the workspace contents
 
     @classmethod
     def single_scene(cls, cams, K: int, tile=(16, 16), **kw):
@@ -131,6 +132,7 @@ class Renderer:
     # ------------------------------------------------------------------ steps
     def project(self, center, quat, radii, lam):
         self._inputs = (center, quat, radii, lam)
+        self.generation = getattr(self, "generation", 0) + 1
         prm = self.params.c()
         check(self.lib.plane_project(C.byref(self.L), _ptr(self.ws), _ptr(center), _ptr(quat), _ptr(radii),
                                      int(center.shape[0]), _ptr(self.cams), self.n_cams, _ptr(lam),
@@ -159,6 +161,8 @@ class Renderer:
             trans = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
             count = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
         prm = self.params.c()
+        if diagnostics:
+            prm.flags |= 64
         _, _, _, lam = self._inputs
         check(self.lib.plane_render_fwd(C.byref(self.L), _ptr(self.ws), _ptr(self.cams), self.n_cams, _ptr(lam),
                                         C.byref(prm), _ptr(depth), _ptr(normal), _ptr(trans), _ptr(count),
@@ -181,12 +185,25 @@ class Renderer:
                                          _ptr(loss), _ptr(gD), _ptr(gN), _stream()))
         return loss, gD, gN
 
-    def backward(self, center, quat, radii, lam, g_depth, g_normal):
+    def loss_cam(self, depth, normal, tgt_depth, tgt_normal, tgt_off, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0):
+        """Loss against per-camera targets (tgt_off: device int64 pixel offset of each camera's target)."""
+        loss = torch.empty(len(self.jobs), 4, dtype=torch.float32, device=self.device)
+        gD = torch.empty_like(depth)
+        gN = torch.empty_like(normal)
+        check(self.lib.loss_depth_normal_cam(C.byref(self.L), _ptr(self.ws), _ptr(depth), _ptr(normal),
+                                             _ptr(tgt_depth), _ptr(tgt_normal), _ptr(mask), _ptr(tgt_off),
+                                             int(tgt_off.numel()), a_cos, a_nl1, a_d, _ptr(loss), _ptr(gD), _ptr(gN),
+                                             _stream()))
+        return loss, gD, gN
+
+    def backward(self, center, quat, radii, lam, g_depth, g_normal, diagnostics: bool = False):
         K = int(center.shape[0])
         gc = torch.empty(K, 3, dtype=torch.float32, device=self.device)
         gq = torch.empty(K, 4, dtype=torch.float32, device=self.device)
         gr = torch.empty(K, 4, dtype=torch.float32, device=self.device)
         prm = self.params.c()
+        if diagnostics:
+            prm.flags |= 64
         check(self.lib.plane_render_bwd(C.byref(self.L), _ptr(self.ws), _ptr(center), _ptr(quat), _ptr(radii), K,
                                         _ptr(self.cams), self.n_cams, _ptr(lam), C.byref(prm),
                                         _ptr(g_depth.contiguous()), _ptr(g_normal.contiguous()),
@@ -194,10 +211,13 @@ class Renderer:
         return gc, gq, gr
 
     def counters(self):
-        out = (C.c_int64 * 8)()
+        out = (C.c_int64 * 19)()
         check(self.lib.ps_read_counters(C.byref(self.L), _ptr(self.ws), out, _stream()))
         return dict(pairs=out[0], overflow=out[1], max_tile=out[2], slow_pixels=out[3], big_tiles=out[4],
-                    bwd_extra_passes=out[5], evals=out[6], commits=out[7])
+                    bwd_extra_passes=out[5], evals=out[6], commits=out[7], steps=out[8], max_steps=out[9],
+                    wave_ticks=out[10], max_wave_ticks=out[11], bwd_ticks_setup=out[12], bwd_ticks_walk=out[13],
+                    bwd_ticks_sort=out[14], bwd_ticks_grad=out[15], bwd_grad_candidates=out[16],
+                    bwd_grad_groups=out[17], overflow_since_init=out[18])
 
     # ------------------------------------------------------------------ image views
     def job_depth(self, depth, s):

@@ -138,7 +138,8 @@ def main():
     fit = SceneFit(init.center, init.quat, init.radii, cams, tgt_d.view(n_views, -1), tgt_n.view(n_views, -1),
                    cfg=cfg, params=params, device=dev)
     fit.ite.fill_(args.start_ite)
-    log(f"pair capacity {fit.rend.L.pair_capacity}")
+    need = fit.size_capacity()
+    log(f"pairs needed (max over views) {need}, capacity {fit.rend.L.pair_capacity}")
     start_state = fit.state()
 
     # warm-up (eager step, graph capture, replays; grows the lists if needed)
@@ -236,6 +237,7 @@ def main():
                          "blocks": n_items,
                          "bwd_block_us_mean": {k: round(cnt["bwd_ticks_" + k] / 100.0 / n_items, 3)
                                                for k in ("setup", "walk", "sort", "grad")},
+                         "bwd_block_us_max": round(cnt["bwd_max_block_ticks"] / 100.0, 3),
                          "bwd_grad_candidates": int(cnt["bwd_grad_candidates"]),
                          "bwd_grad_groups": int(cnt["bwd_grad_groups"])},
         "roofline": roof,

@@ -232,8 +232,9 @@ int adam_step_planes(float* center, float* quat, float* radii, const float* g_ce
  * out[16] the candidates visited and out[17] the candidate groups fetched by
  * the gradient pass.  out[18] is nonzero once any tile_bin since
  * ps_workspace_init overflowed (steps replayed from a graph check it after a
- * run of steps).  PS_N_COUNTERS values are written. */
-#define PS_N_COUNTERS 19
+ * run of steps); out[19] is the longest backward block time (ticks, flags
+ * bit 6).  PS_N_COUNTERS values are written. */
+#define PS_N_COUNTERS 20
 int ps_read_counters(const ps_layout* L, void* ws, int64_t out[PS_N_COUNTERS], void* stream);
 
 /* Message of the last error on this thread. */

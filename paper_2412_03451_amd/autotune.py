@@ -1,0 +1,108 @@
+"""Autotuner of the render configuration: tile shape (8x8, 16x16, 32x8) and
+pending-hit buffer size, chosen per (image size, plane-count bucket) by
+timing graph-replayed fitting steps on the scene itself.
+
+The results are cached in a JSON file (PLANESPLAT_TUNE_CACHE, else
+~/.cache/planesplat/tune.json): key "WxH/K<bucket>" -> {"tile": [w, h],
+"pending": p, "ms": step time, "tried": {...}}.  Tuning only reads the scene;
+the fits it times are thrown away.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import replace
+
+import torch
+
+from .fit import BatchFit, FitConfig, Scene
+from .splat import SplatParams
+
+TILES = ((16, 16), (32, 8), (8, 8))
+PENDING = (6, 8, 4)
+_PENDING_BITS = {6: 0, 4: 1, 8: 2, 12: 3}
+
+
+def pending_flags(pending: int) -> int:
+    """ps_params.flags bits 4-5 for a pending-buffer size."""
+    return _PENDING_BITS[pending] << 4
+
+
+def k_bucket(K: int) -> int:
+    return 1 << max(0, int(round(math.log2(max(K, 1)))))
+
+
+def cache_key(width: int, height: int, K: int) -> str:
+    return f"{width}x{height}/K{k_bucket(K)}"
+
+
+def default_cache_path() -> str:
+    return os.environ.get("PLANESPLAT_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "planesplat", "tune.json"))
+
+
+class Autotuner:
+    def __init__(self, path: str | None = None):
+        self.path = path or default_cache_path()
+        self.table = {}
+        if os.path.exists(self.path):
+            with open(self.path) as f:
+                self.table = json.load(f)
+
+    def save(self):
+        os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.table, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+    def lookup(self, width: int, height: int, K: int):
+        """(tile, pending) cached for this shape, or None."""
+        e = self.table.get(cache_key(width, height, K))
+        return None if e is None else (tuple(e["tile"]), int(e["pending"]))
+
+    @staticmethod
+    def time_config(scene: Scene, tile, pending: int, cfg: FitConfig, steps: int, warmup: int) -> float:
+        """ms per graph-replayed fitting step of one scene with this configuration."""
+        sc = replace(scene, tile=tuple(tile))
+        fit = BatchFit([sc], cfg=replace(cfg, check_every=max(1, warmup)),
+                       params=SplatParams(flags=pending_flags(pending)))
+        fit.run(max(1, warmup), graph=True)
+        st = torch.cuda.current_stream()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(st)
+        for _ in range(steps):
+            fit.graph.replay()
+        b.record(st)
+        torch.cuda.synchronize()
+        if fit.overflowed():
+            return float("inf")
+        return a.elapsed_time(b) / steps
+
+    def tune(self, scene: Scene, cfg: FitConfig | None = None, steps: int = 20, warmup: int = 5,
+             tiles=TILES, pendings=PENDING, force: bool = False):
+        """Best (tile, pending) for the scene's shape; cached."""
+        W, H = int(scene.cams[0].width), int(scene.cams[0].height)
+        K = int(torch.as_tensor(scene.center).reshape(-1, 3).shape[0])
+        key = cache_key(W, H, K)
+        if not force and key in self.table:
+            e = self.table[key]
+            return tuple(e["tile"]), int(e["pending"])
+        cfg = cfg or FitConfig()
+        tried = {}
+        # tiles first at the default buffer size, then buffer sizes at the best tile
+        for t in tiles:
+            tried[f"{t[0]}x{t[1]}/p{pendings[0]}"] = self.time_config(scene, t, pendings[0], cfg, steps, warmup)
+        best_t = min(tiles, key=lambda t: tried[f"{t[0]}x{t[1]}/p{pendings[0]}"])
+        for p in pendings[1:]:
+            tried[f"{best_t[0]}x{best_t[1]}/p{p}"] = self.time_config(scene, best_t, p, cfg, steps, warmup)
+        best = min(tried, key=tried.get)
+        tile_s, p_s = best.split("/p")
+        tile = tuple(int(x) for x in tile_s.split("x"))
+        self.table[key] = {"tile": list(tile), "pending": int(p_s), "ms": tried[best], "tried": tried}
+        self.save()
+        return tile, int(p_s)

@@ -198,6 +198,7 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
     a.counters[C_SLOW] = 0;
     a.counters[C_BWD_PASSES] = 0;
     for (int k = C_EVALS; k < C_STICKY; ++k) a.counters[k] = 0;
+    a.counters[C_BT_MAX] = 0;
   }
 }
 

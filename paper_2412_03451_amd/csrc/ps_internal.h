@@ -126,9 +126,10 @@ enum Counter {
   C_BT_GRAD = 15,
   C_BG_CAND = 16,  // candidates visited by the gradient pass
   C_BG_GROUPS = 17, // candidate groups fetched by the gradient pass
-  C_STICKY = 18    // nonzero once any tile_bin since ps_workspace_init overflowed
+  C_STICKY = 18,   // nonzero once any tile_bin since ps_workspace_init overflowed
+  C_BT_MAX = 19    // longest backward block run time (ticks)
 };
-static_assert(C_STICKY + 1 == PS_N_COUNTERS, "counter count");
+static_assert(C_BT_MAX + 1 == PS_N_COUNTERS, "counter count");
 constexpr int kFlagDiag = 64;   // params.flags bit 6: forward walk statistics
 
 constexpr int kMaxM = 30;

@@ -706,6 +706,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
     mark(3);
   }
   if (diag && lane == 0) {
+    atomicMax((unsigned long long*)&a.counters[C_BT_MAX], ph[0] + ph[1] + ph[2] + ph[3]);
     for (int i = 0; i < 4; ++i) atomicAdd((unsigned long long*)&a.counters[C_BT_SETUP + i], ph[i]);
     atomicAdd((unsigned long long*)&a.counters[C_BG_CAND], ncand);
     atomicAdd((unsigned long long*)&a.counters[C_BG_GROUPS], ngrp);

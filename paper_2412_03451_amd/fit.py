@@ -146,6 +146,28 @@ class BatchFit:
         self.rend.project(self.c, self.q, self.r, self.lam)
         self.rend.bin(check_capacity=True, grow=2.0)
 
+    def size_capacity(self, rows: int | None = None, margin: float = 1.5):
+        """Size the pair lists for the views of the first `rows` schedule rows
+        (every view of the largest scene by default) at the current state."""
+        lib = self.rend.lib
+        if rows is None:
+            rows = max(self.v_off[i + 1] - self.v_off[i] for i in range(len(self.scenes)))
+        rows = min(rows, int(self.table.shape[0]))
+        need_max = 0
+        for row in range(rows):
+            ite = torch.tensor([int(self.ite.item()) + row], dtype=torch.int32, device=self.device)
+            check(lib.ps_fit_schedule(C.byref(self.rend.L), _ptr(self.rend.ws), _ptr(ite), _ptr(self.table),
+                                      int(self.table.shape[0]), _ptr(self.lam), _ptr(self.step_no), _stream()))
+            self.rend.project(self.c, self.q, self.r, self.lam)
+            need = C.c_int64(0)
+            self.rend.lib.tile_bin(C.byref(self.rend.L), _ptr(self.rend.ws), C.byref(need), _stream())
+            need_max = max(need_max, int(need.value))
+        cap = int(need_max * margin) + 1024
+        if cap != self.rend.L.pair_capacity:
+            self.rend._make_layout(cap)
+            self.graph = None
+        return need_max
+
     def _grow(self):
         cap = int(self.rend.L.pair_capacity * self.cfg.grow) + 1024
         self.rend._make_layout(cap)
@@ -220,7 +242,11 @@ class BatchFit:
         """Advance n_steps iterations.  callback(fit, done) runs after every
         checked run of steps (host side, after a synchronisation)."""
         done = 0
+        grows = 0
         while done < n_steps:
+            if grows > 8:
+                raise RuntimeError("pair lists keep overflowing after growing the workspace: a tile list "
+                                   "probably exceeds the per-tile limit (use smaller tiles)")
             chunk = min(self.cfg.check_every, n_steps - done)
             saved = self.state()
             if graph and self.graph is None:
@@ -231,6 +257,7 @@ class BatchFit:
                 if self.overflowed():
                     self.restore(saved)
                     self._grow()
+                    grows += 1
                     continue
                 self.restore(saved)
                 self._capture()
@@ -245,6 +272,7 @@ class BatchFit:
             if self.overflowed():
                 self.restore(saved)
                 self._grow()
+                grows += 1
                 continue
             done += chunk
             if callback is not None:

@@ -211,13 +211,13 @@ class Renderer:
         return gc, gq, gr
 
     def counters(self):
-        out = (C.c_int64 * 19)()
+        out = (C.c_int64 * 20)()
         check(self.lib.ps_read_counters(C.byref(self.L), _ptr(self.ws), out, _stream()))
         return dict(pairs=out[0], overflow=out[1], max_tile=out[2], slow_pixels=out[3], big_tiles=out[4],
                     bwd_extra_passes=out[5], evals=out[6], commits=out[7], steps=out[8], max_steps=out[9],
                     wave_ticks=out[10], max_wave_ticks=out[11], bwd_ticks_setup=out[12], bwd_ticks_walk=out[13],
                     bwd_ticks_sort=out[14], bwd_ticks_grad=out[15], bwd_grad_candidates=out[16],
-                    bwd_grad_groups=out[17], overflow_since_init=out[18])
+                    bwd_grad_groups=out[17], overflow_since_init=out[18], bwd_max_block_ticks=out[19])
 
     # ------------------------------------------------------------------ image views
     def job_depth(self, depth, s):

@@ -15,6 +15,7 @@ from .scenes import (  # noqa: F401
     room_planes,
     room_trajectory,
     room_init_planes,
+    room_batch_specs,
     quat_from_matrix,
     quat_mul,
 )

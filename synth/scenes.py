@@ -286,3 +286,18 @@ def room_init_planes(gt: PlaneSet, seed: int = 1) -> PlaneSet:
     """Noisy initialisation of a room fit: center sigma 0.1 m, rotation sigma
     10 deg, each radius scaled by U[0.7, 1.3]."""
     return perturb_planes(gt, seed, 0.1, 10.0, (0.7, 1.3))
+
+
+def room_batch_specs(n_rooms: int, seed: int = 0, k_range=(200, 4000), view_range=(20, 100)):
+    """Shapes of a batch of synthetic rooms: per room a seed, a plane count
+    log-uniform in k_range, a view count uniform in view_range and, with
+    probability 1/2 each, 320 x 240 (f = 288.5) or 640 x 480 (f = 577)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_rooms):
+        K = int(round(math.exp(rng.uniform(math.log(k_range[0]), math.log(k_range[1])))))
+        V = int(rng.integers(view_range[0], view_range[1] + 1))
+        small = bool(rng.uniform() < 0.5)
+        W, H, f = (320, 240, 288.5) if small else (640, 480, 577.0)
+        out.append({"seed": seed + i, "K": K, "views": V, "width": W, "height": H, "f": f})
+    return out

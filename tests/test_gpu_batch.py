@@ -1,0 +1,118 @@
+"""Batched fitting (many scenes advanced by one launch per phase): a batch of
+scenes with different plane counts, image sizes and tile shapes renders and
+differentiates exactly as each scene on its own; one job of the batch
+matches the float64 oracle; graph replays of the batched step equal eager
+steps; the autotuner picks and caches a configuration."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import depth_err, normal_err, f32
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+SPECS = [  # (planes, seed, width, height, f, tile)
+    (30, 11, 128, 96, 100.0, (16, 16)),
+    (64, 12, 96, 72, 80.0, (8, 8)),
+    (100, 13, 80, 60, 70.0, (32, 8)),
+]
+
+
+def _batch():
+    from paper_2412_03451_amd.splat import Job
+    scenes, jobs, cams, off = [], [], [], 0
+    for i, (K, seed, W, H, f, tile) in enumerate(SPECS):
+        ps = synth.random_planes(K, seed=seed, independent_radii=True)
+        cam = synth.Camera(W, H, f, f, W / 2, H / 2, np.eye(3, dtype=np.float32),
+                           np.array([0.1 * i, -0.05 * i, 3.0], np.float32))
+        scenes.append((ps, cam, tile))
+        jobs.append(Job(off, off + K, i, W, H, tile, i))
+        cams.append(cam)
+        off += K
+    return scenes, jobs, cams
+
+
+def test_batch_equals_separate_and_oracle():
+    from paper_2412_03451_amd.splat import Job, Renderer
+    scenes, jobs, cams = _batch()
+    c = torch.cat([_dev(s[0].center) for s in scenes])
+    q = torch.cat([_dev(s[0].quat) for s in scenes])
+    r = torch.cat([_dev(s[0].radii) for s in scenes])
+    lam = f32(25.0)
+    lt = torch.tensor([lam], device="cuda")
+    rb = Renderer(jobs, cams)
+    D, N = rb.render(c, q, r, lt)
+    rng = np.random.default_rng(0)
+    gD = _dev(rng.normal(size=rb.n_pixels))
+    gN = _dev(rng.normal(size=3 * rb.n_pixels))
+    gb = rb.backward(c, q, r, lt, gD, gN)
+    torch.cuda.synchronize()
+    for i, (ps, cam, tile) in enumerate(scenes):
+        a, b = jobs[i].plane_begin, jobs[i].plane_end
+        rs = Renderer([Job(0, b - a, 0, cam.width, cam.height, tile)], [cam])
+        ds, ns = rs.render(c[a:b].contiguous(), q[a:b].contiguous(), r[a:b].contiguous(), lt)
+        o, P = rb.pix_off[i], cam.width * cam.height
+        gs = rs.backward(c[a:b].contiguous(), q[a:b].contiguous(), r[a:b].contiguous(), lt,
+                         gD[o:o + P].contiguous(), gN[3 * o:3 * (o + P)].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(ds, D[o:o + P])
+        assert torch.equal(ns, N[3 * o:3 * (o + P)])
+        for x, y in zip(gs, gb):
+            assert torch.equal(x, y[a:b])
+    # one job against the oracle
+    ps, cam, _ = scenes[1]
+    Dr, Nr, _ = oracle.render(ps.center, ps.quat, ps.radii, cam, lam)
+    o, P = rb.pix_off[1], cam.width * cam.height
+    assert depth_err(D[o:o + P].cpu().numpy().reshape(cam.height, cam.width), Dr.numpy()).max() <= 1.0
+    assert normal_err(N[3 * o:3 * (o + P)].cpu().numpy().reshape(3, cam.height, cam.width), Nr.numpy()).max() <= 1.0
+
+
+def _room_scenes():
+    from paper_2412_03451_amd.fit import Scene
+    from paper_2412_03451_amd.splat import Job, Renderer
+    out = []
+    for i, (K, W, H, f, tile) in enumerate([(120, 96, 72, 86.5, (16, 16)), (220, 128, 96, 115.4, (32, 8))]):
+        gt, info = synth.room_planes(seed=20 + i, target_K=K)
+        cams = synth.room_trajectory(20 + i, 3, info, width=W, height=H, f=f)
+        init = synth.room_init_planes(gt, seed=30 + i)
+        rt = Renderer([Job(0, gt.K, v, W, H, tile) for v in range(len(cams))], cams)
+        tD, tN = rt.render(_dev(gt.center), _dev(gt.quat), _dev(gt.radii), torch.tensor([300.0], device="cuda"))
+        out.append(Scene(init.center, init.quat, init.radii, cams, tD.view(len(cams), -1).clone(),
+                         tN.view(len(cams), -1).clone(), tile=tile))
+    return out
+
+
+def test_batch_fit_graph_equals_eager():
+    from paper_2412_03451_amd.fit import BatchFit, FitConfig
+    scenes = _room_scenes()
+    states = []
+    for graph in (False, True):
+        f = BatchFit(scenes, cfg=FitConfig(check_every=8))
+        got = []
+        f.run(24, graph=graph, callback=lambda fit, done: got.append(fit.state()))
+        states.append(got)
+    for a, b in zip(*states):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+
+
+def test_autotuner_caches_choice(tmp_path):
+    from paper_2412_03451_amd.autotune import Autotuner, cache_key
+    scenes = _room_scenes()
+    at = Autotuner(str(tmp_path / "tune.json"))
+    tile, pending = at.tune(scenes[0], steps=3, warmup=2)
+    assert tile in ((16, 16), (32, 8), (8, 8)) and pending in (4, 6, 8)
+    at2 = Autotuner(str(tmp_path / "tune.json"))
+    W, H = scenes[0].cams[0].width, scenes[0].cams[0].height
+    K = int(np.asarray(scenes[0].center).shape[0])
+    assert at2.lookup(W, H, K) == (tile, pending)
+    assert cache_key(W, H, K) in at2.table
+    assert len(at2.table[cache_key(W, H, K)]["tried"]) == 5

@@ -78,8 +78,9 @@ typedef struct ps_params {
                           bits 4-5: pending hits kept per lane by the render
                           walks, 0: 6, 1: 4, 2: 8, 3: 12 (a tuning knob, the
                           result does not depend on it);
-                          bit 6: record forward walk statistics in the
-                          counters (ps_read_counters out[6..11]) */
+                          bit 6: record per-block walk statistics of the
+                          forward and backward renders (ps_read_counters
+                          out[6..17] and out[19]) */
 } ps_params;
 
 /* One render job.  The caller fills the first block; ps_layout_init fills
@@ -222,15 +223,15 @@ int adam_step_planes(float* center, float* quat, float* radii, const float* g_ce
  * out[0] pairs needed, out[1] overflow flag, out[2] largest tile list,
  * out[3] pixels that took the exact fallback ordering path, out[4] tiles
  * sorted by the large-list pass, out[5] extra backward recompute passes.
- * Forward walks run with flags bit 6 add, since the last tile_bin:
- * out[6] (pixel, candidate) pairs evaluated, out[7] hits composited,
- * out[8] candidate steps summed over 8x8 blocks, out[9] the most steps of one
- * block, out[10] block run time summed and out[11] its maximum, in ticks of
- * the 100 MHz device wall clock.  Backward walks run with flags bit 6 add
- * out[12..15] the blocks' time spent in set-up, recompute walks, the
- * back-to-front pass with its sort and the gradient pass (ticks, summed),
- * out[16] the candidates visited and out[17] the candidate groups fetched by
- * the gradient pass.  out[18] is nonzero once any tile_bin since
+ * Statistics of the last forward run with flags bit 6 (per 8x8 block,
+ * reduced in a fixed order): out[6] (pixel, candidate) pairs evaluated,
+ * out[7] hits composited, out[8] candidate steps summed over blocks, out[9]
+ * the most steps of one block, out[10] block run time summed and out[11] its
+ * maximum, in ticks of the 100 MHz device wall clock.  Of the last backward
+ * run with flags bit 6: out[12..15] the blocks' time spent in set-up,
+ * recompute walks, the back-to-front pass with its sort and the gradient pass
+ * (ticks, summed), out[16] the candidates visited and out[17] the candidate
+ * groups fetched by the gradient pass.  out[18] is nonzero once any tile_bin since
  * ps_workspace_init overflowed (steps replayed from a graph check it after a
  * run of steps); out[19] is the longest backward block time (ticks, flags
  * bit 6).  PS_N_COUNTERS values are written. */

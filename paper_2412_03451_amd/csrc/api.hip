@@ -86,6 +86,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
       4 * (T + 1),                     // R_BIGTILES
       sizeof(ps::ItemDesc) * ((size_t)items + 1),  // R_ITEMS
       sizeof(ps::Rec) * C,             // R_RECS_S
+      8 * ps::D_NUM * ((size_t)items + 1),  // R_DIAG
   };
   size_t off = 0;
   for (int i = 0; i < PS_NUM_REGIONS; ++i) {
@@ -126,6 +127,9 @@ extern "C" int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void*
   const int64_t n = 2 * 64;  // counters as int32 words
   hipLaunchKernelGGL(ps_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st,
                      (int32_t*)(base + L->region[ps::R_COUNTERS]), n, 0);
+  const int64_t nd = 2 * (int64_t)ps::D_NUM * (L->n_items + 1);  // statistics as int32 words
+  hipLaunchKernelGGL(ps_fill_i32, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st,
+                     (int32_t*)(base + L->region[ps::R_DIAG]), nd, 0);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
@@ -170,11 +174,58 @@ extern "C" int ps_fit_schedule(const ps_layout* L, void* ws, int32_t* ite, const
   return PS_OK;
 }
 
+// Sums and maxima of the per-block statistics into the counters (one
+// workgroup, fixed order).
+__global__ __launch_bounds__(1024) void ps_diag_reduce_kernel(const long long* diag, int n_items, long long* counters) {
+  __shared__ long long red[32][11];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  long long sum[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  long long mx_steps = 0, mx_fwd = 0, mx_bwd = 0;
+  for (int i = tid; i < n_items; i += 1024) {
+    const long long* d = diag + (size_t)i * ps::D_NUM;
+    for (int k = 0; k < 11; ++k) sum[k] += d[k];
+    mx_steps = max(mx_steps, d[ps::D_STEPS]);
+    mx_fwd = max(mx_fwd, d[ps::D_FWD_TICKS]);
+    mx_bwd = max(mx_bwd, d[ps::D_BWD_TICKS]);
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    for (int k = 0; k < 11; ++k) sum[k] += __shfl_xor(sum[k], o, 64);
+    mx_steps = max(mx_steps, __shfl_xor(mx_steps, o, 64));
+    mx_fwd = max(mx_fwd, __shfl_xor(mx_fwd, o, 64));
+    mx_bwd = max(mx_bwd, __shfl_xor(mx_bwd, o, 64));
+  }
+  if (lane == 0) {
+    for (int k = 0; k < 11; ++k) red[wid][k] = sum[k];
+    red[16 + wid][0] = mx_steps; red[16 + wid][1] = mx_fwd; red[16 + wid][2] = mx_bwd;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 16; ++w) {
+      for (int k = 0; k < 11; ++k) red[0][k] += red[w][k];
+      for (int k = 0; k < 3; ++k) red[16][k] = max(red[16][k], red[16 + w][k]);
+    }
+    counters[ps::C_EVALS] = red[0][ps::D_EVALS];
+    counters[ps::C_COMMITS] = red[0][ps::D_COMMITS];
+    counters[ps::C_ITERS] = red[0][ps::D_STEPS];
+    counters[ps::C_MAXITER] = red[16][0];
+    counters[ps::C_WTIME] = red[0][ps::D_FWD_TICKS];
+    counters[ps::C_WTMAX] = red[16][1];
+    for (int k = 0; k < 4; ++k) counters[ps::C_BT_SETUP + k] = red[0][ps::D_BWD_SETUP + k];
+    counters[ps::C_BG_CAND] = red[0][ps::D_BWD_CAND];
+    counters[ps::C_BG_GROUPS] = red[0][ps::D_BWD_GROUPS];
+    counters[ps::C_BT_MAX] = red[16][2];
+  }
+}
+
 extern "C" int ps_read_counters(const ps_layout* L, void* ws, int64_t out[PS_N_COUNTERS], void* stream) {
   int rc = ps_check_ws(L, ws, "ps_read_counters");
   if (rc) return rc;
   if (!out) return ps_set_error(PS_ERR_INVALID, "ps_read_counters: null output");
   hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(ps_diag_reduce_kernel, dim3(1), dim3(1024), 0, st,
+                     (const long long*)((char*)ws + L->region[ps::R_DIAG]), L->n_items,
+                     (long long*)((char*)ws + L->region[ps::R_COUNTERS]));
+  PS_HIP_CHECK(hipGetLastError());
   int64_t tmp[PS_N_COUNTERS];
   PS_HIP_CHECK(hipMemcpyAsync(tmp, (char*)ws + L->region[ps::R_COUNTERS], sizeof(tmp),
                               hipMemcpyDeviceToHost, st));

@@ -90,7 +90,14 @@ enum Region {
   R_BIGTILES,    // int[T]       tiles whose list exceeds the small sort
   R_ITEMS,       // ItemDesc[n_items]  per 8x8 block: list range, pixel origin, camera
   R_RECS_S,      // Rec[C]       record copies in tile-list order
+  R_DIAG,        // int64[n_items][16]  per-block walk statistics (flags bit 6)
   R_NUM_USED     // further regions are reserved (size 0)
+};
+// per-block statistics slots of R_DIAG
+enum DiagSlot {
+  D_EVALS = 0, D_COMMITS, D_STEPS, D_FWD_TICKS,
+  D_BWD_SETUP, D_BWD_WALK, D_BWD_SORT, D_BWD_GRAD, D_BWD_CAND, D_BWD_GROUPS, D_BWD_TICKS,
+  D_NUM = 16
 };
 static_assert(R_NUM_USED <= PS_NUM_REGIONS, "region table");
 

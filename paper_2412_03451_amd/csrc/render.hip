@@ -48,6 +48,7 @@ struct RenderArgs {
   float tau, z_near;
   int M, mode, flags, two_sided;
   long long* counters;
+  long long* diag;          // per-block statistics (flags bit 6)
   float* depth;
   float* normal;
   float* trans;      // optional: final transmittance per pixel
@@ -410,6 +411,8 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   if (a.counters[C_OVERFLOW]) return;
   const bool diag = a.flags & kFlagDiag;
   const uint64_t t_start = diag ? wall_clock64() : 0;
+  long long* dg = a.diag + (size_t)blockIdx.x * D_NUM;
+  if (diag && threadIdx.x < D_BWD_SETUP) dg[threadIdx.x] = 0;
   ItemCtx c;
   if (item_setup(a, blockIdx.x, c) != 0) return;
   c.stage = &stage;
@@ -423,13 +426,10 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
     int commits = s.count;
     for (int o = 32; o >= 1; o >>= 1) commits += __shfl_xor(commits, o, 64);
     if (threadIdx.x == 0) {
-      const unsigned long long dt = wall_clock64() - t_start;
-      atomicAdd((unsigned long long*)&a.counters[C_EVALS], (unsigned long long)evals);
-      atomicAdd((unsigned long long*)&a.counters[C_COMMITS], (unsigned long long)commits);
-      atomicAdd((unsigned long long*)&a.counters[C_ITERS], (unsigned long long)steps);
-      atomicMax((unsigned long long*)&a.counters[C_MAXITER], (unsigned long long)steps);
-      atomicAdd((unsigned long long*)&a.counters[C_WTIME], dt);
-      atomicMax((unsigned long long*)&a.counters[C_WTMAX], dt);
+      dg[D_EVALS] = evals;
+      dg[D_COMMITS] = commits;
+      dg[D_STEPS] = steps;
+      dg[D_FWD_TICKS] = (long long)(wall_clock64() - t_start);
     }
   }
   if (c.inimg) {
@@ -458,19 +458,30 @@ struct BwdLds {
 // Sum 16 per-lane values over the wave by recursive halving: each exchange
 // step sends half of the values still held, so 17 lane exchanges replace
 // 16 x 6.  On return lane 4 q + r (r < 4) holds the total of value q, summed
-// in a fixed order.
+// in a fixed order.  The steps are unrolled by templates so that every array
+// index is a constant (a select between two elements would otherwise become
+// a dynamically indexed register array).
+template <int I, int H, int O>
+struct HalveStep {
+  static __device__ __forceinline__ void run(float (&v)[16], bool up) {
+    const float lo = v[I], hi = v[I + H];
+    const float send = up ? lo : hi;
+    const float keep = up ? hi : lo;
+    v[I] = keep + __shfl_xor(send, O, 64);
+    HalveStep<I + 1, H, O>::run(v, up);
+  }
+};
+template <int H, int O>
+struct HalveStep<H, H, O> {
+  static __device__ __forceinline__ void run(float (&)[16], bool) {}
+};
+
 __device__ __forceinline__ float wave_sum16(float (&v)[16]) {
   const int lane = threadIdx.x;
-#pragma unroll
-  for (int h = 8, o = 32; h >= 1; h >>= 1, o >>= 1) {
-    const bool up = lane & o;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const float send = up ? v[i] : v[i + h];
-      const float keep = up ? v[i + h] : v[i];
-      v[i] = keep + __shfl_xor(send, o, 64);
-    }
-  }
+  HalveStep<0, 8, 32>::run(v, lane & 32);
+  HalveStep<0, 4, 16>::run(v, lane & 16);
+  HalveStep<0, 2, 8>::run(v, lane & 8);
+  HalveStep<0, 1, 4>::run(v, lane & 4);
   float r = v[0];
   r += __shfl_xor(r, 2, 64);
   r += __shfl_xor(r, 1, 64);
@@ -537,6 +548,8 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
       tk = now;
     }
   };
+  long long* dg = a.diag + (size_t)blockIdx.x * D_NUM;
+  if (diag && threadIdx.x >= D_BWD_SETUP && threadIdx.x <= D_BWD_TICKS) dg[threadIdx.x] = 0;
   ItemCtx c;
   const int st = item_setup(a, blockIdx.x, c);
   if (st == 2) return;
@@ -706,10 +719,10 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
     mark(3);
   }
   if (diag && lane == 0) {
-    atomicMax((unsigned long long*)&a.counters[C_BT_MAX], ph[0] + ph[1] + ph[2] + ph[3]);
-    for (int i = 0; i < 4; ++i) atomicAdd((unsigned long long*)&a.counters[C_BT_SETUP + i], ph[i]);
-    atomicAdd((unsigned long long*)&a.counters[C_BG_CAND], ncand);
-    atomicAdd((unsigned long long*)&a.counters[C_BG_GROUPS], ngrp);
+    for (int i = 0; i < 4; ++i) dg[D_BWD_SETUP + i] = (long long)ph[i];
+    dg[D_BWD_CAND] = (long long)ncand;
+    dg[D_BWD_GROUPS] = (long long)ngrp;
+    dg[D_BWD_TICKS] = (long long)(ph[0] + ph[1] + ph[2] + ph[3]);
   }
 }
 
@@ -828,6 +841,7 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
   a.tau = prm->tau; a.z_near = prm->z_near; a.M = prm->M; a.mode = prm->weight_mode;
   a.flags = prm->flags; a.two_sided = prm->two_sided;
   a.counters = (long long*)(base + L->region[R_COUNTERS]);
+  a.diag = (long long*)(base + L->region[R_DIAG]);
   a.partial = (float*)(base + L->region[R_PARTIAL]);
   a.max_sub = L->max_sub;
   return PS_OK;

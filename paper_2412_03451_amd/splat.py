@@ -219,6 +219,14 @@ class Renderer:
                     bwd_ticks_sort=out[14], bwd_ticks_grad=out[15], bwd_grad_candidates=out[16],
                     bwd_grad_groups=out[17], overflow_since_init=out[18], bwd_max_block_ticks=out[19])
 
+    def block_stats(self) -> torch.Tensor:
+        """Per-8x8-block statistics of the last renders run with diagnostics
+        [n_items, 16] int64: evals, commits, steps, forward ticks, backward
+        set-up / walk / sort / gradient ticks, gradient candidates and groups,
+        backward ticks (100 MHz ticks)."""
+        n = int(self.L.n_items)
+        return self.region(18, torch.int64, 16 * n).view(n, 16)
+
     # ------------------------------------------------------------------ image views
     def job_depth(self, depth, s):
         j = self.jobs[s]

@@ -451,6 +451,7 @@ struct BwdLds {
   float a[kChunk][64];    // a* of the hit
   float T[kChunk][64];    // transmittance in front of the hit
   float cg[kChunk][64];   // c_j, then dL/dw_j after the back-to-front walk
+  int16_t hpos[kMaxM][64];  // list positions of the committed hits, in commit order
   int gpos[64];           // a group of candidates of the gradient pass: list positions, ascending
   uint32_t vis[kBigSort / 32];  // list positions visited by the first gradient pass
 };
@@ -510,6 +511,7 @@ struct BwdSink {
     const float cv = pl[0];
     const int j = count - c0;
     const int lane = threadIdx.x;
+    L->hpos[count][lane] = (int16_t)pos;
     if (j >= 0 && j < kChunk) {
       L->pos[j][lane] = pos;
       L->a[j][lane] = as;
@@ -523,6 +525,41 @@ struct BwdSink {
     ++count;
   }
 };
+
+// Commit again, in the same order, the hits that the first pass's walk
+// committed (their list positions are in L.hpos): the same evaluation of the
+// same records gives the same bits, without walking the list again.
+__device__ inline void replay(const RenderArgs& a, const ItemCtx& c, BwdSink& s, int hits, bool one_batch,
+                              double delta) {
+  const int jmax = wave_max_int(hits);
+  const int lane = threadIdx.x;
+  for (int j = 0; j < jmax; ++j) {
+    if (j < hits) {
+      const int pos = s.L->hpos[j][lane];
+      RecHead rec;
+      float nrm[3];
+      if (one_batch) {
+        staged(*c.stage, pos, rec, nrm);
+      } else {
+        const float4* src = reinterpret_cast<const float4*>(&a.recs_s[c.b + pos]);
+        const float4 h0 = src[0], h1 = src[1], h2 = src[2], h3 = src[3], h4 = src[4], h5 = src[5], h6 = src[6];
+        rec.D0 = dbl(h0.x, h0.y); rec.Du = dbl(h0.z, h0.w);
+        rec.Dv = dbl(h1.x, h1.y); rec.X0 = dbl(h1.z, h1.w);
+        rec.Xu = dbl(h2.x, h2.y); rec.Xv = dbl(h2.z, h2.w);
+        rec.Y0 = dbl(h3.x, h3.y); rec.Yu = dbl(h3.z, h3.w);
+        rec.Yv = dbl(h4.x, h4.y); rec.h = dbl(h4.z, h4.w);
+        rec.rxp = h5.x; rec.rxm = h5.y; rec.ryp = h5.z; rec.rym = h5.w;
+        nrm[0] = h6.x; nrm[1] = h6.y; nrm[2] = h6.z;
+      }
+      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+      const float t32 = (float)g.t;
+      const float a32 = (float)g.a;
+      float pl[1];
+      s.payload(t32, nrm, pl);
+      s.commit(t32, a32, pos, pl);
+    }
+  }
+}
 
 __device__ inline void zero_row(const RenderArgs& a, uint32_t em, int sub) {
   float4* row = (float4*)(a.partial + ((size_t)em * a.max_sub + sub) * 16);
@@ -576,10 +613,16 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   const bool one_batch = n <= 64;
   mark(0);
   int passes = 1;
+  int hits = 0;   // hits committed by the first pass's walk
   for (int pass = 0; pass < passes; ++pass) {
     BwdSink s{1.f, 0, pass * kChunk, 1.f, 0.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
     long long evals = 0, steps = 0;
-    walk<P>(a, c, s, lam5, delta, evals, steps);
+    if (pass == 0) {
+      walk<P>(a, c, s, lam5, delta, evals, steps);
+      hits = s.count;
+    } else {
+      replay(a, c, s, hits, one_batch, delta);
+    }
     if (pass == 0) {
       const int jmax = wave_max_int(s.count);
       passes = (jmax + kChunk - 1) / kChunk;

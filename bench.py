@@ -90,6 +90,40 @@ def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
     }
 
 
+KERNEL_SOURCES = ("paper_2412_03451_amd/csrc/render.hip", "paper_2412_03451_amd/csrc/ps_internal.h")
+TRAFFIC_FILES = {"fwd": "profiles/render_fwd_room640_hbm_traffic.txt",
+                 "bwd": "profiles/render_bwd_room640_hbm_traffic.txt"}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(phase: str):
+    """HBM bytes per launch of the render kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, TRAFFIC_FILES[phase])
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +138,8 @@ def main():
                     help="send every pixel through the exact round-based ordering path")
     ap.add_argument("--phase-steps", type=int, default=50,
                     help="eager steps timed phase by phase (per-kernel durations)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -115,6 +151,13 @@ def main():
     import torch
     from paper_2412_03451_amd.fit import FitConfig, SceneFit
     from paper_2412_03451_amd.splat import Job, Renderer, SplatParams
+
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     n_views = 100
     V = args.views
@@ -194,6 +237,7 @@ def main():
     dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
     per_hit = FLOPS_FWD_PER_HIT if dom == "fwd" else FLOPS_BWD_PER_HIT
     achieved = hits * per_hit / (phase_ms[dom] * 1e-3) / 1e12
+    traffic = measured_traffic(dom)
     roof = {
         "kernel": "render_fwd_kernel" if dom == "fwd" else "render_bwd_kernel+bwd_reduce_kernel",
         "bound": "alu",
@@ -201,7 +245,7 @@ def main():
         "peak": MI355X_FP64_VECTOR_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / MI355X_FP64_VECTOR_TFLOPS, 5),
-        "traffic": None,
+        "traffic": traffic,
         "launch_ms": round(phase_ms[dom], 4),
         "algorithmic_units": f"{hits} composited hits x {per_hit} flops",
         "pairs_evaluated": evals,

@@ -176,3 +176,22 @@ def nearest(D):
     m = D.detach().min(dim=0).values
     idx = torch.arange(P)[:, None].expand_as(D)
     return torch.where(D.detach() == m[None, :], idx, torch.full_like(idx, P)).min(dim=0).values
+
+
+def grads_given_arg(X, prm, arg, d_out):
+    """Gradient of sum(d_out * out) with respect to every parameter, with the
+    pooled point of each channel fixed to arg [B, C] (the forward's choice).
+    Returns a dict of float64 tensors shaped like prm."""
+    p = {k: v.detach().clone().requires_grad_(True) for k, v in prm.items()}
+    X = torch.as_tensor(X).to(F64)
+    pre1 = X @ p["W1"] + p["b1"]
+    h1 = _bf16_st(torch.relu(pre1))
+    pre2 = h1 @ p["W2"] + p["b2"]
+    h2 = _bf16_st(torch.relu(pre2))
+    pre3 = h2 @ p["W3"] + p["b3"]
+    h3 = _bf16_st(torch.relu(pre3))
+    arg = torch.as_tensor(arg).to(torch.int64)
+    g = torch.gather(h3, 1, arg[:, None, :]).squeeze(1)
+    out = g @ p["Wh"] + p["bh"]
+    (out * torch.as_tensor(d_out).to(F64)).sum().backward()
+    return {k: v.grad.detach() for k, v in p.items()}

@@ -69,6 +69,15 @@ _EXPORTS = {
     "adam_step_planes": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, C.c_int, _P, C.c_float, C.c_float,
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
     "ps_fit_schedule": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, C.c_int, _P, _P, _P]),
+    "initnet_param_count": (C.c_int64, [C.c_int]),
+    "initnet_packed_count": (C.c_int64, [C.c_int]),
+    "initnet_forward_ws": (C.c_int64, [C.c_int, C.c_int]),
+    "initnet_backward_ws": (C.c_int64, [C.c_int, C.c_int]),
+    "initnet_pack": (C.c_int, [_P, C.c_int, _P, _P]),
+    "initnet_forward": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P]),
+    "initnet_set_loss": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
+    "initnet_backward": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P]),
+    "initnet_adam": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
     "ps_read_counters": (C.c_int, [C.POINTER(PsLayout), _P, C.POINTER(C.c_int64), _P]),
     "ps_last_error": (C.c_char_p, []),
 }

@@ -297,18 +297,26 @@ class BatchFit:
         return D.view(H, W), N.view(3, H, W)
 
     def depth_l1(self, scene: int = 0, views=None, lam: float | None = None) -> float:
-        """Mean |D - D^| over the pixels of the given views of a scene (all by default)."""
+        """Mean |D - D^| over the pixels of the given views of a scene (all by
+        default), every view rendered in one batch."""
         W, H = self.size[scene]
         V = self.v_off[scene + 1] - self.v_off[scene]
-        views = range(V) if views is None else views
-        tot, n = 0.0, 0
-        for vi in views:
-            D, _ = self.render_view(vi, scene, lam)
-            o = int(self.tgt_off[self.v_off[scene] + vi].item())
-            Dt = self.tgt_depth[o:o + W * H].view(H, W)
-            tot += float((D - Dt).abs().sum().item())
-            n += W * H
-        return tot / max(n, 1)
+        views = list(range(V)) if views is None else list(views)
+        a, b = int(self.k_off[scene]), int(self.k_off[scene + 1])
+        tile = tuple(self.scenes[scene].tile or self.cfg.tile)
+        key = (scene, tuple(views))
+        cache = getattr(self, "_eval", {})
+        if key not in cache:
+            cache[key] = Renderer([Job(a, b, self.v_off[scene] + v, W, H, tile) for v in views], self.rend.cams,
+                                  device=self.device, pair_capacity=self.rend.L.pair_capacity * len(views),
+                                  params=self.params)
+            self._eval = cache
+        r = cache[key]
+        lt = torch.tensor([lam if lam is not None else float(self.lam.item())], device=self.device)
+        D, _ = r.render(self.c, self.q, self.r, lt)
+        offs = [int(self.tgt_off[self.v_off[scene] + v].item()) for v in views]
+        Dt = torch.cat([self.tgt_depth[o:o + W * H] for o in offs])
+        return float((D - Dt).abs().mean().item())
 
 
 class SceneFit(BatchFit):

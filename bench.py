@@ -124,6 +124,102 @@ def measured_traffic(phase: str):
         return None
 
 
+def scene_fit_bench(args):
+    """Held-out synthetic rooms (K ~ 500 planes, 20 views of 320 x 240,
+    f = 288.5): each is fitted alone from its noisy initialisation for
+    --fit-iters iterations; its depth L1 after that is its target.  Then all
+    rooms are fitted together in one batched fit from the learned
+    initialisation until every room reaches its target.  Wall-times exclude
+    the depth-L1 checks (taken every 50 iterations); the batched side includes
+    the initialisation's inference.  The initializer is trained first on
+    rooms fitted by the plain method (time reported, not counted)."""
+    import torch
+    import synth
+    from paper_2412_03451_amd import learned_init as li
+    from paper_2412_03451_amd.fit import BatchFit, FitConfig, Scene
+    from paper_2412_03451_amd.initnet import InitNet
+
+    W, H, F, K, V = 320, 240, 288.5, 500, 20
+
+    def room(seed):
+        gt, info = synth.room_planes(seed=seed, target_K=K)
+        cams = synth.room_trajectory(seed, V, info, width=W, height=H, f=F)
+        return {"gt": gt, "init": synth.room_init_planes(gt, seed=seed + 7919), "cams": cams}
+
+    t0 = time.perf_counter()
+    train_rooms = [room(1000 + i) for i in range(args.train_rooms)]
+    fitted = []
+    for s in range(0, len(train_rooms), 16):
+        fitted += li.fit_rooms(train_rooms[s:s + 16], 1500)
+    data = li.training_planes(train_rooms, fitted)
+    net = InitNet(1, seed=0)
+    li.train_planes(net, data, 1500, batch=256, lr=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"initializer trained on {data.X.shape[0]} planes of {len(train_rooms)} rooms in {train_s:.1f} s")
+
+    rooms = [room(5000 + i) for i in range(args.rooms)]
+    for rm in rooms:
+        rm["tD"], rm["tN"] = li.render_targets((rm["gt"].center, rm["gt"].quat, rm["gt"].radii), rm["cams"])
+    # plain: one fit per room
+    plain_s, targets = 0.0, []
+    for i, rm in enumerate(rooms):
+        init = (rm["init"].center, rm["init"].quat, rm["init"].radii)
+        fit = BatchFit([Scene(*init, rm["cams"], rm["tD"], rm["tN"])], cfg=FitConfig(check_every=250))
+        fit.size_capacity()
+        fit.run(1, graph=True)       # capture outside the timed region
+        fit.restore([torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda") for x in init]
+                    + [torch.zeros_like(fit.m), torch.zeros_like(fit.v), torch.zeros_like(fit.ite)])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fit.run(args.fit_iters, graph=True)
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t1
+        targets.append(fit.depth_l1(0, lam=300.0))
+    log(f"plain: {len(rooms)} fits of {args.fit_iters} iterations in {plain_s:.2f} s")
+    # batched + learned initialisation
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    scenes, used = [], 0
+    for rm in rooms:
+        init = (rm["init"].center, rm["init"].quat, rm["init"].radii)
+        planes, info = li.learned_init(net, init, rm["cams"], rm["tD"])
+        used += info["used"] == "learned"
+        scenes.append(Scene(*planes, rm["cams"], rm["tD"], rm["tN"]))
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t1
+    fit = BatchFit(scenes, cfg=FitConfig(check_every=50))
+    fit.size_capacity()
+    done_at = [None] * len(rooms)
+    batched_s, its = 0.0, 0
+    while its < args.fit_iters * 2 and any(d is None for d in done_at):
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fit.run(50, graph=True)
+        torch.cuda.synchronize()
+        batched_s += time.perf_counter() - t2
+        its += 50
+        for i in range(len(rooms)):
+            if done_at[i] is None and fit.depth_l1(i, lam=300.0) <= targets[i]:
+                done_at[i] = its
+    reached = sum(d is not None for d in done_at)
+    total = init_s + batched_s
+    return {
+        "metric": "scene-fit wall-time at equal depth L1, batched+init vs plain",
+        "value": round(plain_s / total, 3), "unit": "x (plain seconds / batched+init seconds)",
+        "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "f32 (f64 ray-plane geometry)",
+        "config": {"workload": f"{len(rooms)} held-out rooms, K~{K}, {V} views of {W}x{H}, plain fits of "
+                               f"{args.fit_iters} iterations set each room's depth-L1 target",
+                   "rooms": len(rooms)},
+        "plain_seconds": round(plain_s, 3), "batched_init_seconds": round(total, 3),
+        "learned_init_seconds": round(init_s, 3), "batched_fit_seconds": round(batched_s, 3),
+        "rooms_reaching_target": reached, "batched_iterations": its,
+        "iterations_to_target": done_at, "learned_init_used": used,
+        "target_depth_l1_mean": round(float(np.mean(targets)), 5),
+        "initializer_training_seconds": round(train_s, 1), "initializer_training_planes": int(data.X.shape[0]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +236,12 @@ def main():
                     help="eager steps timed phase by phase (per-kernel durations)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--workload", default="room", choices=("room", "scene-fit"),
+                    help="room: the fitting-step throughput (default); scene-fit: wall-time of plain fits "
+                         "against batched fits from the learned initialisation at equal depth L1")
+    ap.add_argument("--rooms", type=int, default=32, help="scene-fit: held-out rooms")
+    ap.add_argument("--train-rooms", type=int, default=64, help="scene-fit: rooms fitted to train the initializer")
+    ap.add_argument("--fit-iters", type=int, default=2000, help="scene-fit: iterations of the plain fits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -151,6 +253,10 @@ def main():
     import torch
     from paper_2412_03451_amd.fit import FitConfig, SceneFit
     from paper_2412_03451_amd.splat import Job, Renderer, SplatParams
+
+    if args.workload == "scene-fit":
+        print(json.dumps(scene_fit_bench(args)), flush=True)
+        return
 
     if args.copy_mb > 0:
         src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")

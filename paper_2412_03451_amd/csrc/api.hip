@@ -87,6 +87,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
       sizeof(ps::ItemDesc) * ((size_t)items + 1),  // R_ITEMS
       sizeof(ps::Rec) * C,             // R_RECS_S
       8 * ps::D_NUM * ((size_t)items + 1),  // R_DIAG
+      4 * (T + 1),                     // R_TILEPOS
   };
   size_t off = 0;
   for (int i = 0; i < PS_NUM_REGIONS; ++i) {

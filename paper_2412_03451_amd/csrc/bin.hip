@@ -49,6 +49,7 @@ struct BinArgs {
   long long capacity;
   Rec* recs_s;        // record copies in sorted order
   ItemDesc* items;
+  int* tile_pos;      // first render item of each tile
 };
 
 __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot& sl, int tx, int ty,
@@ -173,9 +174,34 @@ __device__ long long block_scan(const int* __restrict__ in, int* __restrict__ ou
 
 __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   __shared__ int lds[40];
+  __shared__ int hist[kBuckets];
   int mx_t = 0, mx_r = 0;
   const long long total = block_scan(a.tile_cnt, a.tile_off, a.T, lds, mx_t);
   block_scan(a.rec_cnt, a.rec_off, a.R, lds, mx_r);
+  // items per list-length bucket, then the first position of each bucket
+  // with the longest lists first
+  for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < a.T; t += blockDim.x) {
+    const ps_slot& sl = a.slots[find_slot_by_tile(a.slots, a.S, t)];
+    atomicAdd(&hist[length_bucket(a.tile_cnt[t])], (sl.tile_w >> 3) * (sl.tile_h >> 3));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int k = kBuckets - 1; k >= 0; --k) {
+      const int h = hist[k];
+      hist[k] = run;
+      run += h;
+    }
+  }
+  __syncthreads();
+  // each tile's items take consecutive positions in their bucket (the order
+  // of tiles inside a bucket does not matter: items are independent)
+  for (int t = threadIdx.x; t < a.T; t += blockDim.x) {
+    const ps_slot& sl = a.slots[find_slot_by_tile(a.slots, a.S, t)];
+    a.tile_pos[t] = atomicAdd(&hist[length_bucket(a.tile_cnt[t])], (sl.tile_w >> 3) * (sl.tile_h >> 3));
+  }
   // scatter cursors, big-tile list
   __shared__ int nbig;
   if (threadIdx.x == 0) nbig = 0;
@@ -283,7 +309,7 @@ __global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
   const int t = blockIdx.x;
   const int n = a.tile_cnt[t];
   const int off = a.tile_off[t];
-  // render items (8x8 blocks) of this tile
+  // render items (8x8 blocks) of this tile, placed by list length
   if (threadIdx.x < 16) {
     const int s = find_slot_by_tile(a.slots, a.S, t);
     const ps_slot& sl = a.slots[s];
@@ -291,6 +317,7 @@ __global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
     const int sub_per = sub_w * (sl.tile_h >> 3);
     const int sub = threadIdx.x;
     if (sub < sub_per) {
+      const int pos = a.tile_pos[t] + sub;
       const int lt = t - sl.tile_begin;
       ItemDesc d;
       d.b = off;
@@ -303,7 +330,7 @@ __global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
       d.sub = (int16_t)sub;
       d.pad = 0;
       d.pix_off = sl.pix_off;
-      a.items[sl.item_begin + lt * sub_per + sub] = d;
+      a.items[pos] = d;
     }
   }
   if (a.counters[C_OVERFLOW]) return;
@@ -354,6 +381,7 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   a.capacity = L->pair_capacity;
   a.recs_s = (Rec*)(base + L->region[R_RECS_S]);
   a.items = (ItemDesc*)(base + L->region[R_ITEMS]);
+  a.tile_pos = (int*)(base + L->region[R_TILEPOS]);
   hipLaunchKernelGGL(ps_fill_i32, dim3((a.T + 1 + 255) / 256), dim3(256), 0, st, a.tile_cnt,
                      (int64_t)a.T + 1, 0);
   if (a.R > 0)

@@ -91,8 +91,13 @@ enum Region {
   R_ITEMS,       // ItemDesc[n_items]  per 8x8 block: list range, pixel origin, camera
   R_RECS_S,      // Rec[C]       record copies in tile-list order
   R_DIAG,        // int64[n_items][16]  per-block walk statistics (flags bit 6)
+  R_TILEPOS,     // int[T]       first render item of each tile (longest lists first)
   R_NUM_USED     // further regions are reserved (size 0)
 };
+// Render items are placed longest tile list first (buckets of list length),
+// so the blocks that take longest start first.
+constexpr int kBuckets = 1024;
+__host__ __device__ inline int length_bucket(int n) { return n >> 2 < kBuckets - 1 ? n >> 2 : kBuckets - 1; }
 // per-block statistics slots of R_DIAG
 enum DiagSlot {
   D_EVALS = 0, D_COMMITS, D_STEPS, D_FWD_TICKS,

@@ -124,6 +124,64 @@ def measured_traffic(phase: str):
         return None
 
 
+def memory_bench(args):
+    """Peak device memory of one forward + backward through the autograd
+    front end on a large room (K ~ 20000 planes, one 1296 x 968 view,
+    f = 1168.4): the recompute backward against the list-storing variant
+    (M = 30 entries of list position, a* and transmittance per pixel)."""
+    import torch
+    import synth
+    from paper_2412_03451_amd.autograd import PlaneSplatFn, PlaneSplatListsFn
+    from paper_2412_03451_amd.splat import Job, Renderer
+
+    gt, info = synth.room_planes(seed=0, target_K=20000)
+    init = synth.room_init_planes(gt, seed=1)
+    cams = synth.room_trajectory(seed=0, n_views=4, info=info, width=1296, height=968, f=577.0 * 1296 / 640)
+    cam = cams[1]
+    dev = torch.device("cuda")
+
+    def T(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+
+    lam = torch.tensor([7.3576], device=dev)
+    out = {"metric": "peak device memory of forward+backward, recompute vs stored per-pixel lists",
+           "unit": "MiB", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"room, K={gt.K} planes, one 1296x968 view, lambda(0)", "planes": gt.K}}
+    res = {}
+    # pair lists sized for this view (the binning grows the workspace to 1.5x the need)
+    probe = Renderer([Job(0, gt.K, 0, cam.width, cam.height, (16, 16))], [cam])
+    probe.project(T(init.center), T(init.quat), T(init.radii), lam)
+    probe.bin()
+    cap = int(probe.L.pair_capacity)
+    del probe
+    for name, fn in (("recompute", PlaneSplatFn), ("stored_lists", PlaneSplatListsFn)):
+        for rep in range(2):   # the first pass loads the kernels; the second is measured
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats()
+            base = torch.cuda.memory_allocated()
+            r = Renderer([Job(0, gt.K, 0, cam.width, cam.height, (16, 16))], [cam], pair_capacity=cap)
+            c, q, rr = (T(x).requires_grad_(True) for x in (init.center, init.quat, init.radii))
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            D, N = fn.apply(c, q, rr, lam, r)
+            ev[1].record()
+            (D.sum() + N.sum()).backward()
+            ev[2].record()
+            torch.cuda.synchronize()
+            peak = torch.cuda.max_memory_allocated() - base
+            res[name] = {"peak_mib": round(peak / 2**20, 1), "workspace_mib": round(r.ws.numel() / 2**20, 1),
+                         "pairs": int(r.last_pairs), "pair_capacity": cap,
+                         "fwd_ms": round(ev[0].elapsed_time(ev[1]), 3), "bwd_ms": round(ev[1].elapsed_time(ev[2]), 3),
+                         "grad_center_sum": float(c.grad.double().abs().sum())}
+            del r, D, N, c, q, rr
+    out.update(res)
+    out["value"] = res["stored_lists"]["peak_mib"]
+    out["ratio_stored_over_recompute"] = round(res["stored_lists"]["peak_mib"] / res["recompute"]["peak_mib"], 3)
+    out["same_gradient"] = res["recompute"]["grad_center_sum"] == res["stored_lists"]["grad_center_sum"]
+    return out
+
+
 def scene_fit_bench(args):
     """Held-out synthetic rooms (K ~ 500 planes, 20 views of 320 x 240,
     f = 288.5): each is fitted alone from its noisy initialisation for
@@ -236,7 +294,7 @@ def main():
                     help="eager steps timed phase by phase (per-kernel durations)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
-    ap.add_argument("--workload", default="room", choices=("room", "scene-fit"),
+    ap.add_argument("--workload", default="room", choices=("room", "scene-fit", "memory"),
                     help="room: the fitting-step throughput (default); scene-fit: wall-time of plain fits "
                          "against batched fits from the learned initialisation at equal depth L1")
     ap.add_argument("--rooms", type=int, default=32, help="scene-fit: held-out rooms")
@@ -256,6 +314,9 @@ def main():
 
     if args.workload == "scene-fit":
         print(json.dumps(scene_fit_bench(args)), flush=True)
+        return
+    if args.workload == "memory":
+        print(json.dumps(memory_bench(args)), flush=True)
         return
 
     if args.copy_mb > 0:

@@ -131,6 +131,25 @@ int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void* ws, void* 
  * (device int array of n_slots), for captured fitting steps. */
 int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_of_slot, void* stream);
 
+/* The list-storing variant of the render pair, kept to compare memory with
+ * the recompute backward above (it is not used by the fitting loop).
+ * plane_render_fwd_lists renders like plane_render_fwd and also stores, for
+ * every pixel p and committed hit j < M, list_pos[j * n_pixels + p] (the
+ * hit's position in its tile list), list_a[...] (its a*) and list_T[...]
+ * (transmittance in front of it), and list_count[p] (device buffers of
+ * M * n_pixels int32 / float / float and n_pixels int32; entries j >=
+ * list_count[p] are left untouched).  plane_render_bwd_lists computes the
+ * gradients of plane_render_bwd from those lists instead of recomputing each
+ * pixel's sequence; it needs the workspace of the same tile_bin. */
+int plane_render_fwd_lists(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,
+                           const float* lambda, const ps_params* prm, float* depth, float* normal,
+                           int32_t* list_pos, float* list_a, float* list_T, int32_t* list_count, void* stream);
+int plane_render_bwd_lists(const ps_layout* L, void* ws, const float* center, const float* quat,
+                           const float* radii, int K, const ps_camera* cams, int n_cams, const float* lambda,
+                           const ps_params* prm, const float* g_depth, const float* g_normal,
+                           const int32_t* list_pos, const float* list_a, const int32_t* list_count,
+                           float* g_center, float* g_quat, float* g_radii, void* stream);
+
 /* Device-side bookkeeping of one iteration of the fitting loop (Sec. 3.3,
  * Eq. 10), so that whole steps can be captured in a graph and replayed with
  * no host work.  Reads the iteration counter *ite (device int32, 0-based),

@@ -68,6 +68,10 @@ _EXPORTS = {
                                    C.POINTER(PsParams), _P, _P, _P, _P, _P, _P]),
     "adam_step_planes": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, C.c_int, _P, C.c_float, C.c_float,
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
+    "plane_render_fwd_lists": (C.c_int, [C.POINTER(PsLayout), _P, _P, C.c_int, _P, C.POINTER(PsParams), _P, _P, _P,
+                                         _P, _P, _P, _P]),
+    "plane_render_bwd_lists": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,
+                                         C.POINTER(PsParams), _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ps_fit_schedule": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, C.c_int, _P, _P, _P]),
     "initnet_param_count": (C.c_int64, [C.c_int]),
     "initnet_packed_count": (C.c_int64, [C.c_int]),

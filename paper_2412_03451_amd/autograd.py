@@ -47,6 +47,38 @@ class PlaneSplatFn(torch.autograd.Function):
         return gc, gq, gr, None, None
 
 
+class PlaneSplatListsFn(torch.autograd.Function):
+    """The list-storing variant: the forward keeps each pixel's committed
+    hits (list position, a*, transmittance; M entries per pixel) for the
+    backward.  Same values and gradients as PlaneSplatFn; kept for the memory
+    comparison."""
+
+    @staticmethod
+    def forward(ctx, center, quat, radii, lam, renderer: Renderer):
+        center, quat, radii = center.contiguous(), quat.contiguous(), radii.contiguous()
+        renderer.project(center, quat, radii, lam)
+        renderer.bin()
+        D, N, lists = renderer.forward_lists()
+        ctx.renderer = renderer
+        ctx.generation = renderer.generation
+        ctx.save_for_backward(center, quat, radii, lam, *lists)
+        return D, N
+
+    @staticmethod
+    def backward(ctx, gD, gN):
+        center, quat, radii, lam, pos, a, T, cnt = ctx.saved_tensors
+        r: Renderer = ctx.renderer
+        if r.generation != ctx.generation:
+            r.project(center, quat, radii, lam)
+            r.bin()
+        if gD is None:
+            gD = torch.zeros(r.n_pixels, dtype=torch.float32, device=center.device)
+        if gN is None:
+            gN = torch.zeros(3 * r.n_pixels, dtype=torch.float32, device=center.device)
+        gc, gq, gr = r.backward_lists(center, quat, radii, lam, gD.contiguous(), gN.contiguous(), (pos, a, T, cnt))
+        return gc, gq, gr, None, None
+
+
 def plane_splat(center, quat, radii, lam, renderer: Renderer):
     """Differentiable render of the renderer's jobs; see PlaneSplatFn."""
     if not torch.is_tensor(lam):

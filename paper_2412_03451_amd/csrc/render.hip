@@ -53,6 +53,12 @@ struct RenderArgs {
   float* normal;
   float* trans;      // optional: final transmittance per pixel
   int32_t* count;    // optional: committed hits per pixel
+  // stored per-pixel lists [M][n_pixels] (the list-storing variant): list
+  // position, a* and transmittance in front of each committed hit
+  int32_t* lst_pos;
+  float* lst_a;
+  float* lst_T;
+  int64_t lst_stride;
   const float* g_depth;
   const float* g_normal;
   float* partial;
@@ -388,11 +394,19 @@ struct FwdSink {
   int count;
   float lam5;
   int mode;
+  const RenderArgs* args;   // list storage (lst_pos non-null) and the lane's pixel
+  int64_t pix;
   __device__ bool finished(int M) const { return T == 0.f || count >= M; }
   __device__ void payload(float, const float n[3], float* pl) const {
     pl[0] = n[0]; pl[1] = n[1]; pl[2] = n[2];
   }
-  __device__ void commit(float t, float as, int, const float* n) {
+  __device__ void commit(float t, float as, int pos, const float* n) {
+    if (args->lst_pos) {
+      const int64_t o = (int64_t)count * args->lst_stride + pix;
+      args->lst_pos[o] = pos;
+      args->lst_a[o] = as;
+      args->lst_T[o] = T;
+    }
     float omw;
     const float w = splat_weight(as, lam5, mode, omw);
     const float Tw = T * w;
@@ -419,7 +433,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
   const double delta = fringe_margin((double)lam, (double)a.tau, a.mode);
-  FwdSink s{1.f, 0.f, 0.f, 0.f, 0.f, 0, lam5, a.mode};
+  FwdSink s{1.f, 0.f, 0.f, 0.f, 0.f, 0, lam5, a.mode, &a, c.pix};
   long long evals = 0, steps = 0;
   walk<P>(a, c, s, lam5, delta, evals, steps);
   if (diag) {
@@ -561,6 +575,39 @@ __device__ inline void replay(const RenderArgs& a, const ItemCtx& c, BwdSink& s,
   }
 }
 
+// The list-storing variant: commit the hits the forward stored for this
+// pixel (list position and a*), recomputing only the depth and normal of each.
+__device__ inline void load_lists(const RenderArgs& a, const ItemCtx& c, BwdSink& s, int hits, bool one_batch,
+                                  double delta) {
+  const int jmax = wave_max_int(hits);
+  for (int j = 0; j < jmax; ++j) {
+    if (j < hits) {
+      const int64_t o = (int64_t)j * a.lst_stride + c.pix;
+      const int pos = a.lst_pos[o];
+      const float as = a.lst_a[o];
+      RecHead rec;
+      float nrm[3];
+      if (one_batch) {
+        staged(*c.stage, pos, rec, nrm);
+      } else {
+        const float4* src = reinterpret_cast<const float4*>(&a.recs_s[c.b + pos]);
+        const float4 h0 = src[0], h1 = src[1], h2 = src[2], h3 = src[3], h4 = src[4], h5 = src[5], h6 = src[6];
+        rec.D0 = dbl(h0.x, h0.y); rec.Du = dbl(h0.z, h0.w);
+        rec.Dv = dbl(h1.x, h1.y); rec.X0 = dbl(h1.z, h1.w);
+        rec.Xu = dbl(h2.x, h2.y); rec.Xv = dbl(h2.z, h2.w);
+        rec.Y0 = dbl(h3.x, h3.y); rec.Yu = dbl(h3.z, h3.w);
+        rec.Yv = dbl(h4.x, h4.y); rec.h = dbl(h4.z, h4.w);
+        rec.rxp = h5.x; rec.rxm = h5.y; rec.ryp = h5.z; rec.rym = h5.w;
+        nrm[0] = h6.x; nrm[1] = h6.y; nrm[2] = h6.z;
+      }
+      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+      float pl[1];
+      s.payload((float)g.t, nrm, pl);
+      s.commit((float)g.t, as, pos, pl);
+    }
+  }
+}
+
 __device__ inline void zero_row(const RenderArgs& a, uint32_t em, int sub) {
   float4* row = (float4*)(a.partial + ((size_t)em * a.max_sub + sub) * 16);
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -617,7 +664,13 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   for (int pass = 0; pass < passes; ++pass) {
     BwdSink s{1.f, 0, pass * kChunk, 1.f, 0.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
     long long evals = 0, steps = 0;
-    if (pass == 0) {
+    if (pass == 0 && a.lst_pos) {
+      // no walk: stage the first batch here (record heads, emit indices),
+      // which the one-batch paths below read from LDS
+      if (n > 0) stage_batch<true>(a, c, c.b);
+      hits = c.inimg ? a.count[c.pix] : 0;
+      load_lists(a, c, s, hits, one_batch, delta);
+    } else if (pass == 0) {
       walk<P>(a, c, s, lam5, delta, evals, steps);
       hits = s.count;
     } else {
@@ -892,17 +945,7 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
 
 }  // namespace
 
-extern "C" int plane_render_fwd(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,
-                                const float* lambda, const ps_params* prm, float* depth, float* normal,
-                                float* trans, int32_t* count, void* stream) {
-  RenderArgs a;
-  int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, "plane_render_fwd");
-  if (rc) return rc;
-  if (!depth || !normal) return ps_set_error(PS_ERR_INVALID, "plane_render_fwd: null output");
-  a.depth = depth;
-  a.normal = normal;
-  a.trans = trans;
-  a.count = count;
+static int launch_fwd(RenderArgs& a, void* stream) {
   if (a.n_items == 0) return PS_OK;
   switch (pending_of(a.flags)) {
     case 4: hipLaunchKernelGGL(render_fwd_kernel<4>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
@@ -914,20 +957,7 @@ extern "C" int plane_render_fwd(const ps_layout* L, void* ws, const ps_camera* c
   return PS_OK;
 }
 
-extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const float* quat,
-                                const float* radii, int K, const ps_camera* cams, int n_cams,
-                                const float* lambda, const ps_params* prm, const float* g_depth,
-                                const float* g_normal, float* g_center, float* g_quat, float* g_radii,
-                                void* stream) {
-  RenderArgs a;
-  int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, "plane_render_bwd");
-  if (rc) return rc;
-  if (!center || !quat || !radii || !g_depth || !g_normal || !g_center || !g_quat || !g_radii)
-    return ps_set_error(PS_ERR_INVALID, "plane_render_bwd: null pointer");
-  if (K < L->n_planes) return ps_set_error(PS_ERR_INVALID, "plane_render_bwd: K=%d < planes referenced %d", K, L->n_planes);
-  a.g_depth = g_depth; a.g_normal = g_normal;
-  a.center = center; a.quat = quat; a.K = K;
-  a.g_center = g_center; a.g_quat = g_quat; a.g_radii = g_radii;
+static int launch_bwd(RenderArgs& a, int K, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (a.n_items > 0) {
     switch (pending_of(a.flags)) {
@@ -940,4 +970,80 @@ extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* cente
   if (K > 0) hipLaunchKernelGGL(bwd_reduce_kernel, dim3(K), dim3(64), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
+}
+
+static int bwd_args(const ps_layout* L, void* ws, const float* center, const float* quat, const float* radii, int K,
+                    const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm,
+                    const float* g_depth, const float* g_normal, float* g_center, float* g_quat, float* g_radii,
+                    RenderArgs& a, const char* who) {
+  int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, who);
+  if (rc) return rc;
+  if (!center || !quat || !radii || !g_depth || !g_normal || !g_center || !g_quat || !g_radii)
+    return ps_set_error(PS_ERR_INVALID, "%s: null pointer", who);
+  if (K < L->n_planes) return ps_set_error(PS_ERR_INVALID, "%s: K=%d < planes referenced %d", who, K, L->n_planes);
+  a.g_depth = g_depth; a.g_normal = g_normal;
+  a.center = center; a.quat = quat; a.K = K;
+  a.g_center = g_center; a.g_quat = g_quat; a.g_radii = g_radii;
+  return PS_OK;
+}
+
+extern "C" int plane_render_fwd(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,
+                                const float* lambda, const ps_params* prm, float* depth, float* normal,
+                                float* trans, int32_t* count, void* stream) {
+  RenderArgs a;
+  int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, "plane_render_fwd");
+  if (rc) return rc;
+  if (!depth || !normal) return ps_set_error(PS_ERR_INVALID, "plane_render_fwd: null output");
+  a.depth = depth;
+  a.normal = normal;
+  a.trans = trans;
+  a.count = count;
+  return launch_fwd(a, stream);
+}
+
+extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const float* quat,
+                                const float* radii, int K, const ps_camera* cams, int n_cams,
+                                const float* lambda, const ps_params* prm, const float* g_depth,
+                                const float* g_normal, float* g_center, float* g_quat, float* g_radii,
+                                void* stream) {
+  RenderArgs a;
+  int rc = bwd_args(L, ws, center, quat, radii, K, cams, n_cams, lambda, prm, g_depth, g_normal, g_center, g_quat,
+                    g_radii, a, "plane_render_bwd");
+  if (rc) return rc;
+  return launch_bwd(a, K, stream);
+}
+
+extern "C" int plane_render_fwd_lists(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,
+                                      const float* lambda, const ps_params* prm, float* depth, float* normal,
+                                      int32_t* list_pos, float* list_a, float* list_T, int32_t* list_count,
+                                      void* stream) {
+  RenderArgs a;
+  int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, "plane_render_fwd_lists");
+  if (rc) return rc;
+  if (!depth || !normal || !list_pos || !list_a || !list_T || !list_count)
+    return ps_set_error(PS_ERR_INVALID, "plane_render_fwd_lists: null pointer");
+  a.depth = depth;
+  a.normal = normal;
+  a.count = list_count;
+  a.lst_pos = list_pos; a.lst_a = list_a; a.lst_T = list_T;
+  a.lst_stride = L->n_pixels;
+  return launch_fwd(a, stream);
+}
+
+extern "C" int plane_render_bwd_lists(const ps_layout* L, void* ws, const float* center, const float* quat,
+                                      const float* radii, int K, const ps_camera* cams, int n_cams,
+                                      const float* lambda, const ps_params* prm, const float* g_depth,
+                                      const float* g_normal, const int32_t* list_pos, const float* list_a,
+                                      const int32_t* list_count, float* g_center, float* g_quat, float* g_radii,
+                                      void* stream) {
+  RenderArgs a;
+  int rc = bwd_args(L, ws, center, quat, radii, K, cams, n_cams, lambda, prm, g_depth, g_normal, g_center, g_quat,
+                    g_radii, a, "plane_render_bwd_lists");
+  if (rc) return rc;
+  if (!list_pos || !list_a || !list_count) return ps_set_error(PS_ERR_INVALID, "plane_render_bwd_lists: null list");
+  a.lst_pos = const_cast<int32_t*>(list_pos);
+  a.lst_a = const_cast<float*>(list_a);
+  a.count = const_cast<int32_t*>(list_count);
+  a.lst_stride = L->n_pixels;
+  return launch_bwd(a, K, stream);
 }

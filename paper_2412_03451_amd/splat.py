@@ -171,6 +171,38 @@ class Renderer:
             return depth, normal, trans, count
         return depth, normal
 
+    def forward_lists(self):
+        """Forward that also stores the per-pixel lists (list-storing
+        variant): depth, normal and (pos, a*, T) [M, n_pixels] plus count."""
+        M = int(self.params.M)
+        P = self.n_pixels
+        depth = torch.empty(P, dtype=torch.float32, device=self.device)
+        normal = torch.empty(3 * P, dtype=torch.float32, device=self.device)
+        pos = torch.empty(M, P, dtype=torch.int32, device=self.device)
+        a = torch.empty(M, P, dtype=torch.float32, device=self.device)
+        T = torch.empty(M, P, dtype=torch.float32, device=self.device)
+        cnt = torch.empty(P, dtype=torch.int32, device=self.device)
+        prm = self.params.c()
+        _, _, _, lam = self._inputs
+        check(self.lib.plane_render_fwd_lists(C.byref(self.L), _ptr(self.ws), _ptr(self.cams), self.n_cams, _ptr(lam),
+                                              C.byref(prm), _ptr(depth), _ptr(normal), _ptr(pos), _ptr(a), _ptr(T),
+                                              _ptr(cnt), _stream()))
+        return depth, normal, (pos, a, T, cnt)
+
+    def backward_lists(self, center, quat, radii, lam, g_depth, g_normal, lists):
+        """Gradients from the stored per-pixel lists (list-storing variant)."""
+        pos, a, _, cnt = lists
+        K = int(center.shape[0])
+        gc = torch.empty(K, 3, dtype=torch.float32, device=self.device)
+        gq = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        gr = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        prm = self.params.c()
+        check(self.lib.plane_render_bwd_lists(C.byref(self.L), _ptr(self.ws), _ptr(center), _ptr(quat), _ptr(radii), K,
+                                              _ptr(self.cams), self.n_cams, _ptr(lam), C.byref(prm),
+                                              _ptr(g_depth.contiguous()), _ptr(g_normal.contiguous()), _ptr(pos),
+                                              _ptr(a), _ptr(cnt), _ptr(gc), _ptr(gq), _ptr(gr), _stream()))
+        return gc, gq, gr
+
     def render(self, center, quat, radii, lam):
         self.project(center, quat, radii, lam)
         self.bin()

@@ -67,3 +67,33 @@ def test_loss_cam_matches_loss():
     l2, gD2, gN2 = r.loss_cam(_dev(D), _dev(N), _dev(tD.reshape(-1)), _dev(tN.reshape(-1)), off)
     torch.cuda.synchronize()
     assert torch.equal(l1, l2) and torch.equal(gD1, gD2) and torch.equal(gN1, gN2)
+
+
+@pytest.mark.parametrize("mode,lam", [(0, 30.0), (1, 8.0)])
+def test_list_storing_variant_gives_the_same_bits(mode, lam):
+    """Forward lists and list-reading backward equal the recompute path
+    (including lists longer than one recompute chunk in mode B)."""
+    from paper_2412_03451_amd.autograd import PlaneSplatFn, PlaneSplatListsFn
+    from paper_2412_03451_amd.splat import Renderer, SplatParams
+    if mode == 1:
+        ps = synth.random_planes(80, seed=4, center_range=0.3, extent_range=(0.4, 0.9))
+        cam = synth.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, np.eye(3, dtype=np.float32),
+                           np.array([0.0, 0.0, 3.0], np.float32))
+    else:
+        ps = synth.random_planes(64, seed=7, independent_radii=True)
+        cam = synth.tiny_camera()
+    rng = np.random.default_rng(9)
+    P = cam.width * cam.height
+    wD = _dev(rng.normal(size=P))
+    wN = _dev(rng.normal(size=3 * P))
+    lt = torch.tensor([f32(lam)], device="cuda")
+    res = []
+    for fn in (PlaneSplatFn, PlaneSplatListsFn):
+        r = Renderer.single_scene([cam], ps.K, params=SplatParams(weight_mode=mode))
+        c, q, rr = (_dev(x).requires_grad_(True) for x in (ps.center, ps.quat, ps.radii))
+        D, N = fn.apply(c, q, rr, lt, r)
+        ((D * wD).sum() + (N * wN).sum()).backward()
+        torch.cuda.synchronize()
+        res.append((D.detach().clone(), N.detach().clone(), c.grad.clone(), q.grad.clone(), rr.grad.clone()))
+    for x, y in zip(*res):
+        assert torch.equal(x, y)

@@ -124,6 +124,115 @@ def measured_traffic(phase: str):
         return None
 
 
+MI355X_BF16_DENSE_TFLOPS = 2500.0
+
+
+def initnet_bench(args):
+    """The learned initializer's network on a batch of 4096 planes x 128
+    depth samples (P = 1): forward (fused point layers on MFMA + head) and
+    backward, timed with events over --steps repetitions.  Algorithmic MFMA
+    work of the forward: 2 x 128 x 256 x 256 x 2 flops per 128 points."""
+    import torch
+    from paper_2412_03451_amd.initnet import InitNet
+    B, N = 4096, 128
+    rng = np.random.default_rng(0)
+    X = torch.tensor(np.stack([rng.uniform(-0.5, 0.5, (B, N)), rng.uniform(-0.5, 0.5, (B, N)),
+                               rng.normal(scale=0.05, size=(B, N))], -1).astype(np.float32), device="cuda")
+    net = InitNet(1, seed=0)
+    d_out = torch.tensor(rng.normal(size=(B, 12)).astype(np.float32), device="cuda")
+    for _ in range(3):
+        g, arg, out = net.forward(X)
+        net.backward(X, g, arg, d_out)
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    for _ in range(args.steps):
+        g, arg, out = net.forward(X)
+    ev[1].record(st)
+    for _ in range(args.steps):
+        net.backward(X, g, arg, d_out)
+    ev[2].record(st)
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    bwd_ms = ev[1].elapsed_time(ev[2]) / args.steps
+    fwd_flops = (B * N // 128) * 2 * 128 * 256 * 256 * 2
+    # backward MFMA work: dW2 (256 x B*256 x 256) and dh1 (B*256 x 256 x 256), plus the recomputed layer 2
+    bwd_flops = 3 * (B * 256) * 256 * 256 * 2
+    ach = fwd_flops / (fwd_ms * 1e-3) / 1e12
+    return {
+        "metric": "learned-initializer network throughput", "value": round(B * N / (fwd_ms * 1e-3) / 1e6, 1),
+        "unit": "Mpoints/s (forward)", "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
+        "dtype": "bf16 (f32 accumulate)", "data": "synthetic",
+        "config": {"workload": f"{B} planes x {N} depth samples, width 256, P=1"},
+        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+        "roofline": {"kernel": "initnet fwd_kernel + head_kernel", "bound": "mfma", "achieved": round(ach, 2),
+                     "peak": MI355X_BF16_DENSE_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / MI355X_BF16_DENSE_TFLOPS, 4)},
+        "backward_tflops": round(bwd_flops / (bwd_ms * 1e-3) / 1e12, 2),
+    }
+
+
+def batched_bench(args):
+    """Batched fitting step: --rooms synthetic rooms of uneven size (plane
+    counts log-uniform in [200, 4000], 20-100 views, 320x240 or 640x480),
+    every room advancing one iteration (one view) per step, all in one
+    graph-replayed step of one launch per phase.  Tile shapes per room from
+    the autotuner (tuned on the first room of each shape, cached).  Value:
+    sum over rooms of (pixels x planes) per second of step time."""
+    import torch
+    import synth
+    from paper_2412_03451_amd import learned_init as li
+    from paper_2412_03451_amd.autotune import Autotuner
+    from paper_2412_03451_amd.fit import BatchFit, FitConfig, Scene
+
+    specs = synth.room_batch_specs(args.rooms, seed=0)
+    tuner = Autotuner(os.path.join(ROOT, "_build", "tune.json")) if args.autotune else None
+    scenes, work = [], 0
+    for sp in specs:
+        gt, info = synth.room_planes(seed=sp["seed"], target_K=sp["K"])
+        init = synth.room_init_planes(gt, seed=sp["seed"] + 1)
+        cams = synth.room_trajectory(sp["seed"], sp["views"], info, width=sp["width"], height=sp["height"],
+                                     f=sp["f"])
+        tD, tN = li.render_targets((gt.center, gt.quat, gt.radii), cams)
+        sc = Scene(init.center, init.quat, init.radii, cams, tD, tN)
+        if tuner is not None:
+            tile, _ = tuner.tune(sc, steps=10, warmup=3)
+            sc.tile = tile
+        scenes.append(sc)
+        work += sp["width"] * sp["height"] * gt.K
+    log(f"{len(scenes)} rooms ready")
+    fit = BatchFit(scenes, cfg=FitConfig(check_every=max(1, args.warmup)))
+    fit.size_capacity()
+    start_state = fit.state()
+    fit.run(max(1, args.warmup), graph=True)
+    fit.restore(start_state)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(args.steps):
+        fit.graph.replay()
+    e1.record(st)
+    torch.cuda.synchronize()
+    if fit.overflowed():
+        raise RuntimeError("pair capacity exceeded during the timed batched steps")
+    ms = e0.elapsed_time(e1) / args.steps
+    tiles = {}
+    for sc in scenes:
+        k = f"{sc.tile[0]}x{sc.tile[1]}" if sc.tile else "16x16"
+        tiles[k] = tiles.get(k, 0) + 1
+    return {
+        "metric": "fwd+bwd Mpixel*planes/s (batched fitting step)", "value": round(work / (ms * 1e-3) / 1e6, 1),
+        "unit": "Mpixel*planes/s", "higher_is_better": True, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "dtype": "f32 (f64 ray-plane geometry)", "data": "synthetic",
+        "config": {"workload": f"{len(scenes)} rooms, K log-uniform 200-4000, 20-100 views, 320x240 or 640x480, "
+                               f"one view per room per step, lambda from ite 0", "rooms": len(scenes),
+                   "planes": int(fit.K), "pixels_per_step": int(fit.rend.n_pixels), "tiles": tiles,
+                   "pair_capacity": int(fit.rend.L.pair_capacity)},
+    }
+
+
 def memory_bench(args):
     """Peak device memory of one forward + backward through the autograd
     front end on a large room (K ~ 20000 planes, one 1296 x 968 view,
@@ -294,10 +403,11 @@ def main():
                     help="eager steps timed phase by phase (per-kernel durations)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
-    ap.add_argument("--workload", default="room", choices=("room", "scene-fit", "memory"),
+    ap.add_argument("--workload", default="room", choices=("room", "scene-fit", "memory", "batched", "initnet"),
                     help="room: the fitting-step throughput (default); scene-fit: wall-time of plain fits "
                          "against batched fits from the learned initialisation at equal depth L1")
-    ap.add_argument("--rooms", type=int, default=32, help="scene-fit: held-out rooms")
+    ap.add_argument("--rooms", type=int, default=32, help="scene-fit: held-out rooms; batched: rooms")
+    ap.add_argument("--autotune", action="store_true", help="batched: tile shape per room from the autotuner")
     ap.add_argument("--train-rooms", type=int, default=64, help="scene-fit: rooms fitted to train the initializer")
     ap.add_argument("--fit-iters", type=int, default=2000, help="scene-fit: iterations of the plain fits")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -317,6 +427,12 @@ def main():
         return
     if args.workload == "memory":
         print(json.dumps(memory_bench(args)), flush=True)
+        return
+    if args.workload == "batched":
+        print(json.dumps(batched_bench(args)), flush=True)
+        return
+    if args.workload == "initnet":
+        print(json.dumps(initnet_bench(args)), flush=True)
         return
 
     if args.copy_mb > 0:

@@ -178,18 +178,37 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   int mx_t = 0, mx_r = 0;
   const long long total = block_scan(a.tile_cnt, a.tile_off, a.T, lds, mx_t);
   block_scan(a.rec_cnt, a.rec_off, a.R, lds, mx_r);
-  // items per list-length bucket, then the first position of each bucket
-  // with the longest lists first
+  // Items per list-length bucket, then the first position of each bucket
+  // with the longest lists first.  The loops run over the jobs' tile ranges
+  // (a job's tiles are contiguous), so no tile searches for its job.
+  __shared__ int nbig;
   for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) hist[k] = 0;
+  if (threadIdx.x == 0) nbig = 0;
   __syncthreads();
-  for (int t = threadIdx.x; t < a.T; t += blockDim.x) {
-    const ps_slot& sl = a.slots[find_slot_by_tile(a.slots, a.S, t)];
-    atomicAdd(&hist[length_bucket(a.tile_cnt[t])], (sl.tile_w >> 3) * (sl.tile_h >> 3));
+  for (int s = 0; s < a.S; ++s) {
+    const ps_slot& sl = a.slots[s];
+    const int tb = sl.tile_begin, nt = sl.tiles_x * sl.tiles_y;
+    const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
+    for (int t = tb + threadIdx.x; t < tb + nt; t += blockDim.x) {
+      const int c = a.tile_cnt[t];
+      atomicAdd(&hist[length_bucket(c)], sub_per);
+      a.tile_cur[t] = 0;   // scatter cursors of bin_emit
+      if (c > kSmallSort && c <= kBigSort) a.bigtiles[atomicAdd(&nbig, 1)] = t;
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int k = kBuckets - 1; k >= 0; --k) {
+  if (threadIdx.x < 64) {   // exclusive scan over buckets, longest first: 16 buckets per lane
+    const int lane = threadIdx.x;
+    int loc = 0;
+    for (int i = 0; i < 16; ++i) loc += hist[kBuckets - 1 - (16 * lane + i)];
+    int incl = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    int run = incl - loc;
+    for (int i = 0; i < 16; ++i) {
+      const int k = kBuckets - 1 - (16 * lane + i);
       const int h = hist[k];
       hist[k] = run;
       run += h;
@@ -198,21 +217,12 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   __syncthreads();
   // each tile's items take consecutive positions in their bucket (the order
   // of tiles inside a bucket does not matter: items are independent)
-  for (int t = threadIdx.x; t < a.T; t += blockDim.x) {
-    const ps_slot& sl = a.slots[find_slot_by_tile(a.slots, a.S, t)];
-    a.tile_pos[t] = atomicAdd(&hist[length_bucket(a.tile_cnt[t])], (sl.tile_w >> 3) * (sl.tile_h >> 3));
-  }
-  // scatter cursors, big-tile list
-  __shared__ int nbig;
-  if (threadIdx.x == 0) nbig = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < a.T; t += blockDim.x) {
-    a.tile_cur[t] = 0;
-    const int c = a.tile_cnt[t];
-    if (c > kSmallSort && c <= kBigSort) {
-      const int slot = atomicAdd(&nbig, 1);
-      a.bigtiles[slot] = t;
-    }
+  for (int s = 0; s < a.S; ++s) {
+    const ps_slot& sl = a.slots[s];
+    const int tb = sl.tile_begin, nt = sl.tiles_x * sl.tiles_y;
+    const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
+    for (int t = tb + threadIdx.x; t < tb + nt; t += blockDim.x)
+      a.tile_pos[t] = atomicAdd(&hist[length_bucket(a.tile_cnt[t])], sub_per);
   }
   __syncthreads();
   if (threadIdx.x == 0) {

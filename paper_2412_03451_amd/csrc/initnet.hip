@@ -40,7 +40,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int C = IN_C;
 constexpr int TM = IN_TM;
 constexpr int LDA = C + 8;    // LDS row of a tile, bfloat16 elements (16-byte pad)
-constexpr int KC = 512;       // rows per split-K chunk of the weight-gradient product
 constexpr float W_N = 0.25f;  // weight of the normal term of the set loss
 constexpr float W_E = 0.25f;  // weight of the extent term
 constexpr float R_MIN = 0.01f;
@@ -439,13 +438,14 @@ struct BwdArgs {
   // workspace
   float* dg;          // [B][C]
   uint16_t* h1T;      // [C][R]
+  uint16_t* h1r;      // [R][C]
   uint16_t* dp2;      // [R][C]  dL/dpre2, bfloat16
   uint16_t* dp2T;     // [C][R]
   float* dp2f;        // [R][C]  dL/dpre2, float32
   uint16_t* h2r;      // [R][C]
   float* dp3;         // [R]
   float* dh1;         // [R][C]
-  float* pw2;         // [R / KC][C][C] split-K partials of dW2
+  float* pw2;         // [parts][C][C] split-K partials of dW2
   float* colp;        // [R / 256][5][C]
 };
 
@@ -459,21 +459,23 @@ __global__ __launch_bounds__(256) void head_dg_kernel(BwdArgs a) {
   a.dg[b * C + c] = acc;
 }
 
-// dWh[c][j] = sum_b g[b][c] d_out[b][j], dbh[j] = sum_b d_out[b][j]
+// dWh[c][j] = sum_b g[b][c] d_out[b][j] (c < C) and dbh[j] = sum_b d_out[b][j]
+// (c = C): one wave per output, lanes over the views, fixed-order reduction.
 __global__ __launch_bounds__(256) void head_dw_kernel(BwdArgs a) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= a.P12) return;
-  const int cb = blockIdx.y * 16;
-  float acc[16];
-  for (int k = 0; k < 16; ++k) acc[k] = 0.f;
-  float sb = 0.f;
-  for (int b = 0; b < a.B; ++b) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int n_out = (C + 1) * a.P12;
+  if (w >= n_out) return;
+  const int c = w / a.P12, j = w % a.P12;
+  float acc = 0.f;
+  for (int b = lane; b < a.B; b += 64) {
     const float d = a.d_out[(size_t)b * a.P12 + j];
-    sb += d;
-    for (int k = 0; k < 16; ++k) acc[k] = fmaf(a.g[b * C + cb + k], d, acc[k]);
+    acc = c < C ? fmaf(a.g[b * C + c], d, acc) : acc + d;
   }
-  for (int k = 0; k < 16; ++k) a.grad[a.o.Wh + (size_t)(cb + k) * a.P12 + j] = acc[k];
-  if (blockIdx.y == 0) a.grad[a.o.bh + j] = sb;
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) {
+    if (c < C) a.grad[a.o.Wh + (size_t)c * a.P12 + j] = acc;
+    else a.grad[a.o.bh + j] = acc;
+  }
 }
 
 // Rows r = b * C + c (the point attaining channel c of view b): recompute h1,
@@ -497,6 +499,11 @@ __global__ __launch_bounds__(512) void rows_kernel(BwdArgs a) {
     const uint16_t h = f2bf(fmaxf(v, 0.f));
     H[m * LDA + j] = h;
     a.h1T[(size_t)j * a.R + r] = h;
+  }
+  __syncthreads();
+  for (int e = tid; e < TM * C; e += 512) {   // row layout too (coalesced)
+    const int m = e / C, j = e % C;
+    a.h1r[(size_t)(rb + m) * C + j] = H[m * LDA + j];
   }
   __syncthreads();
   const int r0 = (w >> 2) * 64, c0 = (w & 3) * 64;
@@ -596,15 +603,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         Cz[(size_t)(m0 + 32 * i + acc_row(v, l)) * g.ldc + n0 + 32 * j + acc_col(l)] = acc[i][j][v];
 }
 
-// Column sums over a chunk of 256 rows (thread = column): dW1 (3), db1, db2.
+constexpr int kColChunk = 1024;   // rows per column-sum chunk
+
+// Column sums over a chunk of rows (thread = column): dW1 (3), db1, db2.
 __global__ __launch_bounds__(256) void colpart_kernel(BwdArgs a) {
   const int j = threadIdx.x, chunk = blockIdx.x;
   float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int m = 0; m < 256; ++m) {
-    const int r = chunk * 256 + m;
+  const int r0 = chunk * kColChunk, r1 = min(a.R, r0 + kColChunk);
+  for (int r = r0; r < r1; ++r) {
     const int bv = r / C, ch = r % C;
     const float* x = a.X + ((size_t)bv * a.N + a.arg[bv * C + ch]) * 3;
-    const float h1 = bf2f(a.h1T[(size_t)j * a.R + r]);
+    const float h1 = bf2f(a.h1r[(size_t)r * C + j]);
     const float d1 = h1 > 0.f ? a.dh1[(size_t)r * C + j] : 0.f;
     s[0] = fmaf(x[0], d1, s[0]);
     s[1] = fmaf(x[1], d1, s[1]);
@@ -615,27 +624,28 @@ __global__ __launch_bounds__(256) void colpart_kernel(BwdArgs a) {
   for (int k = 0; k < 5; ++k) a.colp[((size_t)chunk * 5 + k) * C + j] = s[k];
 }
 
-// Final sums in a fixed order: dW1, db1, db2 over chunks; dW2 over split-K
-// parts; dW3, db3 over views.
-__global__ __launch_bounds__(256) void wgrad_kernel(BwdArgs a, int nchunk, int nz) {
-  const int blk = blockIdx.x, t = threadIdx.x;
-  if (blk == 0) {
-    float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int ck = 0; ck < nchunk; ++ck)
-      for (int k = 0; k < 5; ++k) s[k] += a.colp[((size_t)ck * 5 + k) * C + t];
-    a.grad[a.o.W1 + t] = s[0];
-    a.grad[a.o.W1 + C + t] = s[1];
-    a.grad[a.o.W1 + 2 * C + t] = s[2];
-    a.grad[a.o.b1 + t] = s[3];
-    a.grad[a.o.b2 + t] = s[4];
-    return;
+// dW1, db1, db2: one wave per (value, column), lanes over chunks.
+__global__ __launch_bounds__(256) void colsum_kernel(BwdArgs a, int nchunk) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w >= 5 * C) return;
+  const int k = w / C, j = w % C;
+  float acc = 0.f;
+  for (int ck = lane; ck < nchunk; ck += 64) acc += a.colp[((size_t)ck * 5 + k) * C + j];
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) {
+    if (k < 3) a.grad[a.o.W1 + k * C + j] = acc;
+    else if (k == 3) a.grad[a.o.b1 + j] = acc;
+    else a.grad[a.o.b2 + j] = acc;
   }
-  const int row = blk - 1;   // 0 .. C-1
-  // dW2[row][t]
+}
+
+// dW2 over the split-K parts; dW3, db3 over views.  Block = row of dW2 /
+// column of dW3, thread = the other index.
+__global__ __launch_bounds__(256) void wgrad_kernel(BwdArgs a, int nz) {
+  const int row = blockIdx.x, t = threadIdx.x;
   float s = 0.f;
   for (int z = 0; z < nz; ++z) s += a.pw2[((size_t)z * C + row) * C + t];
   a.grad[a.o.W2 + (size_t)row * C + t] = s;
-  // dW3[t][row] = sum_b h2[(b, row)][t] dpre3[(b, row)]; db3[row]
   float s3 = 0.f, sb = 0.f;
   for (int b = 0; b < a.B; ++b) {
     const int r = b * C + row;
@@ -694,8 +704,16 @@ __global__ void adam_kernel(float* th, float* m, float* v, const float* g, int64
 
 inline int64_t ws_align(int64_t floats) { return (floats + 63) & ~int64_t(63); }
 
+// split-K parts of the dW2 product: enough workgroups to fill the chip,
+// each over a multiple of 16 rows
+inline int wgrad_parts(int64_t R) {
+  int nz = 1;
+  while (nz < 64 && R / (2 * nz) >= 512 && (R / (2 * nz)) % 16 == 0 && R % (2 * nz) == 0) nz *= 2;
+  return nz;
+}
+
 struct BwdWs {
-  int64_t dg, h1T, dp2, dp2T, dp2f, h2r, dp3, dh1, pw2, colp, n;
+  int64_t dg, h1T, h1r, dp2, dp2T, dp2f, h2r, dp3, dh1, pw2, colp, n;
 };
 inline BwdWs bwd_ws(int B) {
   const int64_t R = (int64_t)B * C;
@@ -703,14 +721,15 @@ inline BwdWs bwd_ws(int B) {
   int64_t o = 0;
   w.dg = o; o += ws_align(R);
   w.h1T = o; o += ws_align(R * C / 2);
+  w.h1r = o; o += ws_align(R * C / 2);
   w.dp2 = o; o += ws_align(R * C / 2);
   w.dp2T = o; o += ws_align(R * C / 2);
   w.dp2f = o; o += ws_align(R * C);
   w.h2r = o; o += ws_align(R * C / 2);
   w.dp3 = o; o += ws_align(R);
   w.dh1 = o; o += ws_align(R * C);
-  w.pw2 = o; o += ws_align((R / KC) * (int64_t)C * C);
-  w.colp = o; o += ws_align((R / 256) * 5 * (int64_t)C);
+  w.pw2 = o; o += ws_align((int64_t)wgrad_parts(R) * C * C);
+  w.colp = o; o += ws_align(((R + kColChunk - 1) / kColChunk) * 5 * (int64_t)C);
   w.n = o;
   return w;
 }
@@ -794,6 +813,7 @@ extern "C" int initnet_backward(const float* master, const uint16_t* packed, int
   a.X = X; a.g = g; a.arg = arg; a.d_out = d_out; a.grad = grad;
   a.dg = ws + w.dg;
   a.h1T = (uint16_t*)(ws + w.h1T);
+  a.h1r = (uint16_t*)(ws + w.h1r);
   a.dp2 = (uint16_t*)(ws + w.dp2);
   a.dp2T = (uint16_t*)(ws + w.dp2T);
   a.dp2f = ws + w.dp2f;
@@ -804,16 +824,19 @@ extern "C" int initnet_backward(const float* master, const uint16_t* packed, int
   a.colp = ws + w.colp;
   const int R = a.R;
   hipLaunchKernelGGL(head_dg_kernel, dim3(B), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(head_dw_kernel, dim3((a.P12 + 255) / 256, C / 16), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(head_dw_kernel, dim3(((C + 1) * a.P12 + 3) / 4), dim3(256), 0, st, a);
   hipLaunchKernelGGL(rows_kernel, dim3(R / TM), dim3(512), 0, st, a);
   // dW2 partials: [k1][k2] = sum_r h1T[k1][r] dp2T[k2][r], split over row chunks
-  GemmArgs g2{a.h1T, R, a.dp2T, R, a.pw2, C, R, KC, (int64_t)C * C};
-  hipLaunchKernelGGL(gemm_kernel, dim3(C / 128, C / 128, R / KC), dim3(256), 0, st, g2);
+  const int nz = wgrad_parts(R);
+  GemmArgs g2{a.h1T, R, a.dp2T, R, a.pw2, C, R, R / nz, (int64_t)C * C};
+  hipLaunchKernelGGL(gemm_kernel, dim3(C / 128, C / 128, nz), dim3(256), 0, st, g2);
   // dh1[r][k1] = sum_k2 dp2[r][k2] W2[k1][k2]
   GemmArgs g1{a.dp2, C, packed + a.po.W2, C, a.dh1, C, C, C, 0};
   hipLaunchKernelGGL(gemm_kernel, dim3(C / 128, R / 128, 1), dim3(256), 0, st, g1);
-  hipLaunchKernelGGL(colpart_kernel, dim3(R / 256), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(wgrad_kernel, dim3(C + 1), dim3(256), 0, st, a, R / 256, R / KC);
+  const int nchunk = (R + kColChunk - 1) / kColChunk;
+  hipLaunchKernelGGL(colpart_kernel, dim3(nchunk), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(colsum_kernel, dim3(5 * C / 4), dim3(256), 0, st, a, nchunk);
+  hipLaunchKernelGGL(wgrad_kernel, dim3(C), dim3(256), 0, st, a, nz);
   IN_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }

@@ -39,13 +39,15 @@ __device__ inline double wave_sum_d(double v) {
   return v;
 }
 
+// grid (items of the largest job / 4, jobs): the job is blockIdx.y, no search
 __global__ __launch_bounds__(256) void loss_kernel(LossArgs a) {
-  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (item >= a.n_items) return;
-  const int s = find_slot_by_item(a.slots, a.S, item);
+  const int s = blockIdx.y;
   const ps_slot sl = a.slots[s];
-  const int local = item - sl.item_begin;
+  const int local = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n_local = (s + 1 < a.S ? a.slots[s + 1].item_begin : a.n_items) - sl.item_begin;
+  if (local >= n_local) return;
+  const int item = sl.item_begin + local;
   const int sub_w = sl.tile_w >> 3;
   const int sub_per = sub_w * (sl.tile_h >> 3);
   const int tile = local / sub_per, sub = local - tile * sub_per;
@@ -144,7 +146,7 @@ static int loss_launch(const ps_layout* L, void* ws, const float* depth, const f
   a.loss = loss;
   hipStream_t st = (hipStream_t)stream;
   if (a.n_items > 0)
-    hipLaunchKernelGGL(loss_kernel, dim3((a.n_items + 3) / 4), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(loss_kernel, dim3((L->max_items + 3) / 4, a.S), dim3(256), 0, st, a);
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(a.S), dim3(256), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;

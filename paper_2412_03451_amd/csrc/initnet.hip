@@ -137,7 +137,8 @@ struct FwdArgs {
   uint16_t* dump; // [3][B*N][C] or null
 };
 
-__global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a) {
+template <bool DUMP>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void fwd_kernel(FwdArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t H[TM * LDA];
   __shared__ float red_v[2][C];
   __shared__ int red_i[2][C];
@@ -149,16 +150,22 @@ __global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a) {
   const uint16_t* W1 = a.packed + a.po.W1;
   const float* b1 = a.master + a.o.b1;
   const size_t BN = (size_t)a.B * a.N;
-  // layer 1 on the vector ALU
-  for (int e = tid; e < TM * C; e += 512) {
-    const int m = e / C, j = e % C;
-    const float x0 = X[3 * m], x1 = X[3 * m + 1], x2 = X[3 * m + 2];
-    float v = fmaf(x0, bf2f(W1[j]), b1[j]);
-    v = fmaf(x1, bf2f(W1[C + j]), v);
-    v = fmaf(x2, bf2f(W1[2 * C + j]), v);
-    const uint16_t h = f2bf(fmaxf(v, 0.f));
-    H[m * LDA + j] = h;
-    if (a.dump) a.dump[(row0 + m) * C + j] = h;
+  // layer 1 on the vector ALU: thread = (column, half of the rows), the
+  // column's weights in registers, the tile's points staged in LDS
+  __shared__ float xs[TM * 3];
+  for (int e = tid; e < TM * 3; e += 512) xs[e] = X[e];
+  __syncthreads();
+  {
+    const int j = tid & (C - 1), half = tid >> 8;
+    const float w0 = bf2f(W1[j]), w1 = bf2f(W1[C + j]), w2 = bf2f(W1[2 * C + j]), bj = b1[j];
+    for (int m = half; m < TM; m += 2) {
+      float v = fmaf(xs[3 * m], w0, bj);
+      v = fmaf(xs[3 * m + 1], w1, v);
+      v = fmaf(xs[3 * m + 2], w2, v);
+      const uint16_t h = f2bf(fmaxf(v, 0.f));
+      H[m * LDA + j] = h;
+      if (DUMP) a.dump[(row0 + m) * C + j] = h;
+    }
   }
   __syncthreads();
   const int r0 = (w >> 2) * 64, c0 = (w & 3) * 64;
@@ -179,7 +186,7 @@ __global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a) {
           const int row = r0 + 32 * i + acc_row(v, lane);
           const uint16_t h = f2bf(fmaxf(acc[i][j][v] + bias, 0.f));
           H[row * LDA + col] = h;
-          if (a.dump) a.dump[BN * C + (row0 + row) * C + col] = h;
+          if (DUMP) a.dump[BN * C + (row0 + row) * C + col] = h;
         }
       }
   }
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(512) void fwd_kernel(FwdArgs a) {
         const int row = r0 + 32 * i + acc_row(v, lane);   // increasing along (i, v)
         const uint16_t hb = f2bf(fmaxf(acc[i][j][v] + bias, 0.f));
         const float h = bf2f(hb);
-        if (a.dump) a.dump[2 * BN * C + (row0 + row) * C + col] = hb;
+        if (DUMP) a.dump[2 * BN * C + (row0 + row) * C + col] = hb;
         if (h > best) {
           best = h;
           bi = row;
@@ -777,7 +784,10 @@ extern "C" int initnet_forward(const float* master, const uint16_t* packed, int 
   a.pv = ws;
   a.pi = (int32_t*)(ws + half);
   a.dump = dump;
-  hipLaunchKernelGGL(fwd_kernel, dim3(a.ntile, B), dim3(512), 0, st, a);
+  if (dump)
+    hipLaunchKernelGGL(fwd_kernel<true>, dim3(a.ntile, B), dim3(512), 0, st, a);
+  else
+    hipLaunchKernelGGL(fwd_kernel<false>, dim3(a.ntile, B), dim3(512), 0, st, a);
   HeadArgs h;
   h.master = master; h.packed = packed; h.B = B; h.P12 = IN_OUT * P; h.ntile = a.ntile;
   h.o = a.o; h.po = a.po; h.pv = a.pv; h.pi = a.pi; h.g = g; h.arg = arg; h.out = out;

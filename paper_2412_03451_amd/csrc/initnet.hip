@@ -103,24 +103,25 @@ __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
 __device__ __forceinline__ int acc_row(int i, int l) { return 8 * (i >> 2) + 4 * (l >> 5) + (i & 3); }
 __device__ __forceinline__ int acc_col(int l) { return l & 31; }
 
-// 64 x 64 block of (tile rows r0.., weight columns c0..) = H[r, :] . Wt[c, :]
-// over K = 256: H is the LDS tile, Wt the transposed weights in global memory.
-__device__ __forceinline__ void gemm_tile(const uint16_t* H, const uint16_t* __restrict__ Wt, int r0, int c0,
-                                          f32x16 (&acc)[2][2]) {
+// 128 x 32 block (every row of the tile, weight columns c0 .. c0+31) of
+// H[r, :] . Wt[c, :] over K = 256: H is the LDS tile, Wt the transposed
+// weights in global memory.  One B fragment per step feeds four MFMAs.
+__device__ __forceinline__ void gemm_tile(const uint16_t* H, const uint16_t* __restrict__ Wt, int c0,
+                                          f32x16 (&acc)[4]) {
   const int l = threadIdx.x & 63;
-  acc[0][0] = zero16(); acc[0][1] = zero16(); acc[1][0] = zero16(); acc[1][1] = zero16();
-  const uint16_t* bp0 = Wt + (size_t)(c0 + (l & 31)) * C + 8 * (l >> 5);
-  const uint16_t* bp1 = bp0 + 32 * C;
-  const uint16_t* ap0 = H + (r0 + (l & 31)) * LDA + 8 * (l >> 5);
-  const uint16_t* ap1 = ap0 + 32 * LDA;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = zero16();
+  const uint16_t* bp = Wt + (size_t)(c0 + (l & 31)) * C + 8 * (l >> 5);
+  const uint16_t* ap = H + (l & 31) * LDA + 8 * (l >> 5);
 #pragma unroll 4
   for (int k0 = 0; k0 < C; k0 += 16) {
-    const bf16x8 b0 = ld8(bp0 + k0), b1 = ld8(bp1 + k0);
-    const bf16x8 a0 = ld8(ap0 + k0), a1 = ld8(ap1 + k0);
-    acc[0][0] = mfma(a0, b0, acc[0][0]);
-    acc[0][1] = mfma(a0, b1, acc[0][1]);
-    acc[1][0] = mfma(a1, b0, acc[1][0]);
-    acc[1][1] = mfma(a1, b1, acc[1][1]);
+    const bf16x8 b = ld8(bp + k0);
+    const bf16x8 a0 = ld8(ap + k0), a1 = ld8(ap + 32 * LDA + k0);
+    const bf16x8 a2 = ld8(ap + 64 * LDA + k0), a3 = ld8(ap + 96 * LDA + k0);
+    acc[0] = mfma(a0, b, acc[0]);
+    acc[1] = mfma(a1, b, acc[1]);
+    acc[2] = mfma(a2, b, acc[2]);
+    acc[3] = mfma(a3, b, acc[3]);
   }
 }
 
@@ -140,8 +141,6 @@ struct FwdArgs {
 template <bool DUMP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void fwd_kernel(FwdArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t H[TM * LDA];
-  __shared__ float red_v[2][C];
-  __shared__ int red_i[2][C];
   const int tile = blockIdx.x, b = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int p0 = tile * TM;
@@ -168,69 +167,53 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
   }
   __syncthreads();
-  const int r0 = (w >> 2) * 64, c0 = (w & 3) * 64;
-  f32x16 acc[2][2];
+  const int c0 = w * 32;   // this wave's 32 output columns, every row
+  const int col = c0 + acc_col(lane);
+  f32x16 acc[4];
   // layer 2
-  gemm_tile(H, a.packed + a.po.W2t, r0, c0, acc);
+  gemm_tile(H, a.packed + a.po.W2t, c0, acc);
   __syncthreads();   // every wave has read layer 1
   {
-    const float* b2 = a.master + a.o.b2;
+    const float bias = a.master[a.o.b2 + col];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int col = c0 + 32 * j + acc_col(lane);
-        const float bias = b2[col];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int row = r0 + 32 * i + acc_row(v, lane);
-          const uint16_t h = f2bf(fmaxf(acc[i][j][v] + bias, 0.f));
-          H[row * LDA + col] = h;
-          if (DUMP) a.dump[BN * C + (row0 + row) * C + col] = h;
-        }
-      }
-  }
-  __syncthreads();
-  // layer 3 and the tile's column maxima
-  gemm_tile(H, a.packed + a.po.W3t, r0, c0, acc);
-  const float* b3 = a.master + a.o.b3;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int col = c0 + 32 * j + acc_col(lane);
-    const float bias = b3[col];
-    float best = -1.f;
-    int bi = 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int row = r0 + 32 * i + acc_row(v, lane);   // increasing along (i, v)
-        const uint16_t hb = f2bf(fmaxf(acc[i][j][v] + bias, 0.f));
-        const float h = bf2f(hb);
-        if (DUMP) a.dump[2 * BN * C + (row0 + row) * C + col] = hb;
-        if (h > best) {
-          best = h;
-          bi = row;
-        }
+        const int row = 32 * i + acc_row(v, lane);
+        const uint16_t h = f2bf(fmaxf(acc[i][v] + bias, 0.f));
+        H[row * LDA + col] = h;
+        if (DUMP) a.dump[BN * C + (row0 + row) * C + col] = h;
       }
-    const float ob = __shfl_xor(best, 32, 64);
-    const int oi = __shfl_xor(bi, 32, 64);
-    if (ob > best || (ob == best && oi < bi)) {
-      best = ob;
-      bi = oi;
-    }
-    if (lane < 32) {
-      red_v[w >> 2][col] = best;
-      red_i[w >> 2][col] = bi;
-    }
   }
   __syncthreads();
-  if (tid < C) {
-    // rows of red_*[0] precede those of red_*[1]: ties keep the first
-    const bool second = red_v[1][tid] > red_v[0][tid];
-    const size_t o = ((size_t)b * a.ntile + tile) * C + tid;
-    a.pv[o] = second ? red_v[1][tid] : red_v[0][tid];
-    a.pi[o] = p0 + (second ? red_i[1][tid] : red_i[0][tid]);
+  // layer 3 and the tile's column maxima (all rows of a column are in this wave)
+  gemm_tile(H, a.packed + a.po.W3t, c0, acc);
+  const float bias = a.master[a.o.b3 + col];
+  float best = -1.f;
+  int bi = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = 32 * i + acc_row(v, lane);   // increasing along (i, v)
+      const uint16_t hb = f2bf(fmaxf(acc[i][v] + bias, 0.f));
+      const float h = bf2f(hb);
+      if (DUMP) a.dump[2 * BN * C + (row0 + row) * C + col] = hb;
+      if (h > best) {
+        best = h;
+        bi = row;
+      }
+    }
+  const float ob = __shfl_xor(best, 32, 64);
+  const int oi = __shfl_xor(bi, 32, 64);
+  if (ob > best || (ob == best && oi < bi)) {
+    best = ob;
+    bi = oi;
+  }
+  if (lane < 32) {
+    const size_t o = ((size_t)b * a.ntile + tile) * C + col;
+    a.pv[o] = best;
+    a.pi[o] = p0 + bi;
   }
 }
 
@@ -513,25 +496,22 @@ __global__ __launch_bounds__(512) void rows_kernel(BwdArgs a) {
     a.h1r[(size_t)(rb + m) * C + j] = H[m * LDA + j];
   }
   __syncthreads();
-  const int r0 = (w >> 2) * 64, c0 = (w & 3) * 64;
-  f32x16 acc[2][2];
-  gemm_tile(H, a.packed + a.po.W2t, r0, c0, acc);
+  const int c0 = w * 32, col = c0 + acc_col(lane);
+  f32x16 acc[4];
+  gemm_tile(H, a.packed + a.po.W2t, c0, acc);
   __syncthreads();
-  const float* b2 = a.master + a.o.b2;
+  {
+    const float bias = a.master[a.o.b2 + col];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = c0 + 32 * j + acc_col(lane);
-      const float bias = b2[col];
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int row = r0 + 32 * i + acc_row(v, lane);
-        const uint16_t h = f2bf(fmaxf(acc[i][j][v] + bias, 0.f));
+        const int row = 32 * i + acc_row(v, lane);
+        const uint16_t h = f2bf(fmaxf(acc[i][v] + bias, 0.f));
         H[row * LDA + col] = h;
         a.h2r[(size_t)(rb + row) * C + col] = h;
       }
-    }
+  }
   __syncthreads();
   // pre3[r][c_r] = h2[r] . W3[:, c_r] + b3[c_r]: four threads per row
   {

@@ -52,6 +52,7 @@ struct BinArgs {
   int* tile_pos;      // first render item of each tile
 };
 
+template <bool KEY>
 __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot& sl, int tx, int ty,
                                  float& key_t) {
   int x0 = tx * sl.tile_w, y0 = ty * sl.tile_h;
@@ -73,11 +74,14 @@ __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot
   for (int c = 0; c < 4; ++c) {
     const double den = fma(rec.Du, cu[c], fma(rec.Dv, cv[c], rec.D0));
     if (rec.h * den > 0.0) {
-      tmin = fmin(tmin, rec.h / den);
+      // h / den to within a few float64 roundoffs, far below the float32
+      // rounding and the one-ulp step below
+      if (KEY) tmin = fmin(tmin, rec.h * rcp64(den));
       any = true;
     }
   }
   if (!any) return false;
+  if (!KEY) return true;
   const float f = __double2float_rd(fmax((double)br.tlb, tmin));
   key_t = __uint_as_float(__float_as_uint(f) - 1u);  // f > 0: one ulp towards zero
   return true;
@@ -103,7 +107,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
       if (idx < n) {
         const int tx = br.tx0 + idx % nx, ty = br.ty0 + idx / nx;
         float kt;
-        pass = tile_test(rec, br, sl, tx, ty, kt);
+        pass = tile_test<false>(rec, br, sl, tx, ty, kt);
         if (pass) atomicAdd(&a.tile_cnt[sl.tile_begin + ty * sl.tiles_x + tx], 1);
       }
       cnt += __popcll(ballot(pass));
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
     if (idx < n) {
       tx = br.tx0 + idx % nx;
       ty = br.ty0 + idx / nx;
-      pass = tile_test(rec, br, sl, tx, ty, kt);
+      pass = tile_test<true>(rec, br, sl, tx, ty, kt);
     }
     const uint64_t m = ballot(pass);
     if (pass) {

@@ -152,6 +152,23 @@ int plane_render_bwd_lists(const ps_layout* L, void* ws, const float* center, co
                            const int32_t* list_pos, const float* list_a, const int32_t* list_count,
                            float* g_center, float* g_quat, float* g_radii, void* stream);
 
+/* Plane splitting (Sec. 3.3).  plane_grad_accumulate adds |g_radii| to acc
+ * (device float [K][4], the caller clears it after each split).
+ * plane_split reads the sums acc over n_acc iterations: plane k is cut
+ * across its X extent (two halves side by side along its X axis, each with
+ * both X radii a quarter of the extent) when (acc[k][x+] + acc[k][x-]) /
+ * (2 n_acc) > thresh, likewise across Y; both gives four children.  The
+ * rotation is kept and so are the radii along an axis that is not cut.
+ * Children of plane k are consecutive and in plane order (x- half before x+,
+ * then y- before y+) at out_* [first[k], first[k+1]) with parent[] = k;
+ * first: device int32 [K + 1], first[K] = *k_out (device int32) = the new
+ * plane count.  out_*: device float [4K][3], [4K][4], [4K][4]; parent: int32
+ * [4K]; ws: device int32 [K + 1]. */
+int plane_grad_accumulate(const float* g_radii, float* acc, int K, void* stream);
+int plane_split(const float* center, const float* quat, const float* radii, const float* acc, int n_acc,
+                float thresh, int K, float* out_center, float* out_quat, float* out_radii, int32_t* parent,
+                int32_t* first, int32_t* k_out, int32_t* ws, void* stream);
+
 /* Device-side bookkeeping of one iteration of the fitting loop (Sec. 3.3,
  * Eq. 10), so that whole steps can be captured in a graph and replayed with
  * no host work.  Reads the iteration counter *ite (device int32, 0-based),

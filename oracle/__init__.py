@@ -16,6 +16,7 @@ forward definition).  Sections cited:
 * filter / per-ray sort / first M / compositing ...... Sec. 3.2, Eq. 11-13
 * render loss ........................................ Sec. 3.2, Eq. 14
 * Adam, learning rate 1e-3 ........................... Sec. 3.3 and appendix A.2
+* plane splitting ..................................... Sec. 3.3, split.py
 * learned initializer (not in the paper; readings) ... initnet.py
 
 Readings taken where the paper is silent or garbled are listed in the
@@ -34,3 +35,4 @@ from .loss import render_loss, loss_terms  # noqa: F401
 from .adam import adam_step  # noqa: F401
 from .grad import render_backward, per_pixel_abs_grad  # noqa: F401
 from . import initnet  # noqa: F401
+from .split import split_planes  # noqa: F401

@@ -116,66 +116,6 @@ __global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
   if (lane == 0) a.rec_cnt[r] = cnt;
 }
 
-// Exclusive scan of in[0, n) into out[0, n], out[n] = total, by one
-// 1024-thread workgroup: blocks of 4096 elements, 4 per thread, wave64
-// inclusive scans by shuffles, wave totals through LDS, running carry.
-__device__ long long block_scan(const int* __restrict__ in, int* __restrict__ out, int n, int* lds_wave,
-                                int& maxv) {
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  long long carry = 0;
-  int mx = 0;
-  for (int base = 0; base < n; base += 4096) {
-    int v[4];
-    int local = 0;
-    for (int j = 0; j < 4; ++j) {
-      const int idx = base + tid * 4 + j;
-      v[j] = idx < n ? in[idx] : 0;
-      mx = max(mx, v[j]);
-      local += v[j];
-    }
-    int incl = local;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    if (lane == 63) lds_wave[wid] = incl;
-    __syncthreads();
-    if (wid == 0) {
-      int x = lane < 16 ? lds_wave[lane] : 0;
-      int xi = x;
-      for (int o = 1; o < 16; o <<= 1) {
-        const int y = __shfl_up(xi, o, 64);
-        if (lane >= o) xi += y;
-      }
-      if (lane < 16) lds_wave[16 + lane] = xi - x;   // exclusive wave offsets
-      if (lane == 15) lds_wave[32] = xi;             // block total
-    }
-    __syncthreads();
-    int run = (int)carry + lds_wave[16 + wid] + (incl - local);
-    for (int j = 0; j < 4; ++j) {
-      const int idx = base + tid * 4 + j;
-      if (idx < n) out[idx] = run;
-      run += v[j];
-    }
-    carry += lds_wave[32];
-    __syncthreads();
-  }
-  // max over the workgroup
-  for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
-  if (lane == 0) lds_wave[wid] = mx;
-  __syncthreads();
-  if (tid == 0) {
-    int m = 0;
-    for (int w = 0; w < 16; ++w) m = max(m, lds_wave[w]);
-    lds_wave[33] = m;
-  }
-  __syncthreads();
-  maxv = lds_wave[33];
-  if (tid == 0) out[n] = (int)carry;
-  __syncthreads();
-  return carry;
-}
-
 __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   __shared__ int lds[40];
   __shared__ int hist[kBuckets];

@@ -24,7 +24,7 @@ import numpy as np
 import torch
 
 from ._lib import check
-from .splat import Job, Renderer, SplatParams, _ptr, _stream, adam_step
+from .splat import Job, Renderer, SplatParams, _ptr, _stream, adam_step, grad_accumulate, split_planes
 
 
 def view_schedule(n_views: int, n_rows: int, per_step: int = 1, seed: int = 0) -> np.ndarray:
@@ -51,6 +51,8 @@ class FitConfig:
     seed: int = 0
     check_every: int = 100
     grow: float = 1.5
+    split_every: int = 0                # plane splitting every n iterations (Sec. 3.3: 1000); 0: off
+    split_thresh: float = 0.2           # average |dL/dr| over a pair of radii that triggers a split
 
 
 @dataclass
@@ -129,7 +131,11 @@ class BatchFit:
                                    for mk, sc in zip(masks, self.scenes)]).contiguous()
         self.tgt_off = torch.tensor(tgt_off, dtype=torch.int64, device=dev)
         self.params = params or SplatParams()
+        self.jobs = jobs
         self.rend = Renderer(jobs, cams, device=dev, pair_capacity=pair_capacity or (1 << 16), params=self.params)
+        self.acc = torch.zeros(self.K, 4, device=dev)   # sum of |dL/dr| since the last split
+        self.since_split = 0
+        self.splits = []                                  # (iteration, planes before, planes after)
         self.graph = None
         self.last_loss = None
         if size_capacity:
@@ -194,6 +200,8 @@ class BatchFit:
                                      a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2])
         m()
         gc, gq, gr = rend.backward(self.c, self.q, self.r, self.lam, gD, gN)
+        if cfg.split_every:
+            grad_accumulate(gr, self.acc)
         m()
         adam_step(self.c, self.q, self.r, gc, gq, gr, self.m, self.v, self.step_no, lr=cfg.lr, betas=cfg.betas,
                   eps=cfg.eps, r_min=cfg.r_min)
@@ -229,11 +237,46 @@ class BatchFit:
         self.graph = g
 
     def state(self):
-        return [t.clone() for t in (self.c, self.q, self.r, self.m, self.v, self.ite)]
+        return [t.clone() for t in (self.c, self.q, self.r, self.m, self.v, self.ite, self.acc)]
 
     def restore(self, st):
-        for dst, src in zip((self.c, self.q, self.r, self.m, self.v, self.ite), st):
+        for dst, src in zip((self.c, self.q, self.r, self.m, self.v, self.ite, self.acc), st):
             dst.copy_(src)
+
+    def _split(self):
+        """Plane splitting (Sec. 3.3) of every scene; the plane set, the Adam
+        moments (kept for planes that are not cut, zero for new children),
+        the jobs' plane ranges and the workspace are rebuilt, and the step is
+        captured again at the next run."""
+        K0 = self.K
+        c, q, r, parent, first = split_planes(self.c, self.q, self.r, self.acc, self.since_split,
+                                              self.cfg.split_thresh)
+        K1 = int(c.shape[0])
+        self.splits.append((int(self.ite.item()), K0, K1))
+        self.since_split = 0
+        self.acc = torch.zeros(K1, 4, device=self.device)
+        if K1 == K0:
+            return
+        first_h = first.cpu().numpy()
+        pl = parent.long()
+        single = ((first[1:] - first[:-1])[pl] == 1).to(torch.float32)
+
+        def moments(x):
+            xc, xq, xr = x[:3 * K0].view(K0, 3), x[3 * K0:7 * K0].view(K0, 4), x[7 * K0:].view(K0, 4)
+            return torch.cat([(xc[pl] * single[:, None]).reshape(-1), (xq[pl] * single[:, None]).reshape(-1),
+                              (xr[pl] * single[:, None]).reshape(-1)]).contiguous()
+
+        self.m, self.v = moments(self.m), moments(self.v)
+        self.c, self.q, self.r = c, q, r
+        self.K = K1
+        self.k_off = np.array([first_h[k] for k in self.k_off])
+        self.jobs = [Job(int(self.k_off[j.scene]), int(self.k_off[j.scene + 1]), j.cam, j.width, j.height, j.tile,
+                         j.scene) for j in self.jobs]
+        self.rend = Renderer(self.jobs, self.rend.cams, device=self.device, pair_capacity=self.rend.L.pair_capacity,
+                             params=self.params)
+        self._eval = {}
+        self.graph = None
+        self.size_capacity()
 
     def overflowed(self) -> bool:
         return bool(self.rend.counters()["overflow_since_init"])
@@ -248,6 +291,8 @@ class BatchFit:
                 raise RuntimeError("pair lists keep overflowing after growing the workspace: a tile list "
                                    "probably exceeds the per-tile limit (use smaller tiles)")
             chunk = min(self.cfg.check_every, n_steps - done)
+            if self.cfg.split_every:
+                chunk = min(chunk, self.cfg.split_every - self.since_split)
             saved = self.state()
             if graph and self.graph is None:
                 # one eager step (loads every kernel), then capture
@@ -275,6 +320,10 @@ class BatchFit:
                 grows += 1
                 continue
             done += chunk
+            if self.cfg.split_every:
+                self.since_split += chunk
+                if self.since_split >= self.cfg.split_every:
+                    self._split()
             if callback is not None:
                 callback(self, done)
         return self

@@ -278,3 +278,28 @@ def adam_step(center, quat, radii, g_center, g_quat, g_radii, m, v, step, lr=(1e
     check(lib.adam_step_planes(_ptr(center), _ptr(quat), _ptr(radii), _ptr(g_center), _ptr(g_quat),
                                _ptr(g_radii), _ptr(m), _ptr(v), int(center.shape[0]), _ptr(step),
                                lr[0], lr[1], lr[2], betas[0], betas[1], eps, r_min, _stream()))
+
+
+def grad_accumulate(g_radii, acc):
+    """acc += |g_radii| (plane_grad_accumulate)."""
+    lib = _lib.load()
+    check(lib.plane_grad_accumulate(_ptr(g_radii), _ptr(acc), int(g_radii.shape[0]), _stream()))
+
+
+def split_planes(center, quat, radii, acc, n_acc: int, thresh: float = 0.2):
+    """Plane splitting (plane_split): (center, quat, radii, parent, first) of
+    the new plane set, trimmed to its size (one host read of the count)."""
+    lib = _lib.load()
+    K = int(center.shape[0])
+    dev = center.device
+    oc = torch.empty(4 * K, 3, dtype=torch.float32, device=dev)
+    oq = torch.empty(4 * K, 4, dtype=torch.float32, device=dev)
+    orr = torch.empty(4 * K, 4, dtype=torch.float32, device=dev)
+    parent = torch.empty(4 * K, dtype=torch.int32, device=dev)
+    first = torch.empty(K + 1, dtype=torch.int32, device=dev)
+    k_out = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(K + 1, dtype=torch.int32, device=dev)
+    check(lib.plane_split(_ptr(center), _ptr(quat), _ptr(radii), _ptr(acc), int(n_acc), float(thresh), K, _ptr(oc),
+                          _ptr(oq), _ptr(orr), _ptr(parent), _ptr(first), _ptr(k_out), _ptr(ws), _stream()))
+    n = int(k_out.item())
+    return oc[:n].contiguous(), oq[:n].contiguous(), orr[:n].contiguous(), parent[:n].contiguous(), first

@@ -286,14 +286,14 @@ __device__ inline float splat_weight(float a, float lam5, int mode, float& omw) 
       return 1.f;
     }
     const float em = expm1f(-z);  // > 0
-    const float d = em + 2.f;
-    omw = em / d;
-    return 2.f / d;
+    const float r = __builtin_amdgcn_rcpf(em + 2.f);   // 1 ulp: both results keep their relative precision
+    omw = em * r;
+    return 2.f * r;
   }
   const float e = expf(-z);
-  const float d = 1.f + e;
-  omw = e / d;
-  return 1.f / d;
+  const float r = __builtin_amdgcn_rcpf(1.f + e);
+  omw = e * r;
+  return r;
 }
 // dw/da* (0 on the opaque side of mode 0).
 __device__ inline float splat_weight_grad(float a, float w, float omw, float lam5, int mode) {

@@ -774,9 +774,9 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
           const float gPX = xp ? -gaX : gaX;
           const float gPY = yp ? -gaY : gaY;
           // d.vx = (P_X + (p - o).vx) / t, d.vy likewise (x = o + t d)
-          const float it = 1.f / t;
+          const float it = __builtin_amdgcn_rcpf(t);
           const float G = Tw * gD + (gPX * (PX + pv.x) + gPY * (PY + pv.y)) * it;
-          const float Gd = G / den;
+          const float Gd = G * __builtin_amdgcn_rcpf(den);
           A[0] = gPX;
           A[1] = gPY;
           A[2] = Gd;

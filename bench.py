@@ -387,6 +387,72 @@ def scene_fit_bench(args):
     }
 
 
+def init_ablation_bench(args):
+    """Plane-initialisation ablation on the synthetic room (the analogue of
+    the paper's Sec. 4.3 comparison).  The default room (~2000 ground-truth
+    rectangles, 100 views of 640 x 480, targets at lambda = 300) is fitted for
+    --fit-iters iterations (one view per step, plane splitting every 1000
+    iterations) from three initialisations of 2000 planes: from the depth
+    maps (Sec. 3.1: fused points at stride 4 and 2 cm voxels), on the scene's
+    bounding sphere (Sec. 4.3, radii 0.05), and the noisy ground truth of the
+    throughput workload.  Depth L1 over all views at lambda = 300 every 500
+    iterations; fit wall-times exclude the evaluations; the initialisation
+    kernels are timed on their own."""
+    import torch
+    from paper_2412_03451_amd import learned_init as li
+    from paper_2412_03451_amd import scene_init as si
+    from paper_2412_03451_amd.fit import FitConfig, SceneFit
+
+    gt, init, cams, info = build_workload(100)
+    V, W, H = len(cams), cams[0].width, cams[0].height
+    tD, tN = li.render_targets((gt.center, gt.quat, gt.radii), cams)
+    D, N = tD.view(V, H, W), tN.view(V, 3, H, W)
+    K = 2000
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / reps * 1e3
+
+    (pts, nrm, n), pts_ms = timed(lambda: si.depth_points(D, N, cams, 4, 0.02))
+    rng = np.random.default_rng(0)
+    sel = rng.choice(n, K, replace=False).astype(np.int32)
+    depth_init, planes_ms = timed(lambda: si.init_from_points(pts, nrm, sel))
+    sphere_init, sphere_ms = timed(lambda: si.init_sphere(pts, K, seed=0))
+    log(f"depth_points: {n} fused points from {V} views in {pts_ms:.2f} ms; plane_init_points {planes_ms:.3f} ms; "
+        f"plane_init_sphere {sphere_ms:.3f} ms")
+    inits = {"depth": depth_init, "sphere": sphere_init, "noisy-gt": (init.center, init.quat, init.radii)}
+    out = {}
+    for name, planes in inits.items():
+        fit = SceneFit(*planes, cams, tD, tN, cfg=FitConfig(check_every=250, split_every=1000, split_thresh=0.2))
+        curve = [[0, round(fit.depth_l1(lam=300.0), 5)]]
+        fit_s = 0.0
+        for ck in range(500, args.fit_iters + 1, 500):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fit.run(500, graph=True)
+            torch.cuda.synchronize()
+            fit_s += time.perf_counter() - t0
+            curve.append([ck, round(fit.depth_l1(lam=300.0), 5)])
+            log(f"{name}: iteration {ck} depth L1 {curve[-1][1]:.4f} m, K {fit.K}")
+        out[name] = {"depth_l1": curve, "K_final": int(fit.K), "fit_seconds": round(fit_s, 3),
+                     "splits": [list(x) for x in fit.splits]}
+    return {
+        "metric": "depth L1 after the fit, by plane initialisation", "unit": "m",
+        "value": out["depth"]["depth_l1"][-1][1], "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+        "dtype": "f32 (f64 ray-plane geometry)",
+        "config": {"workload": f"room, {V} views of {W}x{H}, K_init = {K}, {args.fit_iters} iterations, "
+                               "splitting every 1000", "fused_points": int(n)},
+        "init_ms": {"depth_points": round(pts_ms, 3), "plane_init_points": round(planes_ms, 3),
+                    "plane_init_sphere": round(sphere_ms, 3)},
+        "runs": out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -403,13 +469,15 @@ def main():
                     help="eager steps timed phase by phase (per-kernel durations)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
-    ap.add_argument("--workload", default="room", choices=("room", "scene-fit", "memory", "batched", "initnet"),
+    ap.add_argument("--workload", default="room", choices=("room", "scene-fit", "memory", "batched", "initnet",
+                                                          "init-ablation"),
                     help="room: the fitting-step throughput (default); scene-fit: wall-time of plain fits "
                          "against batched fits from the learned initialisation at equal depth L1")
     ap.add_argument("--rooms", type=int, default=32, help="scene-fit: held-out rooms; batched: rooms")
     ap.add_argument("--autotune", action="store_true", help="batched: tile shape per room from the autotuner")
     ap.add_argument("--train-rooms", type=int, default=64, help="scene-fit: rooms fitted to train the initializer")
-    ap.add_argument("--fit-iters", type=int, default=2000, help="scene-fit: iterations of the plain fits")
+    ap.add_argument("--fit-iters", type=int, default=2000,
+                    help="scene-fit: iterations of the plain fits; init-ablation: iterations of each fit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -433,6 +501,9 @@ def main():
         return
     if args.workload == "initnet":
         print(json.dumps(initnet_bench(args)), flush=True)
+        return
+    if args.workload == "init-ablation":
+        print(json.dumps(init_ablation_bench(args)), flush=True)
         return
 
     if args.copy_mb > 0:

@@ -153,21 +153,77 @@ int plane_render_bwd_lists(const ps_layout* L, void* ws, const float* center, co
                            float* g_center, float* g_quat, float* g_radii, void* stream);
 
 /* Plane splitting (Sec. 3.3).  plane_grad_accumulate adds |g_radii| to acc
- * (device float [K][4], the caller clears it after each split).
- * plane_split reads the sums acc over n_acc iterations: plane k is cut
- * across its X extent (two halves side by side along its X axis, each with
- * both X radii a quarter of the extent) when (acc[k][x+] + acc[k][x-]) /
- * (2 n_acc) > thresh, likewise across Y; both gives four children.  The
- * rotation is kept and so are the radii along an axis that is not cut.
- * Children of plane k are consecutive and in plane order (x- half before x+,
- * then y- before y+) at out_* [first[k], first[k+1]) with parent[] = k;
- * first: device int32 [K + 1], first[K] = *k_out (device int32) = the new
- * plane count.  out_*: device float [4K][3], [4K][4], [4K][4]; parent: int32
- * [4K]; ws: device int32 [K + 1]. */
-int plane_grad_accumulate(const float* g_radii, float* acc, int K, void* stream);
-int plane_split(const float* center, const float* quat, const float* radii, const float* acc, int n_acc,
-                float thresh, int K, float* out_center, float* out_quat, float* out_radii, int32_t* parent,
-                int32_t* first, int32_t* k_out, int32_t* ws, void* stream);
+ * (device float [K][4]) and 1 to cnt[k] (device int32 [K]) for every plane
+ * whose radii gradient is not all zero (the plane took part in the
+ * iteration's render); the caller clears both after each split.
+ * plane_split averages the radii gradients over the iterations each plane
+ * took part in, as the gradient of the per-pixel mean loss: with
+ * gx = (acc[k][x+] + acc[k][x-]) * scale[k] and ct = 2 cnt[k] (float32),
+ * plane k is cut across its X extent (two halves side by side along its X
+ * axis, each with both X radii a quarter of the extent) when
+ * gx > thresh * ct, likewise across Y; both gives four children (a plane
+ * with cnt[k] <= 0 is kept).  scale:
+ * device float [K], the factor from the accumulated loss to the per-pixel
+ * mean (1 / pixels per view of the plane's scene for the summed loss of
+ * loss_depth_normal), or NULL for 1.  The rotation is kept and so are the
+ * radii along an axis that is not cut.  Children of plane k are consecutive
+ * and in plane order (x- half before x+, then y- before y+) at
+ * out_* [first[k], first[k+1]) with parent[] = k; first: device int32
+ * [K + 1], first[K] = *k_out (device int32) = the new plane count.  out_*:
+ * device float [4K][3], [4K][4], [4K][4]; parent: int32 [4K]; ws: device
+ * int32 [K + 1]. */
+int plane_grad_accumulate(const float* g_radii, float* acc, int32_t* cnt, int K, void* stream);
+int plane_split(const float* center, const float* quat, const float* radii, const float* acc, const int32_t* cnt,
+                const float* scale, float thresh, int K, float* out_center, float* out_quat, float* out_radii,
+                int32_t* parent, int32_t* first, int32_t* k_out, int32_t* ws, void* stream);
+
+/* Scene initialisation from depth (Sec. 3.1): plane centers are random
+ * points of a coarse surface built from the depth maps, radii half the
+ * distance to the nearest other center, rotation from the surface normal.
+ *
+ * depth_points fuses the maps into one point per occupied voxel.  Inputs:
+ * depth [V][H][W] and normal [V][3][H][W] (device float32, camera-frame
+ * normals, the layouts plane_render_fwd writes), cams: device array of V
+ * ps_camera (intrinsics and pose; their width and height are not read, the
+ * maps are H x W).  Every stride-th pixel (rows and columns from 0) counts
+ * when depth > 0 and |N| >= 0.5; its point is R^T (z d_c - t) with
+ * z = depth / |N|, d_c = ((i + 1/2 - cx) / fx, (j + 1/2 - cy) / fy, 1), its
+ * normal R^T N / |N|; float64 arithmetic, each operation rounded (no fused
+ * multiply-add).  Voxel index floor(x / voxel) per axis (grid anchored at the
+ * origin; a pixel whose index has magnitude >= 2^20 on an axis is dropped).
+ * Each occupied voxel keeps the point and normal of its first pixel in
+ * (view, row, column) order and voxels are numbered in that order.  Outputs:
+ * points and normals [cap][3] (device float32): the first min(n, cap)
+ * voxels; *n_out (device int32) = n, the number of occupied voxels.  ws:
+ * device scratch of depth_points_ws_bytes(V, H, W, stride) bytes.
+ * PS_ERR_INVALID: null pointer, V, H, W or stride < 1, voxel <= 0, cap < 0,
+ * ws_bytes too small, or more than 2^29 sampled pixels. */
+size_t depth_points_ws_bytes(int V, int H, int W, int stride);
+int depth_points(const float* depth, const float* normal, const ps_camera* cams, int V, int H, int W, int stride,
+                 float voxel, float* points, float* normals, int cap, int32_t* n_out, void* ws, size_t ws_bytes,
+                 void* stream);
+
+/* plane_init_points: K >= 2 planes on the points sel[k] (device int32 [K],
+ * indices into points/normals [n][3], device float32; the caller draws
+ * them).  center = points[sel[k]]; all four radii max(0.5 d, r_min) with d
+ * the distance to the nearest other selected point; quat (w, x, y, z) the
+ * shortest rotation taking e_z to normals[sel[k]] (a normal opposite to e_z
+ * gives the half turn about X); float64 arithmetic as in depth_points.  An
+ * index outside [0, n) gives that plane NaN parameters and is not read.
+ * Outputs center [K][3], quat [K][4], radii [K][4] (device float32).
+ * PS_ERR_INVALID: null pointer, K < 2, n < 1. */
+int plane_init_points(const float* points, const float* normals, int n, const int32_t* sel, int K, float r_min,
+                      float* center, float* quat, float* radii, void* stream);
+
+/* plane_init_sphere: the sphere initialisation of the ablation (Sec. 4.3).
+ * Bounding sphere of points [n][3] (device float32, n >= 1): center c = the
+ * middle of their axis-aligned box, radius R = the largest distance from c
+ * to a point.  Plane k sits at c + R u_k, u_k = dirs[k] / |dirs[k]| (device
+ * float32 [K][3], drawn by the caller), its normal -u_k (rotation as in
+ * plane_init_points), all radii `radius` (0.05 in the paper).  ws: device
+ * scratch of 64 bytes.  PS_ERR_INVALID: null pointer, n < 1, K < 1. */
+int plane_init_sphere(const float* points, int n, const float* dirs, int K, float radius, float* center,
+                      float* quat, float* radii, void* ws, void* stream);
 
 /* Device-side bookkeeping of one iteration of the fitting loop (Sec. 3.3,
  * Eq. 10), so that whole steps can be captured in a graph and replayed with

@@ -5,10 +5,16 @@ plane whose average radii gradient on its X axis (r^{x+}, r^{x-}) exceeds
 0.2 is split along its Y axis, and likewise a plane whose average radii
 gradient on its Y axis exceeds 0.2 is split along its X axis.  Readings:
 
-* "average radii gradient on the X axis" = (mean over the iterations since
-  the last split of |dL/dr^{x+}| and of |dL/dr^{x-}|) averaged over the two,
-  i.e. (A[x+] + A[x-]) / (2 n) with A the sum of magnitudes over n
-  iterations; the gradient is that of the loss as this project sums it;
+* "average radii gradient on the X axis" = (mean of |dL/dr^{x+}| and of
+  |dL/dr^{x-}| over the iterations since the last split in which the plane
+  took part in the render, i.e. had a radii gradient that is not all zero)
+  averaged over the two: (A[x+] + A[x-]) / (2 n_k) with A the sum of
+  magnitudes over those n_k iterations;
+* the gradient is that of the per-pixel mean loss (the summed loss of a view
+  divided by its pixel count, passed as `scale`).  The threshold 0.2 fixes
+  the scale: on the synthetic room most planes cross it at every split under
+  the summed loss, and none under the per-pixel mean averaged over all
+  iterations instead of the iterations the plane took part in;
 * "split along the Y axis": the cut runs parallel to the plane's Y axis
   through the middle of its X extent, giving two rectangles side by side
   along X, each with half the X extent (both radii along X equal to a
@@ -26,8 +32,10 @@ import numpy as np
 from .render import quat_to_frame
 
 
-def split_planes(center, quat, radii, acc, n_acc: int, thresh: float = 0.2):
-    """(center [K',3], quat [K',4], radii [K',4], parent [K']) in float64."""
+def split_planes(center, quat, radii, acc, cnt, scale=1.0, thresh: float = 0.2):
+    """(center [K',3], quat [K',4], radii [K',4], parent [K']) in float64.
+    acc [K,4]: summed |dL/dr|; cnt [K]: iterations with a gradient; scale:
+    scalar or [K], from the summed loss to the per-pixel mean."""
     center = np.asarray(center, np.float64)
     quat = np.asarray(quat, np.float64)
     radii = np.asarray(radii, np.float64)
@@ -35,20 +43,27 @@ def split_planes(center, quat, radii, acc, n_acc: int, thresh: float = 0.2):
     import torch
     vx, vy, _ = (t.numpy() for t in quat_to_frame(torch.as_tensor(quat)))
     out_c, out_q, out_r, parent = [], [], [], []
-    # the split decision is an integer decided in float32 (the kernels' precision)
+    # the split decision is an integer decided in float32 (the kernels'
+    # precision), as average > thresh written without a division:
+    # (A+ + A-) scale > thresh (2 n_k)
     f32 = np.float32
-    inv = f32(1.0) / (f32(2.0) * f32(n_acc))
-    for k in range(center.shape[0]):
-        gx = (f32(acc[k, 0]) + f32(acc[k, 1])) * inv
-        gy = (f32(acc[k, 2]) + f32(acc[k, 3])) * inv
+    K = center.shape[0]
+    cnt = np.asarray(cnt, np.int64).reshape(K)
+    scale = np.broadcast_to(np.asarray(scale, np.float64), (K,))
+    for k in range(K):
+        s = f32(scale[k])
+        ct = f32(thresh) * f32(2 * cnt[k])
+        # a plane with no iteration counted has no average and is kept
+        gx = (f32(acc[k, 0]) + f32(acc[k, 1])) * s if cnt[k] > 0 else f32(0)
+        gy = (f32(acc[k, 2]) + f32(acc[k, 3])) * s if cnt[k] > 0 else f32(0)
         rxp, rxm, ryp, rym = radii[k]
         # pieces along X: (offset of the center, radius +, radius -)
-        if gx > f32(thresh):
+        if gx > ct:
             mx, hx = 0.5 * (rxp - rxm), 0.25 * (rxp + rxm)
             xs = [(mx - hx, hx, hx), (mx + hx, hx, hx)]
         else:
             xs = [(0.0, rxp, rxm)]
-        if gy > f32(thresh):
+        if gy > ct:
             my, hy = 0.5 * (ryp - rym), 0.25 * (ryp + rym)
             ys = [(my - hy, hy, hy), (my + hy, hy, hy)]
         else:

@@ -72,9 +72,14 @@ _EXPORTS = {
                                          _P, _P, _P, _P]),
     "plane_render_bwd_lists": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,
                                          C.POINTER(PsParams), _P, _P, _P, _P, _P, _P, _P, _P, _P]),
-    "plane_grad_accumulate": (C.c_int, [_P, _P, C.c_int, _P]),
-    "plane_split": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_float, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "plane_grad_accumulate": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+    "plane_split": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_float, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ps_fit_schedule": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, C.c_int, _P, _P, _P]),
+    "depth_points_ws_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int]),
+    "depth_points": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_float, _P, _P, C.c_int, _P, _P,
+                               C.c_size_t, _P]),
+    "plane_init_points": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_float, _P, _P, _P, _P]),
+    "plane_init_sphere": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_float, _P, _P, _P, _P, _P]),
     "initnet_param_count": (C.c_int64, [C.c_int]),
     "initnet_packed_count": (C.c_int64, [C.c_int]),
     "initnet_forward_ws": (C.c_int64, [C.c_int, C.c_int]),

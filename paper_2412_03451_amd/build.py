@@ -42,9 +42,15 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# Per-file additions.  The scene initialisation turns floats into integers
+# (voxel indices) and must round every float64 operation on its own, as the
+# definition does: no contraction into fused multiply-adds in that file.
+FILE_FLAGS = {"scene_init.hip": ["-ffp-contract=off"]}
+
+
 def _compile(src: str, hipcc: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc, *FLAGS, "-c", src, "-o", obj]
+    cmd = [hipcc, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,8 +1,9 @@
 // plane_split / plane_grad_accumulate: the plane-splitting step of the
 // fitting loop (Sec. 3.3).  A plane whose average |dL/dr| over its two X
-// radii exceeds the threshold is cut in two across its X extent (halves side
-// by side along X), likewise for Y; both gives four children.  Children of a
-// plane are consecutive, in plane order: count -> exclusive scan (one
+// radii (per-pixel mean loss, averaged over the iterations the plane took
+// part in) exceeds the threshold is cut in two across its X extent (halves
+// side by side along X), likewise for Y; both gives four children.  Children
+// of a plane are consecutive, in plane order: count -> exclusive scan (one
 // workgroup) -> write.
 #include "ps_internal.h"
 
@@ -15,7 +16,8 @@ struct SplitArgs {
   const float* quat;
   const float* radii;
   const float* acc;
-  float inv2n;     // 1 / (2 n_acc)
+  const int* cnt;
+  const float* scale;   // per plane, or null for 1
   float thresh;
   int K;
   int* counts;     // [K + 1]
@@ -27,10 +29,16 @@ struct SplitArgs {
   int* k_out;
 };
 
+// The decision is taken in float32 without a division: the average
+// (acc+ + acc-) scale / (2 cnt) exceeds thresh.
 __device__ inline int split_bits(const SplitArgs& a, int k) {
   const float* g = a.acc + 4 * (size_t)k;
-  const bool sx = (g[0] + g[1]) * a.inv2n > a.thresh;
-  const bool sy = (g[2] + g[3]) * a.inv2n > a.thresh;
+  const float s = a.scale ? a.scale[k] : 1.f;
+  const int n = a.cnt[k];
+  if (n <= 0) return 0;   // no iteration counted: no average, kept
+  const float ct = a.thresh * (float)(2 * n);
+  const bool sx = (g[0] + g[1]) * s > ct;
+  const bool sy = (g[2] + g[3]) * s > ct;
   return (sx ? 1 : 0) | (sy ? 2 : 0);
 }
 
@@ -94,32 +102,40 @@ __global__ void split_write_kernel(SplitArgs a) {
     }
 }
 
-__global__ void grad_acc_kernel(const float* g, float* acc, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) acc[i] += fabsf(g[i]);
+__global__ void grad_acc_kernel(const float4* g, float4* acc, int* cnt, int K) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const float4 x = g[k];
+  float4 s = acc[k];
+  s.x += fabsf(x.x); s.y += fabsf(x.y); s.z += fabsf(x.z); s.w += fabsf(x.w);
+  acc[k] = s;
+  if (x.x != 0.f || x.y != 0.f || x.z != 0.f || x.w != 0.f) cnt[k] += 1;
 }
 
 }  // namespace
 
-extern "C" int plane_grad_accumulate(const float* g_radii, float* acc, int K, void* stream) {
-  if (K < 0 || (K > 0 && (!g_radii || !acc))) return ps_set_error(PS_ERR_INVALID, "plane_grad_accumulate: bad argument");
+extern "C" int plane_grad_accumulate(const float* g_radii, float* acc, int32_t* cnt, int K, void* stream) {
+  if (K < 0 || (K > 0 && (!g_radii || !acc || !cnt)))
+    return ps_set_error(PS_ERR_INVALID, "plane_grad_accumulate: bad argument");
+  if ((reinterpret_cast<uintptr_t>(g_radii) | reinterpret_cast<uintptr_t>(acc)) & 15)
+    return ps_set_error(PS_ERR_INVALID, "plane_grad_accumulate: g_radii and acc must be 16-byte aligned");
   if (K == 0) return PS_OK;
-  const int64_t n = 4 * (int64_t)K;
-  hipLaunchKernelGGL(grad_acc_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, g_radii,
-                     acc, n);
+  hipLaunchKernelGGL(grad_acc_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     (const float4*)g_radii, (float4*)acc, cnt, K);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
 
-extern "C" int plane_split(const float* center, const float* quat, const float* radii, const float* acc, int n_acc,
-                           float thresh, int K, float* out_center, float* out_quat, float* out_radii,
-                           int32_t* parent, int32_t* first, int32_t* k_out, int32_t* ws, void* stream) {
-  if (K < 1 || n_acc < 1 || !center || !quat || !radii || !acc || !out_center || !out_quat || !out_radii ||
-      !parent || !first || !k_out || !ws)
+extern "C" int plane_split(const float* center, const float* quat, const float* radii, const float* acc,
+                           const int32_t* cnt, const float* scale, float thresh, int K, float* out_center,
+                           float* out_quat, float* out_radii, int32_t* parent, int32_t* first, int32_t* k_out,
+                           int32_t* ws, void* stream) {
+  if (K < 1 || !center || !quat || !radii || !acc || !cnt || !out_center || !out_quat || !out_radii || !parent ||
+      !first || !k_out || !ws)
     return ps_set_error(PS_ERR_INVALID, "plane_split: bad argument");
   SplitArgs a;
   a.center = center; a.quat = quat; a.radii = radii; a.acc = acc;
-  a.inv2n = 1.f / (2.f * (float)n_acc);
+  a.cnt = cnt; a.scale = scale;
   a.thresh = thresh;
   a.K = K;
   a.counts = ws; a.first = first;

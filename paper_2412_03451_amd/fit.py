@@ -83,6 +83,8 @@ class BatchFit:
         self.scenes = list(scenes)
 
         def T(x):
+            if torch.is_tensor(x):
+                return x.detach().to(device=dev, dtype=torch.float32).contiguous().clone()
             return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev).clone()
 
         cs = [T(sc.center).reshape(-1, 3) for sc in self.scenes]
@@ -134,6 +136,7 @@ class BatchFit:
         self.jobs = jobs
         self.rend = Renderer(jobs, cams, device=dev, pair_capacity=pair_capacity or (1 << 16), params=self.params)
         self.acc = torch.zeros(self.K, 4, device=dev)   # sum of |dL/dr| since the last split
+        self.cnt = torch.zeros(self.K, dtype=torch.int32, device=dev)   # iterations with a radii gradient
         self.since_split = 0
         self.splits = []                                  # (iteration, planes before, planes after)
         self.graph = None
@@ -201,7 +204,7 @@ class BatchFit:
         m()
         gc, gq, gr = rend.backward(self.c, self.q, self.r, self.lam, gD, gN)
         if cfg.split_every:
-            grad_accumulate(gr, self.acc)
+            grad_accumulate(gr, self.acc, self.cnt)
         m()
         adam_step(self.c, self.q, self.r, gc, gq, gr, self.m, self.v, self.step_no, lr=cfg.lr, betas=cfg.betas,
                   eps=cfg.eps, r_min=cfg.r_min)
@@ -237,11 +240,20 @@ class BatchFit:
         self.graph = g
 
     def state(self):
-        return [t.clone() for t in (self.c, self.q, self.r, self.m, self.v, self.ite, self.acc)]
+        return [t.clone() for t in (self.c, self.q, self.r, self.m, self.v, self.ite, self.acc, self.cnt)]
 
     def restore(self, st):
-        for dst, src in zip((self.c, self.q, self.r, self.m, self.v, self.ite, self.acc), st):
+        for dst, src in zip((self.c, self.q, self.r, self.m, self.v, self.ite, self.acc, self.cnt), st):
             dst.copy_(src)
+
+    def _split_scale(self):
+        """Per plane: 1 / pixels per view of its scene, the factor from the
+        summed loss of loss_depth_normal to the per-pixel mean that the
+        splitting threshold is read against."""
+        sc = np.empty(self.K, np.float32)
+        for i, (W, H) in enumerate(self.size):
+            sc[int(self.k_off[i]):int(self.k_off[i + 1])] = 1.0 / (W * H)
+        return torch.from_numpy(sc).to(self.device)
 
     def _split(self):
         """Plane splitting (Sec. 3.3) of every scene; the plane set, the Adam
@@ -249,14 +261,18 @@ class BatchFit:
         the jobs' plane ranges and the workspace are rebuilt, and the step is
         captured again at the next run."""
         K0 = self.K
-        c, q, r, parent, first = split_planes(self.c, self.q, self.r, self.acc, self.since_split,
+        c, q, r, parent, first = split_planes(self.c, self.q, self.r, self.acc, self.cnt, self._split_scale(),
                                               self.cfg.split_thresh)
         K1 = int(c.shape[0])
         self.splits.append((int(self.ite.item()), K0, K1))
         self.since_split = 0
-        self.acc = torch.zeros(K1, 4, device=self.device)
         if K1 == K0:
+            # same plane set: the captured step keeps its buffers
+            self.acc.zero_()
+            self.cnt.zero_()
             return
+        self.acc = torch.zeros(K1, 4, device=self.device)
+        self.cnt = torch.zeros(K1, dtype=torch.int32, device=self.device)
         first_h = first.cpu().numpy()
         pl = parent.long()
         single = ((first[1:] - first[:-1])[pl] == 1).to(torch.float32)

@@ -280,15 +280,18 @@ def adam_step(center, quat, radii, g_center, g_quat, g_radii, m, v, step, lr=(1e
                                lr[0], lr[1], lr[2], betas[0], betas[1], eps, r_min, _stream()))
 
 
-def grad_accumulate(g_radii, acc):
-    """acc += |g_radii| (plane_grad_accumulate)."""
+def grad_accumulate(g_radii, acc, cnt):
+    """acc += |g_radii|, cnt += 1 where the radii gradient is not all zero
+    (plane_grad_accumulate)."""
     lib = _lib.load()
-    check(lib.plane_grad_accumulate(_ptr(g_radii), _ptr(acc), int(g_radii.shape[0]), _stream()))
+    check(lib.plane_grad_accumulate(_ptr(g_radii), _ptr(acc), _ptr(cnt), int(g_radii.shape[0]), _stream()))
 
 
-def split_planes(center, quat, radii, acc, n_acc: int, thresh: float = 0.2):
+def split_planes(center, quat, radii, acc, cnt, scale=None, thresh: float = 0.2):
     """Plane splitting (plane_split): (center, quat, radii, parent, first) of
-    the new plane set, trimmed to its size (one host read of the count)."""
+    the new plane set, trimmed to its size (one host read of the count).
+    scale: per-plane device float tensor (summed loss -> per-pixel mean), or
+    None for 1."""
     lib = _lib.load()
     K = int(center.shape[0])
     dev = center.device
@@ -299,7 +302,8 @@ def split_planes(center, quat, radii, acc, n_acc: int, thresh: float = 0.2):
     first = torch.empty(K + 1, dtype=torch.int32, device=dev)
     k_out = torch.empty(1, dtype=torch.int32, device=dev)
     ws = torch.empty(K + 1, dtype=torch.int32, device=dev)
-    check(lib.plane_split(_ptr(center), _ptr(quat), _ptr(radii), _ptr(acc), int(n_acc), float(thresh), K, _ptr(oc),
-                          _ptr(oq), _ptr(orr), _ptr(parent), _ptr(first), _ptr(k_out), _ptr(ws), _stream()))
+    check(lib.plane_split(_ptr(center), _ptr(quat), _ptr(radii), _ptr(acc), _ptr(cnt), _ptr(scale), float(thresh), K,
+                          _ptr(oc), _ptr(oq), _ptr(orr), _ptr(parent), _ptr(first), _ptr(k_out), _ptr(ws),
+                          _stream()))
     n = int(k_out.item())
     return oc[:n].contiguous(), oq[:n].contiguous(), orr[:n].contiguous(), parent[:n].contiguous(), first

@@ -301,3 +301,23 @@ def room_batch_specs(n_rooms: int, seed: int = 0, k_range=(200, 4000), view_rang
         W, H, f = (320, 240, 288.5) if small else (640, 480, 577.0)
         out.append({"seed": seed + i, "K": K, "views": V, "width": W, "height": H, "f": f})
     return out
+
+
+# ----------------------------------------------------------------------------
+# random depth / normal maps (scene-initialisation checks)
+# ----------------------------------------------------------------------------
+
+def random_depth_maps(width: int, height: int, seed: int, bg_frac: float = 0.1):
+    """Depth [H, W] and camera-frame normal [3, H, W] maps in the renderer's
+    layout: per pixel a depth t ~ U[0.5, 4], a random unit normal n and a
+    coverage w ~ U[0.3, 1] give D = w t and N = w n (a pixel partly covered by
+    one plane); a fraction bg_frac of the pixels is background (D = 0)."""
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0.5, 4.0, size=(height, width))
+    n = rng.normal(size=(3, height, width))
+    n /= np.linalg.norm(n, axis=0, keepdims=True)
+    w = rng.uniform(0.3, 1.0, size=(height, width))
+    D = (w * t).astype(np.float32)
+    N = (w[None] * n).astype(np.float32)
+    D[rng.uniform(size=(height, width)) < bg_frac] = 0.0
+    return D, N

@@ -14,7 +14,7 @@ import torch
 
 import oracle
 from oracle import depth_init as di
-from synth.scenes import Camera, quat_mul
+from synth.scenes import Camera, quat_mul, random_depth_maps
 
 
 def _rot_camera(seed, W=40, H=30, f=35.0):
@@ -27,17 +27,8 @@ def _rot_camera(seed, W=40, H=30, f=35.0):
                   rng.normal(size=3).astype(np.float32))
 
 
-def _random_maps(cam, seed, stride=1):
-    rng = np.random.default_rng(seed)
-    H, W = cam.height, cam.width
-    t = rng.uniform(0.5, 4.0, size=(H, W))
-    n = rng.normal(size=(3, H, W))
-    n /= np.linalg.norm(n, axis=0, keepdims=True)
-    w = rng.uniform(0.3, 1.0, size=(H, W))            # coverage; < 0.5 is rejected
-    D = (w * t).astype(np.float32)
-    N = (w[None] * n).astype(np.float32)
-    D[rng.uniform(size=(H, W)) < 0.1] = 0.0            # background pixels
-    return D, N
+def _random_maps(cam, seed):
+    return random_depth_maps(cam.width, cam.height, seed)
 
 
 def test_back_projection_reprojects_to_the_pixel():

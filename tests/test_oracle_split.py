@@ -26,7 +26,7 @@ def test_split_x_gives_two_halves_covering_the_parent():
     c = np.array([1.0, 2.0, 3.0])
     r = np.array([0.5, 0.3, 0.2, 0.4])
     acc = np.array([[3.0, 1.0, 0.0, 0.0]])        # average over x+, x-: (3 + 1) / (2 * 4) = 0.5
-    cc, qq, rr, par = split_planes(c[None], q[None], r[None], acc, 4, 0.2)
+    cc, qq, rr, par = split_planes(c[None], q[None], r[None], acc, [4], 1.0, 0.2)
     assert list(par) == [0, 0]
     b0, b1 = _world_box(cc[0], qq[0], rr[0]), _world_box(cc[1], qq[1], rr[1])
     P = _world_box(c, q, r)
@@ -45,7 +45,7 @@ def test_thresholds_and_four_children():
     acc = np.array([[0.19, 0.2, 0.0, 0.0],        # average 0.195 <= 0.2: no split
                     [0.0, 0.0, 0.41, 0.41],       # y only: two children along y
                     [1.0, 1.0, 1.0, 1.0]])        # both: four
-    cc, qq, rr, par = split_planes(c, q, r, acc, 1, 0.2)
+    cc, qq, rr, par = split_planes(c, q, r, acc, [1, 1, 1], 1.0, 0.2)
     assert list(par) == [0, 1, 1, 2, 2, 2, 2]
     assert np.allclose(cc[0], 0) and np.allclose(rr[0], r[0])
     assert np.allclose(cc[1], [0, -0.1, 0]) and np.allclose(cc[2], [0, 0.1, 0])
@@ -55,3 +55,20 @@ def test_thresholds_and_four_children():
     assert np.isclose(sum(areas), (0.8) * (0.4))
     assert np.allclose(sorted(map(tuple, np.round(cc[3:, :2], 12))),
                        sorted([(-0.2, -0.1), (-0.2, 0.1), (0.2, -0.1), (0.2, 0.1)]))
+
+
+def test_average_over_the_iterations_a_plane_took_part_in():
+    """The average divides by each plane's own count and applies its scale;
+    a plane that never took part does not split; the comparison is strict."""
+    q = np.array([[1.0, 0, 0, 0]] * 5)
+    c = np.zeros((5, 3))
+    r = np.array([[0.4, 0.4, 0.2, 0.2]] * 5)
+    acc = np.array([[30.0, 30.0, 0, 0]] * 5)
+    cnt = [100, 200, 0, 100, 150]               # averages 0.3, 0.15, -, 0.3 (scaled 0.03), 0.2 (not > 0.2)
+    scale = [1.0, 1.0, 1.0, 0.1, 1.0]
+    _, _, _, par = split_planes(c, q, r, acc, cnt, scale, 0.2)
+    assert list(par) == [0, 0, 1, 2, 3, 4]
+    # the same sums over a per-pixel mean: scale = 1 / pixels of the view
+    acc2 = np.array([[0.3 * 2 * 50 * 307200, 0.0, 0, 0]])
+    _, _, _, par = split_planes(c[:1], q[:1], r[:1], acc2, [50], 1.0 / 307200, 0.2)
+    assert list(par) == [0, 0]

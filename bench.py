@@ -395,7 +395,8 @@ def init_ablation_bench(args):
     iterations) from three initialisations of 2000 planes: from the depth
     maps (Sec. 3.1: fused points at stride 4 and 2 cm voxels), on the scene's
     bounding sphere (Sec. 4.3, radii 0.05), and the noisy ground truth of the
-    throughput workload.  Depth L1 over all views at lambda = 300 every 500
+    throughput workload; the depth initialisation is also fitted without
+    splitting.  Depth L1 over all views at lambda = 300 every 500
     iterations; fit wall-times exclude the evaluations; the initialisation
     kernels are timed on their own."""
     import torch
@@ -425,10 +426,12 @@ def init_ablation_bench(args):
     sphere_init, sphere_ms = timed(lambda: si.init_sphere(pts, K, seed=0))
     log(f"depth_points: {n} fused points from {V} views in {pts_ms:.2f} ms; plane_init_points {planes_ms:.3f} ms; "
         f"plane_init_sphere {sphere_ms:.3f} ms")
-    inits = {"depth": depth_init, "sphere": sphere_init, "noisy-gt": (init.center, init.quat, init.radii)}
+    runs = {"depth": (depth_init, 1000), "depth, no splitting": (depth_init, 0), "sphere": (sphere_init, 1000),
+            "noisy-gt": ((init.center, init.quat, init.radii), 1000)}
     out = {}
-    for name, planes in inits.items():
-        fit = SceneFit(*planes, cams, tD, tN, cfg=FitConfig(check_every=250, split_every=1000, split_thresh=0.2))
+    for name, (planes, split_every) in runs.items():
+        fit = SceneFit(*planes, cams, tD, tN,
+                       cfg=FitConfig(check_every=250, split_every=split_every, split_thresh=0.2))
         curve = [[0, round(fit.depth_l1(lam=300.0), 5)]]
         fit_s = 0.0
         for ck in range(500, args.fit_iters + 1, 500):

@@ -154,20 +154,47 @@ inline __host__ __device__ size_t align256(size_t x) { return (x + 255) & ~size_
 // wave64 helpers
 __device__ inline int lane_id() { return __lane_id(); }
 
+// Cross-lane exchanges that stay on the VALU (no LDS round trip): DPP quad
+// permutes (lane ^ 1, lane ^ 2) and row mirrors (lane ^ 7 inside 8 lanes,
+// lane ^ 15 inside a 16-lane row), and the gfx950 permlane swaps, which
+// exchange the odd 16-lane rows of one register with the even rows of
+// another (lane ^ 16) or the upper half of one with the lower half of
+// another (lane ^ 32).  The six partners reach every lane of the wave.
+// Every lane must be active.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppMirror16 = 0x140, kDppMirror8 = 0x141;
+template <int CTRL>
+__device__ inline int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ inline float dpp_float(float v) {
+  return __int_as_float(dpp_int<CTRL>(__float_as_int(v)));
+}
+
+// All-reduce over the wave; every lane receives the same bits (each step
+// combines a lane with its partner by a commutative operation).
+template <class T, class Op>
+__device__ inline T wave_allreduce(T v, Op op) {
+  static_assert(sizeof(T) == 4, "32-bit values");
+  auto bits = [](T x) { return __builtin_bit_cast(unsigned, x); };
+  auto back = [](unsigned x) { return __builtin_bit_cast(T, x); };
+  v = op(v, back((unsigned)dpp_int<kDppXor1>((int)bits(v))));
+  v = op(v, back((unsigned)dpp_int<kDppXor2>((int)bits(v))));
+  v = op(v, back((unsigned)dpp_int<kDppMirror8>((int)bits(v))));
+  v = op(v, back((unsigned)dpp_int<kDppMirror16>((int)bits(v))));
+  const auto r16 = __builtin_amdgcn_permlane16_swap(bits(v), bits(v), false, false);
+  v = op(back(r16[0]), back(r16[1]));
+  const auto r32 = __builtin_amdgcn_permlane32_swap(bits(v), bits(v), false, false);
+  return op(back(r32[0]), back(r32[1]));
+}
 __device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return wave_allreduce(v, [](float x, float y) { return x + y; });
 }
 __device__ inline int wave_min_int(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
+  return wave_allreduce(v, [](int x, int y) { return min(x, y); });
 }
 __device__ inline int wave_max_int(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+  return wave_allreduce(v, [](int x, int y) { return max(x, y); });
 }
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -243,7 +270,7 @@ __device__ inline long long block_scan(const int* __restrict__ in, int* __restri
     __syncthreads();
   }
   // max over the workgroup
-  for (int o = 32; o >= 1; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+  mx = wave_max_int(mx);
   if (lane == 0) lds_wave[wid] = mx;
   __syncthreads();
   if (tid == 0) {

@@ -438,7 +438,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   walk<P>(a, c, s, lam5, delta, evals, steps);
   if (diag) {
     int commits = s.count;
-    for (int o = 32; o >= 1; o >>= 1) commits += __shfl_xor(commits, o, 64);
+    commits = wave_allreduce(commits, [](int x, int y) { return x + y; });
     if (threadIdx.x == 0) {
       dg[D_EVALS] = evals;
       dg[D_COMMITS] = commits;
@@ -471,35 +471,40 @@ struct BwdLds {
 };
 
 // Sum 16 per-lane values over the wave by recursive halving: each exchange
-// step sends half of the values still held, so 17 lane exchanges replace
-// 16 x 6.  On return lane 4 q + r (r < 4) holds the total of value q, summed
-// in a fixed order.  The steps are unrolled by templates so that every array
-// index is a constant (a select between two elements would otherwise become
-// a dynamically indexed register array).
-template <int I, int H, int O>
-struct HalveStep {
-  static __device__ __forceinline__ void run(float (&v)[16], bool up) {
-    const float lo = v[I], hi = v[I + H];
-    const float send = up ? lo : hi;
-    const float keep = up ? hi : lo;
-    v[I] = keep + __shfl_xor(send, O, 64);
-    HalveStep<I + 1, H, O>::run(v, up);
-  }
-};
-template <int H, int O>
-struct HalveStep<H, H, O> {
-  static __device__ __forceinline__ void run(float (&)[16], bool) {}
-};
-
+// step sends half of the values still held (permlane swaps across the wave
+// halves and the 16-lane rows, then DPP mirrors inside the rows, then quad
+// permutes), 8 + 4 + 2 + 1 + 2 exchanges in all, none through LDS.  On return
+// lane 4 q + r (r < 4) holds the total of value q, summed in a fixed order;
+// the four lanes of a quad hold the same bits.
 __device__ __forceinline__ float wave_sum16(float (&v)[16]) {
   const int lane = threadIdx.x;
-  HalveStep<0, 8, 32>::run(v, lane & 32);
-  HalveStep<0, 4, 16>::run(v, lane & 16);
-  HalveStep<0, 2, 8>::run(v, lane & 8);
-  HalveStep<0, 1, 4>::run(v, lane & 4);
-  float r = v[0];
-  r += __shfl_xor(r, 2, 64);
-  r += __shfl_xor(r, 1, 64);
+  // lane ^ 32: lanes 0-31 keep values 0-7, lanes 32-63 values 8-15
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  // lane ^ 16: lanes with bit 4 clear keep the first 4 of their 8, the others the last 4
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 4]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  // lane ^ 15 (row mirror): bit 3 picks 2 of the 4
+  const bool u8 = lane & 8;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float send = u8 ? v[i] : v[i + 2];
+    const float keep = u8 ? v[i + 2] : v[i];
+    v[i] = keep + dpp_float<kDppMirror16>(send);
+  }
+  // lane ^ 7 (half-row mirror): bit 2 picks 1 of the 2
+  const bool u4 = lane & 4;
+  const float send = u4 ? v[0] : v[1];
+  const float keep = u4 ? v[1] : v[0];
+  float r = keep + dpp_float<kDppMirror8>(send);
+  r += dpp_float<kDppXor2>(r);
+  r += dpp_float<kDppXor1>(r);
   return r;
 }
 
@@ -862,8 +867,14 @@ __global__ __launch_bounds__(64) void bwd_reduce_kernel(RenderArgs a) {
       A[8] += r2.x; A[9] += r2.y; A[10] += r2.z; A[11] += r2.w;
       A[12] += r3.x;
     }
+    {
+      float V[16];
 #pragma unroll
-    for (int q = 0; q < 13; ++q) A[q] = wave_sum(A[q]);
+      for (int q = 0; q < 16; ++q) V[q] = q < 13 ? A[q] : 0.f;
+      const float tot = wave_sum16(V);   // lane 4 q holds the sum of A[q]
+#pragma unroll
+      for (int q = 0; q < 13; ++q) A[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), 4 * q));
+    }
     const ps_camera cam = a.cams[sl.cam];
     Frame f;
     if (!plane_frame(a.center, a.quat, k, cam, f)) continue;

@@ -32,17 +32,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_HBM_GBS = 8000.0
-MI355X_FP64_VECTOR_TFLOPS = 78.6   # = non-packed fp32 FMA rate; packed fp32 is not used
+# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane
+# operations per second (one non-packed fp32 or fp64 operation per lane per
+# cycle; packed fp32 is not used; an FMA counts as one operation).
+MI355X_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic flops per composited (pixel, plane) hit (Sec. 3.2 arithmetic):
-#   ray-plane intersection and in-plane coordinates (Eq. 4, 6): den (2 FMA),
-#   t = h/den (1 div), x = o + t d (3 FMA), x - p (3), P_X, P_Y (2 x 3 FMA) -> 26
-#   splat weight (Eq. 7-9): 2 |P|, 2 subtractions, min, sigmoid (exp, add, div) -> 8
-#   compositing (Eq. 11-13): T w, D += T w t, N += T w n (3 FMA), T *= 1 - w -> 12
-FLOPS_FWD_PER_HIT = 46
-# backward per composited hit: recompute (46) + suffix walk (4) + chain to 13
-# accumulators (~30) -> 80, plus the wave reduction of the accumulators
-FLOPS_BWD_PER_HIT = 80
+# Algorithmic work of the render kernels, in lane operations (Sec. 3.2):
+#   per evaluated (pixel, candidate) pair: three affine forms in the pixel
+#   (den, and the numerators of P_X, P_Y), the reciprocal of den, t, P_X, P_Y,
+#   branch radii, |P|, two differences, the minimum, the filter test
+#   -> about 16 operations and 1 transcendental
+OPS_PER_EVAL = 17
+#   per composited hit: the weight (exp, reciprocal, ~4 operations), the
+#   compositing of depth, normal and transmittance (~6), the ordered insertion (~4)
+OPS_PER_HIT_FWD = 16
+#   backward per composited hit: the forward's work for the hit in the
+#   recomputing walk, its evaluation again in the gradient pass (17), and the
+#   chain rule to the 13 per-pair accumulators (~40)
+OPS_PER_HIT_BWD = OPS_PER_HIT_FWD + OPS_PER_EVAL + 40
 
 
 def log(*a):
@@ -590,22 +597,24 @@ def main():
 
     pix = V * W * H
     value = pix * K / (ms_step * 1e-3) / 1e6
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel: algorithmic lane operations per launch
+    # (evaluated pairs and composited hits of the step's view) / launch time
     dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
-    per_hit = FLOPS_FWD_PER_HIT if dom == "fwd" else FLOPS_BWD_PER_HIT
-    achieved = hits * per_hit / (phase_ms[dom] * 1e-3) / 1e12
+    per_hit = OPS_PER_HIT_FWD if dom == "fwd" else OPS_PER_HIT_BWD
+    ops = evals * OPS_PER_EVAL + hits * per_hit
+    achieved = ops / (phase_ms[dom] * 1e-3) / 1e12
     traffic = measured_traffic(dom)
     roof = {
         "kernel": "render_fwd_kernel" if dom == "fwd" else "render_bwd_kernel+bwd_reduce_kernel",
         "bound": "alu",
         "achieved": round(achieved, 4),
-        "peak": MI355X_FP64_VECTOR_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / MI355X_FP64_VECTOR_TFLOPS, 5),
+        "peak": round(MI355X_VALU_TOPS, 2),
+        "unit": "T lane-op/s",
+        "frac": round(achieved / MI355X_VALU_TOPS, 5),
         "traffic": traffic,
         "launch_ms": round(phase_ms[dom], 4),
-        "algorithmic_units": f"{hits} composited hits x {per_hit} flops",
-        "pairs_evaluated": evals,
+        "algorithmic_units": f"{evals} evaluated pairs x {OPS_PER_EVAL} + {hits} composited hits x {per_hit} "
+                             f"lane operations",
     }
     n_items = max(1, int(fit.rend.L.n_items))
     out = {

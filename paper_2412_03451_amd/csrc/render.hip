@@ -114,34 +114,16 @@ __device__ inline int item_setup(const RenderArgs& a, int item, ItemCtx& c) {
 }
 
 // Sorted buffer of pending hits (ascending (t, record)), in registers.  Each
-// entry keeps the float32 a* of the hit (weights are formed at commit time),
-// its list position and NP payload floats that the sink needs at commit time
-// (the normal for the forward, c = gD t + gN.n for the backward), so a commit
-// never waits on memory.
-template <int P, int NP>
+// entry keeps the float32 a* of the hit (weights are formed at commit time)
+// and its list position; what the sink needs of the plane (its normal) is
+// read back at commit time by list position, from the staged batch when the
+// hit came from it.  Four registers per entry keep insertions and pops short.
+template <int P>
 struct Pending {
   float t[P];
   int r[P];
   float a[P];
   int pos[P];
-  // payload as separate 1-D arrays (NP <= 3): small arrays stay in registers
-  float p0[P], p1[P], p2[P];
-  __device__ __forceinline__ void plmove(int dst, int src) {
-    if constexpr (NP > 0) p0[dst] = p0[src];
-    if constexpr (NP > 1) p1[dst] = p1[src];
-    if constexpr (NP > 2) p2[dst] = p2[src];
-  }
-  __device__ __forceinline__ void plset(int k, const float* v) {
-    if constexpr (NP > 0) p0[k] = v[0];
-    if constexpr (NP > 1) p1[k] = v[1];
-    if constexpr (NP > 2) p2[k] = v[2];
-  }
-  __device__ __forceinline__ void plget(int k, float* v) const {
-    if constexpr (NP > 0) v[0] = p0[k];
-    if constexpr (NP > 1) v[1] = p1[k];
-    if constexpr (NP > 2) v[2] = p2[k];
-  }
-  static_assert(NP <= 3, "payload of at most 3 floats");
   int n;
   float ot; int orr;   // key of the opaque pending hit, +inf if none
   float tt; int tr;    // key of the last pending hit
@@ -154,7 +136,7 @@ struct Pending {
 
   // Keep the `cap` nearest hits (cap = hits still allowed by M, or fewer).
   // false: the buffer is full and the hit may still be among the nearest cap.
-  __device__ bool insert(float nt, int nr, float na, bool opq, int npos, const float* npl, int cap) {
+  __device__ bool insert(float nt, int nr, float na, bool opq, int npos, int cap) {
     if (key_less(ot, orr, nt, nr)) return true;              // behind an opaque hit
     if (n >= cap) {
       if (n == 0 || !key_less(nt, nr, tt, tr)) return true;  // not among the nearest cap
@@ -171,13 +153,11 @@ struct Pending {
     for (int k = P - 1; k >= 1; --k)
       if (k > at && k <= n) {
         t[k] = t[k - 1]; r[k] = r[k - 1]; a[k] = a[k - 1]; pos[k] = pos[k - 1];
-        plmove(k, k - 1);
       }
 #pragma unroll
     for (int k = 0; k < P; ++k)
       if (k == at) {
         t[k] = nt; r[k] = nr; a[k] = na; pos[k] = npos;
-        plset(k, npl);
       }
     n += 1;
     if (opq) {   // everything behind an opaque hit is hidden
@@ -190,13 +170,11 @@ struct Pending {
     return true;
   }
 
-  __device__ void pop(float& ft, int& fr, float& fa, int& fpos, float* fpl) {
+  __device__ void pop(float& ft, int& fr, float& fa, int& fpos) {
     ft = t[0]; fr = r[0]; fa = a[0]; fpos = pos[0];
-    plget(0, fpl);
 #pragma unroll
     for (int k = 0; k + 1 < P; ++k) {
       t[k] = t[k + 1]; r[k] = r[k + 1]; a[k] = a[k + 1]; pos[k] = pos[k + 1];
-      plmove(k, k + 1);
     }
     n -= 1;
     if (n == 0) { tt = -INFINITY; tr = -1; ot = INFINITY; orr = 0x7fffffff; }
@@ -254,17 +232,40 @@ __device__ inline void staged(const StageLds& S, int j, RecHead& rec, float n[3]
   n[0] = h6.x; n[1] = h6.y; n[2] = h6.z;
 }
 
+// Normal of the candidate at list position pos (relative to the item's list):
+// from the staged batch starting at list index sb when it is there, else
+// from the record copy in memory (a hit kept pending across batches).
+__device__ inline void cand_normal(const RenderArgs& a, const ItemCtx& c, int sb, int pos, float n[3]) {
+  const int j = c.b + pos - sb;
+  float4 h;
+  if (j >= 0 && j < 64)
+    h = c.stage->head[6][j];
+  else
+    h = reinterpret_cast<const float4*>(&a.recs_s[c.b + pos])[6];
+  n[0] = h.x; n[1] = h.y; n[2] = h.z;
+}
+
+// Pop the nearest pending hit and hand it to the sink with its payload.
+template <int P, class Sink>
+__device__ __forceinline__ void commit_next(const RenderArgs& a, const ItemCtx& c, int sb, Pending<P>& pd,
+                                            Sink& sink, float& lt, int& lr) {
+  float ft, fa; int fr, fp;
+  pd.pop(ft, fr, fa, fp);
+  float nrm[3], pl[Sink::NP];
+  cand_normal(a, c, sb, fp, nrm);
+  sink.payload(ft, nrm, pl);
+  sink.commit(ft, fa, fp, pl);
+  lt = ft; lr = fr;
+}
+
 // Commit the pending hits nearer than `bound` (no later candidate can precede them).
-template <class PD, class Sink>
-__device__ __forceinline__ void drain(PD& pd, Sink& sink, int M, float bound, bool& done, float& lt, int& lr,
-                                      float* fpl) {
+template <int P, class Sink>
+__device__ __forceinline__ void drain(const RenderArgs& a, const ItemCtx& c, int sb, Pending<P>& pd, Sink& sink,
+                                      int M, float bound, bool& done, float& lt, int& lr) {
   bool want = !done && pd.n > 0 && pd.t[0] < bound;
   if (ballot(want)) {
     while (want) {
-      float ft, fa; int fr, fp;
-      pd.pop(ft, fr, fa, fp, fpl);
-      sink.commit(ft, fa, fp, fpl);
-      lt = ft; lr = fr;
+      commit_next(a, c, sb, pd, sink, lt, lr);
       if (sink.finished(M)) { done = true; break; }
       want = pd.n > 0 && pd.t[0] < bound;
     }
@@ -272,19 +273,18 @@ __device__ __forceinline__ void drain(PD& pd, Sink& sink, int M, float bound, bo
 }
 
 // Walk the tile list of one 8x8 block and hand every committed hit, in exact
-// per-ray order, to sink.commit(t, a*, list position, payload).
+// per-ray order, to sink.commit(t, a*, list position, payload), the payload
+// formed by sink.payload(t, normal of the plane).
 template <int P, class Sink>
 __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink& sink, float lam5,
                                      double delta, long long& evals, long long& steps) {
-  constexpr int NP = Sink::NP;
-  Pending<P, NP> pd;
+  Pending<P> pd;
   pd.reset();
   bool slow = (a.flags & 1) && c.inimg;
   bool done = !c.inimg || slow || sink.finished(a.M);
   float lt = -INFINITY;
   int lr = -1;
   StageLds& S = *c.stage;
-  float fpl[NP];
   bool stop = ballot(!done) == 0;
   for (int base = c.b; base < c.e && !stop; base += 64) {
     uint64_t ovm = stage_batch<Sink::BWD>(a, c, base);
@@ -304,19 +304,30 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
       evals += __popcll(ballot(!done));
       const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
       const bool hit = g.ok && !done;
-      if (ballot(hit)) {
-        if (hit) {
-          const float t32 = (float)g.t;
-          const float a32 = (float)g.a;
-          float pl[NP];
+      const float t32 = (float)g.t;
+      const float a32 = (float)g.a;
+      // nothing pending and no later candidate can come before it: commit
+      // now (what inserting and draining to tlb_next would do)
+      const bool now = hit && pd.n == 0 && t32 < tlb_next;
+      if (ballot(now)) {
+        if (now) {
+          float pl[Sink::NP];
           sink.payload(t32, nrm, pl);
-          if (!pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, pl, a.M - sink.count)) {
+          sink.commit(t32, a32, base + j - c.b, pl);
+          lt = t32; lr = ri;
+          if (sink.finished(a.M)) done = true;
+        }
+      }
+      const bool ins = hit && !now;
+      if (ballot(ins)) {
+        if (ins) {
+          if (!pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, a.M - sink.count)) {
             slow = true;
             done = true;
           }
         }
       }
-      drain(pd, sink, a.M, tlb_next, done, lt, lr, fpl);
+      drain(a, c, base, pd, sink, a.M, tlb_next, done, lt, lr);
       if (ballot(!done) == 0) {
         stop = true;
         break;
@@ -324,7 +335,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
     }
     // pending hits below the bound of everything after this batch
     if (!stop) {
-      drain(pd, sink, a.M, tlb_after, done, lt, lr, fpl);
+      drain(a, c, base, pd, sink, a.M, tlb_after, done, lt, lr);
       stop = ballot(!done) == 0;
     }
     __syncthreads();
@@ -342,8 +353,10 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
     pd.reset();
     const int cap = min(P, a.M - sink.count);
     bool stop2 = false;
+    int sb = c.b;   // the batch left staged in LDS
     for (int base = c.b; base < c.e && !stop2; base += 64) {
       uint64_t ovm = stage_batch<Sink::BWD>(a, c, base);
+      sb = base;
       while (ovm) {
         const int j = __ffsll((unsigned long long)ovm) - 1;
         ovm &= ovm - 1;
@@ -364,23 +377,14 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
         if (need && g.ok) {
           const float t32 = (float)g.t;
           const float a32 = (float)g.a;
-          if (key_less(lt, lr, t32, ri)) {
-            float pl[NP];
-            sink.payload(t32, nrm, pl);
-            pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, pl, cap);
-          }
+          if (key_less(lt, lr, t32, ri)) pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, cap);
         }
       }
       __syncthreads();
     }
     if (act) {
       const bool exhausted = pd.n < cap && pd.ot == INFINITY;
-      while (pd.n > 0 && !sink.finished(a.M)) {
-        float ft, fa; int fr, fp;
-        pd.pop(ft, fr, fa, fp, fpl);
-        sink.commit(ft, fa, fp, fpl);
-        lt = ft; lr = fr;
-      }
+      while (pd.n > 0 && !sink.finished(a.M)) commit_next(a, c, sb, pd, sink, lt, lr);
       if (exhausted) slow = false;
     }
   }

@@ -29,7 +29,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
                         (long long)pair_capacity);
   memset(out, 0, sizeof(*out));
   int64_t rec = 0, tiles = 0, items = 0, pix = 0;
-  int max_sub = 1, n_planes = 0, max_items = 0;
+  int max_sub = 1, n_planes = 0, max_items = 0, max_chunks = 1;
   for (int s = 0; s < n_slots; ++s) {
     ps_slot& sl = slots[s];
     if (sl.plane_begin < 0 || sl.plane_end < sl.plane_begin)
@@ -54,6 +54,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
     tiles += (int64_t)sl.tiles_x * sl.tiles_y;
     items += (int64_t)sl.tiles_x * sl.tiles_y * sub;
     if (sl.tiles_x * sl.tiles_y * sub > max_items) max_items = sl.tiles_x * sl.tiles_y * sub;
+    if ((sl.tiles_x * sl.tiles_y + 63) / 64 > max_chunks) max_chunks = (sl.tiles_x * sl.tiles_y + 63) / 64;
     pix += (int64_t)sl.width * sl.height;
     if (sl.plane_end > n_planes) n_planes = sl.plane_end;
   }
@@ -67,6 +68,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
   out->pair_capacity = pair_capacity;
   out->max_sub = max_sub;
   out->max_items = max_items;
+  out->max_chunks = max_chunks;
   out->n_planes = n_planes;
   const size_t R = (size_t)rec, T = (size_t)tiles, C = (size_t)pair_capacity;
   const size_t sizes[PS_NUM_REGIONS] = {
@@ -90,6 +92,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
       sizeof(ps::Rec) * C,             // R_RECS_S
       8 * ps::D_NUM * ((size_t)items + 1),  // R_DIAG
       4 * (T + 1),                     // R_TILEPOS
+      4 * (R * (size_t)max_chunks + 1),  // R_CHUNK_CNT
   };
   size_t off = 0;
   for (int i = 0; i < PS_NUM_REGIONS; ++i) {

@@ -36,6 +36,8 @@ struct BinArgs {
   const Rec* recs;
   const BinRec* brecs;
   int* rec_cnt;
+  int* chunk_cnt;   // [R][CH]
+  int CH;           // chunks of 64 tiles per record, maximum over jobs
   int* rec_off;
   int* tile_cnt;
   int* tile_off;
@@ -90,30 +92,40 @@ __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot
 // One wave per record: the 64 lanes test the record's candidate tiles in
 // row-major order, 64 at a time (a plane near the camera can cover every
 // tile of the image, so one thread per record would serialise it).
+// Waves over (record, group of 64 tiles of its tile box): grid (R / 4, G),
+// wave (r, y) takes the groups y, y + G, ... of record r, so records with big
+// boxes (planes close to the camera, wide fringes at small lambda) spread
+// over up to G waves instead of one long loop.  Each group's count goes to
+// chunk_cnt for the emit pass; rec_cnt (cleared with the tile counts)
+// accumulates the record's total.
+constexpr int kChunkWaves = 8;
+
 __global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= a.R) return;
   const BinRec& br = a.brecs[r];
-  int cnt = 0;
-  if (br.nedge != 0) {
-    const Rec& rec = a.recs[r];
-    const ps_slot& sl = a.slots[br.slot];
-    const int nx = br.tx1 - br.tx0 + 1;
-    const int n = nx * (br.ty1 - br.ty0 + 1);
-    for (int base = 0; base < n; base += 64) {
-      const int idx = base + lane;
-      bool pass = false;
-      if (idx < n) {
-        const int tx = br.tx0 + idx % nx, ty = br.ty0 + idx / nx;
-        float kt;
-        pass = tile_test<false>(rec, br, sl, tx, ty, kt);
-        if (pass) atomicAdd(&a.tile_cnt[sl.tile_begin + ty * sl.tiles_x + tx], 1);
-      }
-      cnt += __popcll(ballot(pass));
+  if (br.nedge == 0) return;
+  const int nx = br.tx1 - br.tx0 + 1;
+  const int n = nx * (br.ty1 - br.ty0 + 1);
+  if ((int)blockIdx.y * 64 >= n) return;
+  const Rec& rec = a.recs[r];
+  const ps_slot& sl = a.slots[br.slot];
+  int total = 0;
+  for (int ch = blockIdx.y; ch * 64 < n; ch += gridDim.y) {
+    const int idx = ch * 64 + lane;
+    bool pass = false;
+    if (idx < n) {
+      const int tx = br.tx0 + idx % nx, ty = br.ty0 + idx / nx;
+      float kt;
+      pass = tile_test<false>(rec, br, sl, tx, ty, kt);
+      if (pass) atomicAdd(&a.tile_cnt[sl.tile_begin + ty * sl.tiles_x + tx], 1);
     }
+    const int cnt = __popcll(ballot(pass));
+    if (lane == 0) a.chunk_cnt[(size_t)r * a.CH + ch] = cnt;
+    total += cnt;
   }
-  if (lane == 0) a.rec_cnt[r] = cnt;
+  if (lane == 0 && total) atomicAdd(&a.rec_cnt[r], total);
 }
 
 __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
@@ -182,8 +194,9 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   }
 }
 
-// One wave per record, same tile order as bin_count_kernel: the j-th passing
-// tile of record r gets emit index rec_off[r] + j (ballot prefix count).
+// Waves over (record, group of 64 tiles) as in bin_count_kernel: the j-th
+// passing tile of record r, in tile-box order, gets emit index rec_off[r] + j
+// (counts of the earlier groups, then a ballot prefix count).
 __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -191,14 +204,18 @@ __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
   if (a.counters[C_OVERFLOW]) return;
   const BinRec& br = a.brecs[r];
   if (br.nedge == 0) return;
-  const Rec& rec = a.recs[r];
-  const ps_slot& sl = a.slots[br.slot];
   const int nx = br.tx1 - br.tx0 + 1;
   const int n = nx * (br.ty1 - br.ty0 + 1);
+  if ((int)blockIdx.y * 64 >= n) return;
+  const Rec& rec = a.recs[r];
+  const ps_slot& sl = a.slots[br.slot];
+  const int* cc = a.chunk_cnt + (size_t)r * a.CH;
   int j = a.rec_off[r];
+  int done = 0;   // groups counted into j
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int base = 0; base < n; base += 64) {
-    const int idx = base + lane;
+  for (int ch = blockIdx.y; ch * 64 < n; ch += gridDim.y) {
+    for (; done < ch; ++done) j += cc[done];
+    const int idx = ch * 64 + lane;
     bool pass = false;
     float kt = 0.f;
     int tx = 0, ty = 0;
@@ -214,7 +231,6 @@ __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
       a.keys_u[slot] = ((uint64_t)__float_as_uint(kt) << 32) | (uint32_t)r;
       a.emit_u[slot] = (uint32_t)(j + __popcll(m & below));
     }
-    j += __popcll(m);
   }
 }
 
@@ -322,6 +338,8 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   a.recs = (const Rec*)(base + L->region[R_REC]);
   a.brecs = (const BinRec*)(base + L->region[R_BINREC]);
   a.rec_cnt = (int*)(base + L->region[R_REC_CNT]);
+  a.chunk_cnt = (int*)(base + L->region[R_CHUNK_CNT]);
+  a.CH = L->max_chunks;
   a.rec_off = (int*)(base + L->region[R_REC_OFF]);
   a.tile_cnt = (int*)(base + L->region[R_TILE_CNT]);
   a.tile_off = (int*)(base + L->region[R_TILE_OFF]);
@@ -336,13 +354,16 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   a.recs_s = (Rec*)(base + L->region[R_RECS_S]);
   a.items = (ItemDesc*)(base + L->region[R_ITEMS]);
   a.tile_pos = (int*)(base + L->region[R_TILEPOS]);
-  hipLaunchKernelGGL(ps_fill_i32, dim3((a.T + 1 + 255) / 256), dim3(256), 0, st, a.tile_cnt,
-                     (int64_t)a.T + 1, 0);
+  // one fill clears the record counts, their offsets and the tile counts
+  // (adjacent regions; the gaps between them are padding)
+  static_assert(R_REC_OFF == R_REC_CNT + 1 && R_TILE_CNT == R_REC_OFF + 1, "region order");
+  const int64_t nfill = (int64_t)(L->region[R_TILE_CNT] - L->region[R_REC_CNT]) / 4 + a.T + 1;
+  hipLaunchKernelGGL(ps_fill_i32, dim3((unsigned)((nfill + 255) / 256)), dim3(256), 0, st, a.rec_cnt, nfill, 0);
   if (a.R > 0)
-    hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 3) / 4), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 3) / 4, std::min(a.CH, kChunkWaves)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, a);
   if (a.R > 0)
-    hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + 3) / 4), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + 3) / 4, std::min(a.CH, kChunkWaves)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_sort_small_kernel, dim3(a.T), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_sort_big_kernel, dim3(32), dim3(1024), 12 * kBigSort, st, a);
   PS_HIP_CHECK(hipGetLastError());

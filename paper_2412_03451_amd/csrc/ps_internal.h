@@ -92,6 +92,7 @@ enum Region {
   R_RECS_S,      // Rec[C]       record copies in tile-list order
   R_DIAG,        // int64[n_items][16]  per-block walk statistics (flags bit 6)
   R_TILEPOS,     // int[T]       first render item of each tile (longest lists first)
+  R_CHUNK_CNT,   // int[R][max_chunks]  passing tiles per (record, group of 64 tiles of its box)
   R_NUM_USED     // further regions are reserved (size 0)
 };
 // Render items are placed longest tile list first (buckets of list length),

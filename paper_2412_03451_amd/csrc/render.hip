@@ -843,10 +843,11 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
 //   dL/dq = 2 (0, dL/domega) (x) q^ / |q|
 // The in-plane offsets (P_X, P_Y) enter instead of the hit point, so no sum
 // carries the (large) camera distance of the plane.
-__global__ __launch_bounds__(64) void bwd_reduce_kernel(RenderArgs a) {
+__global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
+  __shared__ float part[4][16];
   const int k = blockIdx.x;
   if (k >= a.K) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double gp[3] = {0, 0, 0}, gw[3] = {0, 0, 0}, gr[4] = {0, 0, 0, 0};
   double qn[4] = {0, 0, 0, 0}, qnorm = 0;
   const bool ok = !a.counters[C_OVERFLOW];
@@ -862,7 +863,7 @@ __global__ __launch_bounds__(64) void bwd_reduce_kernel(RenderArgs a) {
     float A[13];
 #pragma unroll
     for (int q = 0; q < 13; ++q) A[q] = 0.f;
-    for (int idx = lane; idx < rows; idx += 64) {
+    for (int idx = tid; idx < rows; idx += 256) {
       const int e = e0 + idx / nsub, sb = idx % nsub;
       const float4* row = (const float4*)(a.partial + ((size_t)e * a.max_sub + sb) * 16);
       const float4 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
@@ -875,9 +876,13 @@ __global__ __launch_bounds__(64) void bwd_reduce_kernel(RenderArgs a) {
       float V[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) V[q] = q < 13 ? A[q] : 0.f;
-      const float tot = wave_sum16(V);   // lane 4 q holds the sum of A[q]
+      const float tot = wave_sum16(V);   // lane 4 q holds the wave's sum of A[q]
+      if ((lane & 3) == 0) part[wid][lane >> 2] = tot;
+      __syncthreads();
+      // the four waves' sums in a fixed order
 #pragma unroll
-      for (int q = 0; q < 13; ++q) A[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), 4 * q));
+      for (int q = 0; q < 13; ++q) A[q] = ((part[0][q] + part[1][q]) + part[2][q]) + part[3][q];
+      __syncthreads();
     }
     const ps_camera cam = a.cams[sl.cam];
     Frame f;
@@ -896,7 +901,7 @@ __global__ __launch_bounds__(64) void bwd_reduce_kernel(RenderArgs a) {
     }
     for (int q = 0; q < 4; ++q) gr[q] += A[9 + q];
   }
-  if (lane == 0) {
+  if (tid == 0) {
     for (int i = 0; i < 3; ++i) a.g_center[3 * k + i] = (float)gp[i];
     for (int q = 0; q < 4; ++q) a.g_radii[4 * k + q] = (float)gr[q];
     // 2 (0, w) (x) q^  =  2 (-(w . v), q0 w + w x v),  v = (q1, q2, q3)
@@ -982,7 +987,7 @@ static int launch_bwd(RenderArgs& a, int K, void* stream) {
       default: hipLaunchKernelGGL(render_bwd_kernel<6>, dim3(a.n_items), dim3(64), 0, st, a); break;
     }
   }
-  if (K > 0) hipLaunchKernelGGL(bwd_reduce_kernel, dim3(K), dim3(64), 0, st, a);
+  if (K > 0) hipLaunchKernelGGL(bwd_reduce_kernel, dim3(K), dim3(256), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }

@@ -18,6 +18,7 @@ forward definition).  Sections cited:
 * Adam, learning rate 1e-3 ........................... Sec. 3.3 and appendix A.2
 * plane splitting ..................................... Sec. 3.3, split.py
 * initialisation from depth, sphere initialisation ... Sec. 3.1 and 4.3, depth_init.py
+* plane merge ........................................ Sec. 3.3, merge.py
 * learned initializer (not in the paper; readings) ... initnet.py
 
 Readings taken where the paper is silent or garbled are listed in the
@@ -38,3 +39,4 @@ from .grad import render_backward, per_pixel_abs_grad  # noqa: F401
 from . import initnet  # noqa: F401
 from .split import split_planes  # noqa: F401
 from . import depth_init  # noqa: F401
+from .merge import merge_planes  # noqa: F401

@@ -225,6 +225,24 @@ int plane_init_points(const float* points, const float* normals, int n, const in
 int plane_init_sphere(const float* points, int n, const float* dirs, int K, float radius, float* center,
                       float* quat, float* radii, void* ws, void* stream);
 
+/* plane_merge (Sec. 3.3, plane merge): plane instances of K fitted planes.
+ * Planes i and j are related when |d| > cos_thr and |o_i - sign(d) o_j| <
+ * off_thr, with d = n_i . n_j, n = R(q / |q|) e_z (Eq. 3; primitives are
+ * two-sided, hence the sign) and o = (p - c) . n the offset of the plane
+ * from the scene center c (float64, each operation rounded on its own, in
+ * this order).  Instances are the connected components of the relation;
+ * label[k] is the smallest plane index of plane k's instance and *n_out the
+ * number of instances.  The paper's thresholds: cos_thr = cos(25 deg),
+ * off_thr = 0.001 m.  center [K][3], quat [K][4], scene_center [3]: device
+ * float32; label: device int32 [K]; n_out: device int32; ws: device scratch
+ * of plane_merge_ws_bytes(K) bytes.  Runs rounds of linking until a round
+ * links nothing (at most K; the stream is synchronised after each round, so
+ * the call is not capturable in a graph).  PS_ERR_INVALID: null pointer,
+ * K < 1, off_thr < 0, ws_bytes too small. */
+size_t plane_merge_ws_bytes(int K);
+int plane_merge(const float* center, const float* quat, int K, const float* scene_center, double cos_thr,
+                double off_thr, int32_t* label, int32_t* n_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Device-side bookkeeping of one iteration of the fitting loop (Sec. 3.3,
  * Eq. 10), so that whole steps can be captured in a graph and replayed with
  * no host work.  Reads the iteration counter *ite (device int32, 0-based),

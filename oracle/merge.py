@@ -62,7 +62,7 @@ def merge_planes(center, quat, scene_center=None, angle_deg: float = 25.0, offse
         scene_center = default_center(center)
     n, o = normals_offsets(center, quat, scene_center)
     cos_thr = math.cos(math.radians(angle_deg))
-    off_thr = float(np.float32(offset))
+    off_thr = float(offset)
     label = -np.ones(K, np.int64)
     # breadth-first search over the pair relation, components found in index order
     for s in range(K):

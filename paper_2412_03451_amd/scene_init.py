@@ -1,5 +1,6 @@
 """Scene initialisation over the C ABI: planes from depth maps (Sec. 3.1)
-and the sphere initialisation of the ablation (Sec. 4.3).
+and the sphere initialisation of the ablation (Sec. 4.3); the plane merge
+after the fit (Sec. 3.3).
 
 The random draws (which fused points become planes, the directions on the
 sphere) are made here with a seeded numpy generator and passed to the
@@ -99,3 +100,26 @@ def init_sphere(points, K: int = 2000, seed: int = 0, radius: float = 0.05, dirs
     check(lib.plane_init_sphere(_ptr(points.contiguous()), int(points.shape[0]), _ptr(dirs), K, float(radius),
                                 _ptr(c), _ptr(q), _ptr(r), _ptr(ws), _stream()))
     return c, q, r
+
+
+def merge_planes(center, quat, scene_center=None, angle_deg: float = 25.0, offset: float = 0.001):
+    """Plane instances (plane_merge): int32 labels [K] (smallest plane index
+    of each instance) and the number of instances.  scene_center: [3]
+    (device tensor or sequence); by default the middle of the box of the
+    plane centers."""
+    import math
+    lib = _lib.load()
+    dev = center.device
+    center = center.contiguous().float()
+    quat = quat.contiguous().float()
+    K = int(center.shape[0])
+    if scene_center is None:
+        scene_center = 0.5 * (center.min(dim=0).values.double() + center.max(dim=0).values.double())
+    sc = torch.as_tensor(scene_center, dtype=torch.float32).to(dev).contiguous()
+    nbytes = int(lib.plane_merge_ws_bytes(K))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    label = torch.empty(K, dtype=torch.int32, device=dev)
+    n_out = torch.empty(1, dtype=torch.int32, device=dev)
+    check(lib.plane_merge(_ptr(center), _ptr(quat), K, _ptr(sc), math.cos(math.radians(angle_deg)), float(offset),
+                          _ptr(label), _ptr(n_out), _ptr(ws), nbytes, _stream()))
+    return label, int(n_out.item())

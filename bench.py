@@ -403,7 +403,7 @@ def init_ablation_bench(args):
     maps (Sec. 3.1: fused points at stride 4 and 2 cm voxels), on the scene's
     bounding sphere (Sec. 4.3, radii 0.05), and the noisy ground truth of the
     throughput workload; the depth initialisation is also fitted without
-    splitting.  Each fit ends with the plane merge (Sec. 3.3, 25 degrees and
+    splitting and with single-direction radii (the plane-radii ablation).  Each fit ends with the plane merge (Sec. 3.3, 25 degrees and
     0.1 cm), timed, with its instance count beside the ground truth's.  Depth L1 over all views at lambda = 300 every 500
     iterations; fit wall-times exclude the evaluations; the initialisation
     kernels are timed on their own."""
@@ -434,12 +434,13 @@ def init_ablation_bench(args):
     sphere_init, sphere_ms = timed(lambda: si.init_sphere(pts, K, seed=0))
     log(f"depth_points: {n} fused points from {V} views in {pts_ms:.2f} ms; plane_init_points {planes_ms:.3f} ms; "
         f"plane_init_sphere {sphere_ms:.3f} ms")
-    runs = {"depth": (depth_init, 1000), "depth, no splitting": (depth_init, 0), "sphere": (sphere_init, 1000),
-            "noisy-gt": ((init.center, init.quat, init.radii), 1000)}
+    runs = {"depth": (depth_init, 1000, False), "depth, no splitting": (depth_init, 0, False),
+            "depth, single radii": (depth_init, 1000, True), "sphere": (sphere_init, 1000, False),
+            "noisy-gt": ((init.center, init.quat, init.radii), 1000, False)}
     out = {}
-    for name, (planes, split_every) in runs.items():
+    for name, (planes, split_every, single) in runs.items():
         fit = SceneFit(*planes, cams, tD, tN,
-                       cfg=FitConfig(check_every=250, split_every=split_every, split_thresh=0.2))
+                       cfg=FitConfig(check_every=250, split_every=split_every, split_thresh=0.2, single_radii=single))
         curve = [[0, round(fit.depth_l1(lam=300.0), 5)]]
         fit_s = 0.0
         for ck in range(500, args.fit_iters + 1, 500):

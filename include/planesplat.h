@@ -331,6 +331,15 @@ int adam_step_planes(float* center, float* quat, float* radii, const float* g_ce
                      const int32_t* step, float lr_center, float lr_quat, float lr_radii,
                      float beta1, float beta2, float eps, float r_min, void* stream);
 
+/* plane_tie_radii: the single-direction radii variant of the ablation
+ * (Sec. 4.3, plane radii): each axis has one radius shared by both
+ * directions, r^{x+} = r^{x-} and r^{y+} = r^{y-}.  The gradient of a shared
+ * radius is the sum of the two directions' gradients; it is written to both
+ * entries of g_radii (device float [K][4], 16-byte aligned) so that Adam,
+ * started from equal radii, keeps them equal.  Call between
+ * plane_render_bwd and adam_step_planes. */
+int plane_tie_radii(float* g_radii, int K, void* stream);
+
 /* Counters of the last binning and renders (synchronises the stream):
  * out[0] pairs needed, out[1] overflow flag, out[2] largest tile list,
  * out[3] pixels that took the exact fallback ordering path, out[4] tiles

@@ -81,6 +81,7 @@ _EXPORTS = {
     "plane_init_points": (C.c_int, [_P, _P, C.c_int, _P, C.c_int, C.c_float, _P, _P, _P, _P]),
     "plane_init_sphere": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_float, _P, _P, _P, _P, _P]),
     "plane_merge_ws_bytes": (C.c_size_t, [C.c_int]),
+    "plane_tie_radii": (C.c_int, [_P, C.c_int, _P]),
     "plane_merge": (C.c_int, [_P, _P, C.c_int, _P, C.c_double, C.c_double, _P, _P, _P, C.c_size_t, _P]),
     "initnet_param_count": (C.c_int64, [C.c_int]),
     "initnet_packed_count": (C.c_int64, [C.c_int]),

@@ -65,3 +65,26 @@ extern "C" int adam_step_planes(float* center, float* quat, float* radii, const 
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
+
+namespace {
+// Single-direction radii (the ablation of Sec. 4.3): r^{x+} = r^{x-} is one
+// parameter, whose gradient is the sum of the two directions' gradients.
+__global__ __launch_bounds__(256) void tie_radii_kernel(float4* g, int K) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  float4 v = g[k];
+  const float gx = v.x + v.y, gy = v.z + v.w;
+  v.x = gx; v.y = gx; v.z = gy; v.w = gy;
+  g[k] = v;
+}
+}  // namespace
+
+extern "C" int plane_tie_radii(float* g_radii, int K, void* stream) {
+  if (K < 0 || (K > 0 && !g_radii)) return ps_set_error(PS_ERR_INVALID, "plane_tie_radii: bad argument");
+  if (reinterpret_cast<uintptr_t>(g_radii) & 15)
+    return ps_set_error(PS_ERR_INVALID, "plane_tie_radii: g_radii must be 16-byte aligned");
+  if (K == 0) return PS_OK;
+  hipLaunchKernelGGL(tie_radii_kernel, dim3((K + 255) / 256), dim3(256), 0, (hipStream_t)stream, (float4*)g_radii, K);
+  PS_HIP_CHECK(hipGetLastError());
+  return PS_OK;
+}

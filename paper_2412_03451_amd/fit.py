@@ -24,7 +24,7 @@ import numpy as np
 import torch
 
 from ._lib import check
-from .splat import Job, Renderer, SplatParams, _ptr, _stream, adam_step, grad_accumulate, split_planes
+from .splat import Job, Renderer, SplatParams, _ptr, _stream, adam_step, grad_accumulate, split_planes, tie_radii
 
 
 def view_schedule(n_views: int, n_rows: int, per_step: int = 1, seed: int = 0) -> np.ndarray:
@@ -53,6 +53,7 @@ class FitConfig:
     grow: float = 1.5
     split_every: int = 0                # plane splitting every n iterations (Sec. 3.3: 1000); 0: off
     split_thresh: float = 0.2           # average |dL/dr| over a pair of radii that triggers a split
+    single_radii: bool = False          # ablation (Sec. 4.3): one radius per axis, r+ = r- (from their mean)
 
 
 @dataclass
@@ -91,6 +92,11 @@ class BatchFit:
         self.c = torch.cat(cs).contiguous()
         self.q = torch.cat([T(sc.quat).reshape(-1, 4) for sc in self.scenes]).contiguous()
         self.r = torch.cat([T(sc.radii).reshape(-1, 4) for sc in self.scenes]).contiguous()
+        if self.cfg.single_radii:
+            # one radius per axis: both directions start from their mean
+            mx = 0.5 * (self.r[:, 0] + self.r[:, 1])
+            my = 0.5 * (self.r[:, 2] + self.r[:, 3])
+            self.r = torch.stack([mx, mx, my, my], dim=1).contiguous()
         self.K = int(self.c.shape[0])
         self.k_off = np.cumsum([0] + [int(x.shape[0]) for x in cs])
         self.m = torch.zeros(11 * self.K, device=dev)
@@ -203,6 +209,8 @@ class BatchFit:
                                      a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2])
         m()
         gc, gq, gr = rend.backward(self.c, self.q, self.r, self.lam, gD, gN)
+        if cfg.single_radii:
+            tie_radii(gr)
         if cfg.split_every:
             grad_accumulate(gr, self.acc, self.cnt)
         m()

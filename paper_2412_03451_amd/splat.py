@@ -280,6 +280,13 @@ def adam_step(center, quat, radii, g_center, g_quat, g_radii, m, v, step, lr=(1e
                                lr[0], lr[1], lr[2], betas[0], betas[1], eps, r_min, _stream()))
 
 
+def tie_radii(g_radii):
+    """Single-direction radii: g[x+] = g[x-] = their sum, likewise y
+    (plane_tie_radii), in place."""
+    lib = _lib.load()
+    check(lib.plane_tie_radii(_ptr(g_radii), int(g_radii.shape[0]), _stream()))
+
+
 def grad_accumulate(g_radii, acc, cnt):
     """acc += |g_radii|, cnt += 1 where the radii gradient is not all zero
     (plane_grad_accumulate)."""

@@ -13,8 +13,12 @@ adam_step_planes, captured once in a HIP graph and replayed.
 
 Metric: fwd+bwd Mpixel.planes/s = (pixels of the step) * K / step time / 1e6,
 with the whole replayed step (Adam included) inside the timed region and all
-inputs resident in HBM.  Per-kernel durations come from the same steps run
-eagerly with events between the phases.  Prints one JSON line.
+inputs resident in HBM.  By default the timed steps are the room's whole
+5000-iteration fit from its start (lambda rising from 7.4 to 300 by Eq. 10);
+the first 200 steps, the slowest (widest fringes), are reported beside it.
+Per-kernel durations come from steps sampled evenly over the same
+trajectory, run eagerly with events between the phases.  Prints one JSON
+line.
 """
 
 from __future__ import annotations
@@ -476,7 +480,7 @@ def init_ablation_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=5000, help="timed fitting iterations (the room fit is 5000)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--views", type=int, default=1, help="views per fitting step")
     ap.add_argument("--tile", type=int, nargs=2, default=(16, 16))
@@ -486,7 +490,7 @@ def main():
     ap.add_argument("--force-rounds", action="store_true",
                     help="send every pixel through the exact round-based ordering path")
     ap.add_argument("--phase-steps", type=int, default=50,
-                    help="eager steps timed phase by phase (per-kernel durations)")
+                    help="eager steps timed phase by phase (per-kernel durations), spread over the timed steps")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--workload", default="room", choices=("room", "scene-fit", "memory", "batched", "initnet",
@@ -559,34 +563,54 @@ def main():
     log(f"pairs needed (max over views) {need}, capacity {fit.rend.L.pair_capacity}")
     start_state = fit.state()
 
-    # warm-up (eager step, graph capture, replays; grows the lists if needed)
-    log(f"warmup {args.warmup} steps (graph capture)")
-    fit.run(max(1, args.warmup), graph=True)
+    # warm-up: the whole timed trajectory once through the fit loop (eager
+    # step, graph capture, replays; the pair lists grow if any step of it
+    # needs more), then back to the start
+    log(f"warmup: the {args.steps}-step trajectory through the fit loop, then {args.warmup} replays")
+    fit.run(args.steps, graph=True)
+    fit.restore(start_state)
+    for _ in range(max(1, args.warmup)):
+        fit.graph.replay()
     fit.restore(start_state)
 
-    # timed: K replays of the captured step
+    # timed: K replays of the captured step from the start state (the fit's
+    # first K iterations, lambda following Eq. 10), inputs resident in HBM
     log(f"timing {args.steps} graph-replayed steps")
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
+    early = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
+    n_early = min(args.steps, 200)
     start.record(stream)
-    for _ in range(args.steps):
+    for i in range(args.steps):
         fit.graph.replay()
+        if i + 1 == n_early:
+            early.record(stream)
     end.record(stream)
     torch.cuda.synchronize()
     ms_step = start.elapsed_time(end) / args.steps
+    ms_early = start.elapsed_time(early) / n_early
     if fit.overflowed():
         raise RuntimeError("pair capacity exceeded during the timed steps")
     final_loss = fit._graph_loss.sum(0).cpu().tolist()
 
-    # per-phase durations: the same steps run eagerly with events between the
-    # phases (on the stream the kernels are launched on)
+    # per-phase durations and walk statistics, sampled over the same
+    # trajectory: every `stride`-th step runs eagerly with events between the
+    # phases (on the stream the kernels are launched on) after a diagnostics
+    # pass on its state; the other steps are replays (same bits)
     fit.restore(start_state)
     names = ("project", "bin", "fwd", "loss", "bwd", "adam")
     ev = {n: [] for n in names}
-    log(f"timing {args.phase_steps} eager steps phase by phase")
-    for _ in range(args.phase_steps):
+    n_samples = max(1, min(args.phase_steps, args.steps))
+    stride = max(1, args.steps // n_samples)
+    log(f"timing {n_samples} eager steps phase by phase, one every {stride} steps")
+    stats = []
+    for i in range(args.steps):
+        if i % stride or len(stats) >= n_samples:
+            fit.graph.replay()
+            continue
+        stats.append(fit.diagnose())
         marks = []
 
         def mark():
@@ -595,15 +619,16 @@ def main():
             marks.append(e)
         fit._step(mark=mark)
         torch.cuda.synchronize()
-        for i, n in enumerate(names):
-            ev[n].append(marks[i].elapsed_time(marks[i + 1]))
+        for j, n in enumerate(names):
+            ev[n].append(marks[j].elapsed_time(marks[j + 1]))
     phase_ms = {n: float(np.mean(x)) for n, x in ev.items()}
-    eager_ms = float(np.mean([sum(ev[n][k] for n in names) for k in range(args.phase_steps)]))
-
-    # diagnostics (untimed): walk statistics of the next views
-    cnt = fit.diagnose()
-    hits = int(cnt["composited_hits"])
-    evals = int(cnt["evals"])
+    eager_ms = float(np.mean([sum(ev[n][k] for n in names) for k in range(len(ev["fwd"]))]))
+    cnt = {k: float(np.mean([st[k] for st in stats])) for k in stats[0] if not isinstance(stats[0][k], list)}
+    cnt["max_steps"] = max(st["max_steps"] for st in stats)
+    cnt["max_wave_ticks"] = max(st["max_wave_ticks"] for st in stats)
+    cnt["bwd_max_block_ticks"] = max(st["bwd_max_block_ticks"] for st in stats)
+    hits = int(round(cnt["composited_hits"]))
+    evals = int(round(cnt["evals"]))
 
     pix = V * W * H
     value = pix * K / (ms_step * 1e-3) / 1e6
@@ -635,14 +660,15 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_first_200": round(ms_early, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (f64 ray-plane geometry)",
         "data": "synthetic",
         "config": {"workload": f"single room, K={K} planes, {V} view(s)/step of {W}x{H}, f=577, "
-                               f"tile {args.tile[0]}x{args.tile[1]}, lambda from ite {args.start_ite}, "
-                               f"graph-replayed fitting step",
+                               f"tile {args.tile[0]}x{args.tile[1]}, fitting iterations {args.start_ite}-"
+                               f"{args.start_ite + args.steps - 1} (lambda of Eq. 10), graph-replayed steps",
                    "planes": K, "views_per_step": V, "width": W, "height": H,
                    "pairs_per_step": int(cnt["pairs"])},
         "eager_ms_per_step": round(eager_ms, 4),

@@ -49,7 +49,7 @@ __device__ inline void affine(const double c[3], const ps_camera& cam, double& c
   c0 = c[2] - cu * (double)cam.cx - cv * (double)cam.cy;
 }
 
-__global__ __launch_bounds__(256) void project_kernel(ProjArgs a) {
+__global__ __launch_bounds__(64) void project_kernel(ProjArgs a) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.R) return;
   const int s = find_slot_by_rec(a.slots, a.S, r);
@@ -102,37 +102,47 @@ __global__ __launch_bounds__(256) void project_kernel(ProjArgs a) {
       corner[c][i] = (double)cam.R[3 * i] * xw[0] + (double)cam.R[3 * i + 1] * xw[1] +
                      (double)cam.R[3 * i + 2] * xw[2] + (double)cam.t[i];
   }
-  // clip to z >= z_near (one plane of Sutherland-Hodgman)
-  double poly[5][3];
-  int np = 0;
+  // clip to z >= z_near (one plane of Sutherland-Hodgman).  Edge c of the
+  // quad (corner c -> corner c+1) gives at most two vertices of the clipped
+  // polygon, kept in fixed slots 2c (corner c, when inside) and 2c + 1 (the
+  // crossing, when the edge crosses): the valid slots in slot order are the
+  // polygon in order, and every array index below is a constant (no
+  // scratch memory).
   const double zn = (double)a.z_near;
+  double px[8], py[8], pz[8];
+  bool ok[8];
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const double* A = corner[c];
     const double* B = corner[(c + 1) & 3];
     const bool ina = A[2] >= zn, inb = B[2] >= zn;
-    if (ina) {
-      for (int i = 0; i < 3; ++i) poly[np][i] = A[i];
-      ++np;
-    }
-    if (ina != inb) {
-      const double t = (zn - A[2]) / (B[2] - A[2]);
-      for (int i = 0; i < 3; ++i) poly[np][i] = A[i] + t * (B[i] - A[i]);
-      poly[np][2] = zn;
-      ++np;
-    }
+    ok[2 * c] = ina;
+    px[2 * c] = A[0]; py[2 * c] = A[1]; pz[2 * c] = A[2];
+    ok[2 * c + 1] = ina != inb;
+    const double t = (ina != inb) ? (zn - A[2]) / (B[2] - A[2]) : 0.0;
+    px[2 * c + 1] = A[0] + t * (B[0] - A[0]);
+    py[2 * c + 1] = A[1] + t * (B[1] - A[1]);
+    pz[2 * c + 1] = zn;
   }
+  int np = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) np += ok[c] ? 1 : 0;
   if (np == 0) {
     store_culled(a.recs, a.brecs, r, s);
     return;
   }
-  double zmin = poly[0][2], umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
-  double pu[5], pv[5];
-  for (int c = 0; c < np; ++c) {
-    zmin = fmin(zmin, poly[c][2]);
-    pu[c] = (double)cam.fx * poly[c][0] / poly[c][2] + (double)cam.cx;
-    pv[c] = (double)cam.fy * poly[c][1] / poly[c][2] + (double)cam.cy;
-    umin = fmin(umin, pu[c]); umax = fmax(umax, pu[c]);
-    vmin = fmin(vmin, pv[c]); vmax = fmax(vmax, pv[c]);
+  double zmin = 1e300, umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+  double pu[8], pv[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const double z = ok[c] ? pz[c] : 1.0;
+    pu[c] = (double)cam.fx * px[c] / z + (double)cam.cx;
+    pv[c] = (double)cam.fy * py[c] / z + (double)cam.cy;
+    if (ok[c]) {
+      zmin = fmin(zmin, pz[c]);
+      umin = fmin(umin, pu[c]); umax = fmax(umax, pu[c]);
+      vmin = fmin(vmin, pv[c]); vmax = fmax(vmax, pv[c]);
+    }
   }
   // pixel i is inside when umin <= i + 1/2 <= umax; one pixel of guard
   const double W = sl.width, H = sl.height;
@@ -146,43 +156,65 @@ __global__ __launch_bounds__(256) void project_kernel(ProjArgs a) {
   rec.py0 = (int16_t)j0; rec.py1 = (int16_t)j1;
   a.recs[r] = rec;
 
-  BinRec b;
-  // orientation: make the polygon counter-clockwise (positive signed area)
-  double area = 0.0;
-  for (int c = 0; c < np; ++c) {
-    const int d = (c + 1 == np) ? 0 : c + 1;
-    area += pu[c] * pv[d] - pu[d] * pv[c];
+  // next valid slot after each slot, cyclically (itself when it is the only one)
+  int nxt[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    int n = c;
+#pragma unroll
+    for (int k = 7; k >= 1; --k)
+      if (ok[(c + k) & 7]) n = (c + k) & 7;
+    nxt[c] = n;
   }
-  for (int e = 0; e < 5; ++e) b.edge[e][0] = b.edge[e][1] = b.edge[e][2] = 0.0;
+  // orientation: signed area of the polygon, summed from its first vertex
+  double area = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (!ok[c]) continue;
+    double un = pu[0], vn = pv[0];
+#pragma unroll
+    for (int d = 0; d < 8; ++d)
+      if (d == nxt[c]) { un = pu[d]; vn = pv[d]; }
+    area += pu[c] * vn - un * pv[c];
+  }
+  BinRec* bo = a.brecs + r;
+  for (int e = 0; e < 5; ++e) bo->edge[e][0] = bo->edge[e][1] = bo->edge[e][2] = 0.0;
   if (np >= 3 && fabs(area) > 1e-3) {
-    // signed distance to each edge, positive inside the counter-clockwise polygon
-    b.nedge = np;
-    for (int e = 0; e < np; ++e) {
-      const int ia = area > 0 ? e : np - 1 - e;
-      const int ib = area > 0 ? (e + 1 == np ? 0 : e + 1) : (e + 1 == np ? np - 1 : np - 2 - e);
-      const double ex = pu[ib] - pu[ia], ey = pv[ib] - pv[ia];
+    // signed distance to each edge, positive inside: edges run from each
+    // vertex to the next (counter-clockwise polygon) or back (clockwise)
+    bo->nedge = np;
+    int e = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (!ok[c]) continue;
+      double un = pu[0], vn = pv[0];
+#pragma unroll
+      for (int d = 0; d < 8; ++d)
+        if (d == nxt[c]) { un = pu[d]; vn = pv[d]; }
+      const double ua = area > 0 ? pu[c] : un, va = area > 0 ? pv[c] : vn;
+      const double ub = area > 0 ? un : pu[c], vb = area > 0 ? vn : pv[c];
+      const double ex = ub - ua, ey = vb - va;
       const double len = sqrt(ex * ex + ey * ey);
-      if (!(len > 0.0)) {  // repeated vertex: no constraint
-        b.edge[e][0] = 0.0; b.edge[e][1] = 0.0; b.edge[e][2] = 1.0;
-        continue;
+      if (len > 0.0) {
+        bo->edge[e][0] = -ey / len;
+        bo->edge[e][1] = ex / len;
+        bo->edge[e][2] = (ey * ua - ex * va) / len;
+      } else {  // repeated vertex: no constraint
+        bo->edge[e][2] = 1.0;
       }
-      b.edge[e][0] = -ey / len;
-      b.edge[e][1] = ex / len;
-      b.edge[e][2] = (ey * pu[ia] - ex * pv[ia]) / len;
+      ++e;
     }
   } else {
-    b.nedge = -1;
+    bo->nedge = -1;
   }
   // depth lower bound over the grown, clipped rectangle, rounded down.  The
   // ray parameter of a hit equals its camera z only up to the float32
   // rounding of R (R R^T = I to ~1e-7): a relative margin of 4e-6 covers it.
-  float tl = __double2float_rd(fmax(zmin, zn) * (1.0 - 4e-6));
-  b.tlb = tl;
-  b.tx0 = (int)i0 / sl.tile_w; b.tx1 = (int)i1 / sl.tile_w;
-  b.ty0 = (int)j0 / sl.tile_h; b.ty1 = (int)j1 / sl.tile_h;
-  b.slot = s;
-  b.pad[0] = b.pad[1] = b.pad[2] = 0;
-  a.brecs[r] = b;
+  bo->tlb = __double2float_rd(fmax(zmin, zn) * (1.0 - 4e-6));
+  bo->tx0 = (int)i0 / sl.tile_w; bo->tx1 = (int)i1 / sl.tile_w;
+  bo->ty0 = (int)j0 / sl.tile_h; bo->ty1 = (int)j1 / sl.tile_h;
+  bo->slot = s;
+  bo->pad[0] = bo->pad[1] = bo->pad[2] = 0;
 }
 
 }  // namespace
@@ -210,7 +242,7 @@ extern "C" int plane_project(const ps_layout* L, void* ws, const float* center, 
   a.tau = prm->tau; a.z_near = prm->z_near; a.mode = prm->weight_mode; a.two_sided = prm->two_sided;
   a.recs = (Rec*)(base + L->region[R_REC]);
   a.brecs = (BinRec*)(base + L->region[R_BINREC]);
-  hipLaunchKernelGGL(project_kernel, dim3((a.R + 255) / 256), dim3(256), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL(project_kernel, dim3((a.R + 63) / 64), dim3(64), 0, (hipStream_t)stream, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }

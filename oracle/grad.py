@@ -14,6 +14,7 @@ judged against this scale where the pixel contributions cancel.
 
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from .render import OracleParams, _t, render_pixels
@@ -44,17 +45,20 @@ def render_backward(center, quat, radii, cam, lam, gD, gN, prm: OracleParams = O
 
 
 def per_pixel_abs_grad(center, quat, radii, cam, lam, gD, gN, prm: OracleParams = OracleParams(),
-                       chunk: int = 2048):
+                       chunk: int = 2048, pix=None):
     """(grad, abs_sum) for each of center, quat, radii: grad is the plain
-    gradient, abs_sum the per-coordinate sum over pixels of |contribution|."""
+    gradient, abs_sum the per-coordinate sum over pixels of |contribution|.
+    pix: the pixels to sum over (flat indices; all by default), for upstream
+    gradients that vanish elsewhere."""
     center, quat, radii = _t(center), _t(quat), _t(radii)
     gD, gN = _upstream(cam, gD, gN)
     P = cam.width * cam.height
     K = center.shape[0]
+    allpix = torch.arange(P) if pix is None else torch.as_tensor(np.asarray(pix), dtype=torch.int64)
     grads = [torch.zeros(K, 3, dtype=F64), torch.zeros(K, 4, dtype=F64), torch.zeros(K, 4, dtype=F64)]
     abss = [torch.zeros(K, 3, dtype=F64), torch.zeros(K, 4, dtype=F64), torch.zeros(K, 4, dtype=F64)]
-    for s in range(0, P, chunk):
-        pix = torch.arange(s, min(P, s + chunk))
+    for s in range(0, allpix.numel(), chunk):
+        pix = allpix[s:s + chunk]
         n = pix.numel()
         cc = center[None].expand(n, K, 3).clone().requires_grad_(True)
         qq = quat[None].expand(n, K, 4).clone().requires_grad_(True)

@@ -15,7 +15,7 @@ import torch
 
 import oracle
 import synth
-from helpers import cosine, f32, grad_check
+from helpers import U32, cosine, f32, grad_check
 
 pytestmark = pytest.mark.gpu
 
@@ -35,10 +35,10 @@ def _upstream(ps, tgt, cam, lam, prm):
     return Dv.grad.numpy().astype(np.float32), Nv.grad.numpy().astype(np.float32)
 
 
-def _check_grads(gpu, ref, abss, label):
+def _check_grads(gpu, ref, abss, label, c=32.0):
     for name, g, gr, s in zip(("center", "quat", "radii"), gpu, ref, abss):
         g = g.detach().cpu().numpy()
-        err, tol = grad_check(g, gr.numpy(), s.numpy())
+        err, tol = grad_check(g, gr.numpy(), s.numpy(), c=c)
         cs = cosine(g, gr.numpy())
         ratio = err / np.maximum(tol, 1e-300)
         w = np.unravel_index(np.argmax(ratio), ratio.shape)
@@ -240,3 +240,43 @@ def test_full_step_tiny_config():
         # first step moves each coordinate by lr * sign(g) unless g vanishes
         big = np.abs(g.numpy()) > 1e-3
         np.testing.assert_allclose(delta[big], delta_ref[big], rtol=1e-3, atol=2e-7)
+
+
+def test_room_backward_sampled_pixels():
+    """Full-size room view (640x480, ~2000 planes, the benchmark's shape):
+    upstream gradients on 300 sampled pixels, zero elsewhere, so the oracle
+    differentiates those pixels only; at the first iteration's lambda and at 300.
+
+    Bound per coordinate: 1e-4 |g_ref| + 1e-4 S (S the sum over pixels of
+    |contribution|), the relative 1e-4 gradient bar read per coordinate.  The
+    tighter 32 float32 roundoffs of S of the small scenes does not hold here:
+    in pixels with 30 hits at the first iteration's wide fringes,
+    dL/dw_j = T_j (c_j - S_{j+1}) cancels (c_j, formed from the float32 depth,
+    is close to the mean S_{j+1} of what lies behind), and one contribution
+    was measured 9e-5 off in relative terms with the same hit list as the
+    oracle's."""
+    from paper_2412_03451_amd.splat import Renderer
+    gt, info = synth.room_planes(seed=0, target_K=2000)
+    init = synth.room_init_planes(gt, seed=1)
+    cams = synth.room_trajectory(seed=0, n_views=1, info=info)
+    cam = cams[0]
+    P = cam.width * cam.height
+    rng = np.random.default_rng(17)
+    for lam in (oracle.lambda_at(0), 300.0):
+        print(f"room backward lambda {lam:.4g}", flush=True)
+        r = Renderer.single_scene(cams, init.K, tile=(16, 16))
+        lt = torch.tensor([lam], device="cuda")
+        c, q, rr = _dev(init.center), _dev(init.quat), _dev(init.radii)
+        r.project(c, q, rr, lt)
+        r.bin()
+        r.forward()
+        pix = rng.choice(P, size=300, replace=False)
+        gD = np.zeros(P, np.float32)
+        gN = np.zeros((3, P), np.float32)
+        gD[pix] = rng.normal(size=300).astype(np.float32)
+        gN[:, pix] = rng.normal(size=(3, 300)).astype(np.float32)
+        gpu = r.backward(c, q, rr, lt, _dev(gD), _dev(gN.reshape(-1)))
+        torch.cuda.synchronize()
+        grads, abss = oracle.per_pixel_abs_grad(init.center, init.quat, init.radii, cam, f32(lam), gD, gN,
+                                                chunk=25, pix=pix)
+        _check_grads(gpu, grads, abss, f"room lambda {lam:.4g}", c=1e-4 / U32)

@@ -600,7 +600,7 @@ def main():
     # phases (on the stream the kernels are launched on) after a diagnostics
     # pass on its state; the other steps are replays (same bits)
     fit.restore(start_state)
-    names = ("project", "bin", "fwd", "loss", "bwd", "adam")
+    names = ("project", "bin", "fwd", "bwd", "adam")   # "fwd": forward with the render loss
     ev = {n: [] for n in names}
     n_samples = max(1, min(args.phase_steps, args.steps))
     stride = max(1, args.steps // n_samples)

@@ -133,6 +133,19 @@ int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void* ws, void* 
  * (device int array of n_slots), for captured fitting steps. */
 int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_of_slot, void* stream);
 
+/* plane_render_fwd_loss: plane_render_fwd and loss_depth_normal_cam
+ * (Eq. 11-14) in one pass: the forward forms the loss of every pixel it
+ * renders right after compositing it, with the arithmetic of the loss call,
+ * so depth, normal, g_depth, g_normal and loss hold the same bits as the two
+ * calls give (the loss kernel's read of the maps is saved).  Arguments as in
+ * the two calls; tgt_off may be null (targets laid out like the jobs, as for
+ * loss_depth_normal), else n_tgt offsets as n_cams of loss_depth_normal_cam. */
+int plane_render_fwd_loss(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, const float* lambda,
+                          const ps_params* prm, float* depth, float* normal, const float* tgt_depth,
+                          const float* tgt_normal, const uint8_t* mask, const int64_t* tgt_off, int n_tgt,
+                          float a_cos, float a_nl1, float a_d, float* loss, float* g_depth, float* g_normal,
+                          void* stream);
+
 /* The list-storing variant of the render pair, kept to compare memory with
  * the recompute backward above (it is not used by the fitting loop).
  * plane_render_fwd_lists renders like plane_render_fwd and also stores, for

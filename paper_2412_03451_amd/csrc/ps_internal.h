@@ -365,6 +365,82 @@ __device__ inline PairGeom eval_pair(const R& r, double u, double v, double eps_
   return g;
 }
 
+// Render loss of Eq. 14 at one pixel and its gradient, shared by the loss
+// kernel and the forward that forms the loss itself (same arithmetic, same
+// bits):
+//   l = a_cos |1 - N.N^| + a_nl1 sum_c |N_c - N^_c| + a_d |D - D^|,
+//   dl/dD = a_d sgn(D - D^),  dl/dN = -a_cos sgn(1 - N.N^) N^ + a_nl1 sgn(N - N^)
+// with sgn(0) = 0 and the dot product in float64 (products of float32 values
+// are exact there).  Adds the pixel's three terms and |D - D^| to l[0..3].
+struct LossView {
+  const float* Dt;
+  const float* Nt;
+  const uint8_t* mask;
+  const int64_t* tgt_off;   // null: targets laid out like the jobs; else per-camera pixel offsets
+  int n_cams;
+  float a_cos, a_nl1, a_d;
+  float* gD;
+  float* gN;
+};
+
+// float64 wave sum (the loss partials), in a fixed order
+__device__ inline double wave_sum_double(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline float sgn_f(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+__device__ inline void loss_pixel(const LossView& a, const ps_slot& sl, int px, int py, float D, const float N[3],
+                                  double l[4]) {
+  const int64_t HW = (int64_t)sl.width * sl.height;
+  const int64_t local = (int64_t)py * sl.width + px;
+  const int64_t p = sl.pix_off + local;
+  const int64_t nb = 3 * sl.pix_off + local;
+  // targets of a camera: its own image at tgt_off[cam] (a camera whose
+  // index is out of range contributes nothing)
+  const bool valid = !a.tgt_off || (sl.cam >= 0 && sl.cam < a.n_cams);
+  if (!valid) {
+    a.gD[p] = 0.f;
+    for (int c = 0; c < 3; ++c) a.gN[nb + c * HW] = 0.f;
+    return;
+  }
+  const int64_t tp = a.tgt_off ? a.tgt_off[sl.cam] + local : p;
+  const int64_t tnb = a.tgt_off ? 3 * a.tgt_off[sl.cam] + local : nb;
+  const float m = a.mask ? (a.mask[tp] ? 1.f : 0.f) : 1.f;
+  const float Dt = a.Dt[tp];
+  float Nt[3];
+  for (int c = 0; c < 3; ++c) Nt[c] = a.Nt[tnb + c * HW];
+  const double dot = (double)N[0] * Nt[0] + (double)N[1] * Nt[1] + (double)N[2] * Nt[2];
+  const double e1 = 1.0 - dot;
+  const float s1 = e1 > 0 ? 1.f : (e1 < 0 ? -1.f : 0.f);
+  const float ed = D - Dt;
+  a.gD[p] = m * a.a_d * sgn_f(ed);
+  double nl1 = 0;
+  for (int c = 0; c < 3; ++c) {
+    const float ec = N[c] - Nt[c];
+    nl1 += fabs((double)N[c] - (double)Nt[c]);
+    a.gN[nb + c * HW] = m * (-a.a_cos * s1 * Nt[c] + a.a_nl1 * sgn_f(ec));
+  }
+  if (m != 0.f) {
+    const double ad = fabs((double)D - (double)Dt);
+    l[0] += a.a_cos * fabs(e1);
+    l[1] += a.a_nl1 * nl1;
+    l[2] += a.a_d * ad;
+    l[3] += ad;
+  }
+}
+
+__device__ inline int find_slot_by_pix(const ps_slot* __restrict__ sl, int S, int64_t pix_off) {
+  int lo = 0, hi = S - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sl[mid].pix_off <= pix_off) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Strict order of hits: float32 depth, then record index (= plane order).
 __device__ inline bool key_less(float ta, int ia, float tb, int ib) {
   return ta < tb || (ta == tb && ia < ib);
@@ -374,6 +450,8 @@ __device__ inline bool key_less(float ta, int ia, float tb, int ib) {
 
 // error plumbing (api.hip)
 extern "C" int ps_set_error(int code, const char* fmt, ...);
+// Loss sums per job from the per-8x8-block partials of the loss region.
+int ps_loss_reduce(const ps_layout* L, void* ws, float* loss, void* stream);
 #define PS_HIP_CHECK(expr)                                                      \
   do {                                                                          \
     hipError_t _e = (expr);                                                     \

@@ -70,6 +70,10 @@ struct RenderArgs {
   float* g_center;
   float* g_quat;
   float* g_radii;
+  // the forward that forms the render loss (Eq. 14) of the pixels it renders:
+  // gradients and per-8x8-block partial sums (null: plain forward)
+  LossView loss;
+  double* loss_part;
 };
 
 struct ItemCtx {
@@ -423,6 +427,27 @@ struct FwdSink {
   }
 };
 
+// The render loss of this 8x8 block's pixels (the loss kernel's arithmetic)
+// and the block's partial sums, stored where the loss kernel stores them: at
+// the job's first item plus the block's index in tile order.
+__device__ void block_loss(const RenderArgs& a, int item, const ItemCtx& c, bool pix_on, float D, float N0,
+                           float N1, float N2) {
+  const ItemDesc d = a.items[item];
+  const ps_slot& sl = a.slots[find_slot_by_pix(a.slots, a.S, d.pix_off)];
+  double l[4] = {0, 0, 0, 0};
+  if (pix_on) {
+    const float N[3] = {N0, N1, N2};
+    loss_pixel(a.loss, sl, c.px, c.py, D, N, l);
+  }
+  for (int q = 0; q < 4; ++q) l[q] = wave_sum_double(l[q]);
+  if (threadIdx.x == 0) {
+    const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
+    const int tile = (d.oy / sl.tile_h) * sl.tiles_x + d.ox / sl.tile_w;
+    double* o = a.loss_part + 4 * ((size_t)sl.item_begin + (size_t)tile * sub_per + d.sub);
+    o[0] = l[0]; o[1] = l[1]; o[2] = l[2]; o[3] = l[3];
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   __shared__ StageLds stage;
@@ -432,7 +457,13 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   long long* dg = a.diag + (size_t)blockIdx.x * D_NUM;
   if (diag && threadIdx.x < D_BWD_SETUP) dg[threadIdx.x] = 0;
   ItemCtx c;
-  if (item_setup(a, blockIdx.x, c) != 0) return;
+  const int st = item_setup(a, blockIdx.x, c);
+  if (st != 0) {
+    // no render here; the loss still needs the block's partials (zero) and,
+    // for a camera out of range, zero gradients
+    if (a.loss_part) block_loss(a, blockIdx.x, c, st == 2 && c.inimg, 0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   c.stage = &stage;
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
@@ -459,6 +490,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
     a.normal[nb + c.HW] = s.N1;
     a.normal[nb + 2 * c.HW] = s.N2;
   }
+  if (a.loss_part) block_loss(a, blockIdx.x, c, c.inimg, s.D, s.N0, s.N1, s.N2);
 }
 
 // ------------------------------------------------------------------ backward
@@ -1019,6 +1051,28 @@ extern "C" int plane_render_fwd(const ps_layout* L, void* ws, const ps_camera* c
   a.trans = trans;
   a.count = count;
   return launch_fwd(a, stream);
+}
+
+extern "C" int plane_render_fwd_loss(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,
+                                     const float* lambda, const ps_params* prm, float* depth, float* normal,
+                                     const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
+                                     const int64_t* tgt_off, int n_tgt, float a_cos, float a_nl1, float a_d,
+                                     float* loss, float* g_depth, float* g_normal, void* stream) {
+  RenderArgs a;
+  int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, "plane_render_fwd_loss");
+  if (rc) return rc;
+  if (!depth || !normal || !tgt_depth || !tgt_normal || !loss || !g_depth || !g_normal || (tgt_off && n_tgt <= 0))
+    return ps_set_error(PS_ERR_INVALID, "plane_render_fwd_loss: bad argument");
+  a.depth = depth;
+  a.normal = normal;
+  a.loss.Dt = tgt_depth; a.loss.Nt = tgt_normal; a.loss.mask = mask;
+  a.loss.tgt_off = tgt_off; a.loss.n_cams = tgt_off ? n_tgt : 0;
+  a.loss.a_cos = a_cos; a.loss.a_nl1 = a_nl1; a.loss.a_d = a_d;
+  a.loss.gD = g_depth; a.loss.gN = g_normal;
+  a.loss_part = (double*)((char*)ws + L->region[R_LOSS]);
+  rc = launch_fwd(a, stream);
+  if (rc) return rc;
+  return ps_loss_reduce(L, ws, loss, stream);
 }
 
 extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const float* quat,

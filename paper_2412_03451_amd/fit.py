@@ -190,8 +190,9 @@ class BatchFit:
 
     # ------------------------------------------------------------------ one step
     def _step(self, mark=None, ite=None):
-        """One iteration; mark() (if given) is called between the phases,
-        ite (if given) replaces the state's iteration counter."""
+        """One iteration; mark() (if given) is called between the phases
+        (schedule + project, bin, forward + loss, backward, Adam), ite (if
+        given) replaces the state's iteration counter."""
         cfg = self.cfg
         rend = self.rend
         m = mark or (lambda: None)
@@ -203,10 +204,9 @@ class BatchFit:
         m()
         rend.bin(check_capacity=False)
         m()
-        D, N = rend.forward()
-        m()
-        loss, gD, gN = rend.loss_cam(D, N, self.tgt_depth, self.tgt_normal, self.tgt_off, mask=self.mask,
-                                     a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2])
+        # forward and render loss in one pass (plane_render_fwd_loss)
+        D, N, loss, gD, gN = rend.forward_loss(self.tgt_depth, self.tgt_normal, self.tgt_off, mask=self.mask,
+                                               a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2])
         m()
         gc, gq, gr = rend.backward(self.c, self.q, self.r, self.lam, gD, gN)
         if cfg.single_radii:

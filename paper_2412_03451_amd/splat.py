@@ -228,6 +228,25 @@ class Renderer:
                                              _stream()))
         return loss, gD, gN
 
+    def forward_loss(self, tgt_depth, tgt_normal, tgt_off=None, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0):
+        """Forward that forms the render loss as it composites
+        (plane_render_fwd_loss): depth, normal, loss [jobs, 4], g_depth,
+        g_normal, the bits of forward() followed by loss_cam() / loss()."""
+        P = self.n_pixels
+        depth = torch.empty(P, dtype=torch.float32, device=self.device)
+        normal = torch.empty(3 * P, dtype=torch.float32, device=self.device)
+        loss = torch.empty(len(self.jobs), 4, dtype=torch.float32, device=self.device)
+        gD = torch.empty_like(depth)
+        gN = torch.empty_like(normal)
+        prm = self.params.c()
+        _, _, _, lam = self._inputs
+        n_tgt = 0 if tgt_off is None else int(tgt_off.numel())
+        check(self.lib.plane_render_fwd_loss(C.byref(self.L), _ptr(self.ws), _ptr(self.cams), self.n_cams, _ptr(lam),
+                                             C.byref(prm), _ptr(depth), _ptr(normal), _ptr(tgt_depth),
+                                             _ptr(tgt_normal), _ptr(mask), _ptr(tgt_off), n_tgt, a_cos, a_nl1, a_d,
+                                             _ptr(loss), _ptr(gD), _ptr(gN), _stream()))
+        return depth, normal, loss, gD, gN
+
     def backward(self, center, quat, radii, lam, g_depth, g_normal, diagnostics: bool = False):
         K = int(center.shape[0])
         gc = torch.empty(K, 3, dtype=torch.float32, device=self.device)

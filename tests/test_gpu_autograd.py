@@ -97,3 +97,40 @@ def test_list_storing_variant_gives_the_same_bits(mode, lam):
         res.append((D.detach().clone(), N.detach().clone(), c.grad.clone(), q.grad.clone(), rr.grad.clone()))
     for x, y in zip(*res):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_forward_loss_matches_forward_then_loss(tile):
+    """plane_render_fwd_loss gives the bits of plane_render_fwd followed by
+    the loss call: three jobs of two sizes (one ragged against the tiles),
+    per-camera targets with a mask, and the job-ordered targets."""
+    from paper_2412_03451_amd.splat import Job, Renderer
+    ps = synth.random_planes(90, seed=31, independent_radii=True)
+    c0 = synth.tiny_camera()
+    c1 = synth.scaled_camera(synth.tiny_camera(), 100, 70, 80.0)
+    cams = [c0, c1, c0]
+    jobs = [Job(0, 90, 0, 128, 96, tile), Job(0, 60, 1, 100, 70, tile), Job(30, 90, 2, 128, 96, tile)]
+    r = Renderer(jobs, cams)
+    lam = torch.tensor([9.0], device="cuda")
+    r.project(_dev(ps.center), _dev(ps.quat), _dev(ps.radii), lam)
+    r.bin()
+    rng = np.random.default_rng(7)
+    sizes = [128 * 96, 100 * 70, 128 * 96]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    P = int(offs[-1])
+    tD = _dev(rng.uniform(0.5, 4, size=P).astype(np.float32))
+    tN = _dev(rng.normal(size=3 * P).astype(np.float32))
+    mask = torch.as_tensor(rng.uniform(size=P) < 0.8, dtype=torch.uint8, device="cuda")
+    D0, N0 = r.forward()
+    off = torch.as_tensor(offs[:-1], dtype=torch.int64, device="cuda")
+    for kwargs in ({}, {"tgt_off": off, "mask": mask}):
+        if "tgt_off" in kwargs:
+            l0, gD0, gN0 = r.loss_cam(D0, N0, tD, tN, kwargs["tgt_off"], mask=kwargs["mask"])
+        else:
+            l0, gD0, gN0 = r.loss(D0, N0, tD, tN)
+        D1, N1, l1, gD1, gN1 = r.forward_loss(tD, tN, **kwargs)
+        torch.cuda.synchronize()
+        print(f"tile {tile} {sorted(kwargs)}: loss {l1.cpu().numpy().round(3).tolist()}", flush=True)
+        assert torch.equal(D0, D1) and torch.equal(N0, N1)
+        assert torch.equal(gD0, gD1) and torch.equal(gN0, gN1)
+        assert torch.equal(l0, l1)

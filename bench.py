@@ -491,6 +491,8 @@ def main():
                     help="send every pixel through the exact round-based ordering path")
     ap.add_argument("--phase-steps", type=int, default=50,
                     help="eager steps timed phase by phase (per-kernel durations), spread over the timed steps")
+    ap.add_argument("--sync-every", type=int, default=0,
+                    help="synchronise after every N timed replays (for hardware-counter runs; off by default)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     ap.add_argument("--workload", default="room", choices=("room", "scene-fit", "memory", "batched", "initnet",
@@ -587,6 +589,8 @@ def main():
         fit.graph.replay()
         if i + 1 == n_early:
             early.record(stream)
+        if args.sync_every and (i + 1) % args.sync_every == 0:
+            torch.cuda.synchronize()
     end.record(stream)
     torch.cuda.synchronize()
     ms_step = start.elapsed_time(end) / args.steps

@@ -112,6 +112,8 @@ typedef struct ps_layout {
   int32_t n_planes;    /* planes referenced: max plane_end */
   int32_t max_items;   /* 8x8 blocks of the largest job */
   int32_t max_chunks;  /* groups of 64 tiles of the largest job */
+  int32_t slots_sorted; /* plane_begin and plane_end nondecreasing over the slots */
+  int32_t pad;
   size_t region[PS_NUM_REGIONS]; /* byte offsets inside the workspace */
   size_t ws_bytes;
 } ps_layout;

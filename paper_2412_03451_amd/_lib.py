@@ -44,6 +44,7 @@ class PsLayout(C.Structure):
     _fields_ = [("n_slots", C.c_int32), ("n_records", C.c_int32), ("n_tiles", C.c_int32),
                 ("n_items", C.c_int32), ("n_pixels", C.c_int64), ("pair_capacity", C.c_int64),
                 ("max_sub", C.c_int32), ("n_planes", C.c_int32), ("max_items", C.c_int32), ("max_chunks", C.c_int32),
+                ("slots_sorted", C.c_int32), ("pad", C.c_int32),
                 ("region", C.c_size_t * PS_NUM_REGIONS), ("ws_bytes", C.c_size_t)]
 
 

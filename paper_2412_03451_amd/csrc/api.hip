@@ -69,6 +69,10 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
   out->max_sub = max_sub;
   out->max_items = max_items;
   out->max_chunks = max_chunks;
+  out->slots_sorted = 1;
+  for (int s = 1; s < n_slots; ++s)
+    if (slots[s].plane_begin < slots[s - 1].plane_begin || slots[s].plane_end < slots[s - 1].plane_end)
+      out->slots_sorted = 0;
   out->n_planes = n_planes;
   const size_t R = (size_t)rec, T = (size_t)tiles, C = (size_t)pair_capacity;
   const size_t sizes[PS_NUM_REGIONS] = {

@@ -74,6 +74,7 @@ struct RenderArgs {
   // gradients and per-8x8-block partial sums (null: plain forward)
   LossView loss;
   double* loss_part;
+  int slots_sorted;   // plane ranges nondecreasing over the slots
 };
 
 struct ItemCtx {
@@ -883,8 +884,20 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
   double gp[3] = {0, 0, 0}, gw[3] = {0, 0, 0}, gr[4] = {0, 0, 0, 0};
   double qn[4] = {0, 0, 0, 0}, qnorm = 0;
   const bool ok = !a.counters[C_OVERFLOW];
-  for (int s = 0; s < a.S && ok; ++s) {
+  // the slots holding plane k, in slot order: with sorted plane ranges they
+  // are a run starting at the first slot whose range ends after k
+  int s0 = 0;
+  if (a.slots_sorted) {
+    int lo = 0, hi = a.S;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (a.slots[mid].plane_end > k) hi = mid; else lo = mid + 1;
+    }
+    s0 = lo;
+  }
+  for (int s = s0; s < a.S && ok; ++s) {
     const ps_slot sl = a.slots[s];
+    if (a.slots_sorted && sl.plane_begin > k) break;
     if (k < sl.plane_begin || k >= sl.plane_end) continue;
     if (sl.cam < 0 || sl.cam >= a.n_cams) continue;
     const int r = sl.rec_begin + (k - sl.plane_begin);
@@ -975,6 +988,7 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
   memset(&a, 0, sizeof(a));
   a.slots = (const ps_slot*)(base + L->region[R_SLOTS]);
   a.S = L->n_slots;
+  a.slots_sorted = L->slots_sorted;
   a.n_items = L->n_items;
   a.recs = (const Rec*)(base + L->region[R_REC]);
   a.items = (const ItemDesc*)(base + L->region[R_ITEMS]);

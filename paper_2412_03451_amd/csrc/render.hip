@@ -495,7 +495,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
 }
 
 // ------------------------------------------------------------------ backward
-constexpr int kChunk = 12;   // hits per lane kept in LDS per recompute pass
+constexpr int kChunk = 8;    // hits per lane kept in LDS per recompute pass
 
 struct BwdLds {
   int pos[kChunk][64];

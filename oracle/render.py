@@ -17,6 +17,10 @@ leaves open (each also listed in the design doc):
   uses sigmoid(.) without the factor 2.
 * Eq. 9's "otherwise" gives w_Y on a tie, Eq. 7's "otherwise" takes r^{x-}
   at P_X = 0.
+* mode "G", the Gaussian splat function of Eq. 5 (the paper's comparison):
+  the covariance is planar with standard deviations equal to the radii on
+  the hit's side, w = exp(-((P_X / r_X)^2 + (P_Y / r_Y)^2) / 2); no lambda,
+  never opaque; the filter keeps w >= tau.
 * intersections with |d . n| <= 1e-12 |d| or depth t <= z_near are no hits.
 * the filter keeps w >= tau; the survivors are ordered by depth, and the
   per-ray order is decided on the depth rounded to float32 (the precision of
@@ -42,13 +46,19 @@ class OracleParams:
     M: int = 30             # nearest intersections composited per ray (Sec. 3.2)
     tau: float = 1e-4       # weight filter threshold (Sec. 3.2)
     z_near: float = 0.01    # near clip in metres (not in the paper)
-    weight_mode: str = "A"  # "A": min(1, 2 sigmoid(5 lambda a)); "B": sigmoid(5 lambda a)
+    weight_mode: str = "A"  # "A": min(1, 2 sigmoid(5 lambda a)); "B": sigmoid(5 lambda a);
+    #                         "G": the Gaussian of Eq. 5 (the ablation's splat function)
     two_sided: bool = True
 
 
 def lambda_at(ite: int) -> float:
     """Eq. 10: lambda = min(20 e^{-(1 - 0.001 ite)}, 300), ite counted from 0."""
     return min(20.0 * math.exp(-(1.0 - 0.001 * ite)), 300.0)
+
+
+def gauss_bound(prm: OracleParams) -> float:
+    """Q such that the Gaussian weight exp(-q/2) >= tau  <=>  q <= Q."""
+    return 2.0 * math.log(1.0 / prm.tau)
 
 
 def fringe_margin(lam: float, prm: OracleParams) -> float:
@@ -114,6 +124,20 @@ def _pairs(center, quat, radii, cam, lam, pix, prm: OracleParams, cand=None):
     # 1 - w is formed from the same argument by an identity instead of a
     # subtraction (1 - s(z) = s(-z), 1 - 2 s(z) = tanh(-z/2)), so the
     # transmittance behind a nearly opaque layer keeps its precision.
+    if prm.weight_mode == "G":
+        # Eq. 5: exp(-(x - p)^T Sigma^-1 (x - p) / 2) with the planar covariance
+        # of standard deviations r along v_x and v_y (the radius on the hit's
+        # side, as Eq. 7-8 pick it): q = (P_X / r_X)^2 + (P_Y / r_Y)^2
+        qg = (PX / rX) ** 2 + (PY / rY) ** 2
+        w = torch.exp(-qg / 2)
+        omw = -torch.expm1(-qg / 2)
+        keep = valid & (qg <= gauss_bound(prm))       # filter: exp(-q/2) >= tau
+        if cand is not None:
+            keep = keep & cand
+        n_cam = n @ Rcw.T
+        if prm.two_sided:
+            n_cam = n_cam * (-torch.sign(num))[..., None]
+        return dict(t=t, w=w, omw=omw, keep=keep, n=n_cam, PX=PX, PY=PY, rX=rX, rY=rY, num=num, den=den)
     if prm.weight_mode == "A":
         wX, wY = 2 * torch.sigmoid(zX), 2 * torch.sigmoid(zY)
         oX, oY = torch.tanh(-zX / 2), torch.tanh(-zY / 2)
@@ -225,12 +249,14 @@ def footprint_tiles(center, quat, radii, cam, lam, prm: OracleParams, tw: int, t
     radii = _t(radii).detach().numpy()
     Rcw = np.asarray(cam.R, np.float64)
     tcw = np.asarray(cam.t, np.float64)
-    dl = fringe_margin(lam, prm)
+    gauss = prm.weight_mode == "G"
+    dl = 0.0 if gauss else fringe_margin(lam, prm)
+    ext = math.sqrt(gauss_bound(prm)) if gauss else 1.0   # the Gaussian's footprint: |P| <= r sqrt(Q)
     ntx = (cam.width + tw - 1) // tw
     nty = (cam.height + th - 1) // th
     out = np.zeros((center.shape[0], 4), np.int64)
     for k in range(center.shape[0]):
-        xp, xm, yp, ym = radii[k] + dl
+        xp, xm, yp, ym = radii[k] * ext + dl
         corners = [center[k] + a * vx[k] + b * vy[k] for a, b in ((xp, yp), (-xm, yp), (-xm, -ym), (xp, -ym))]
         cc = [Rcw @ c + tcw for c in corners]
         poly = []

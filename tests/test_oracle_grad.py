@@ -25,12 +25,12 @@ def _objective(c, q, r, cam, lam, gD, gN, prm):
     return float((gD * D).sum() + (gN * N).sum()), sig
 
 
-@pytest.mark.parametrize("lam", [oracle.lambda_at(0), 60.0])
-def test_autograd_matches_central_differences(lam):
+@pytest.mark.parametrize("lam,mode", [(oracle.lambda_at(0), "A"), (60.0, "A"), (10.0, "G")])
+def test_autograd_matches_central_differences(lam, mode):
     ps = synth.random_planes(12, seed=11, independent_radii=True, center_range=0.6)
     cam = synth.Camera(40, 30, 30.0, 30.0, 20.0, 15.0, np.eye(3, dtype=np.float32),
                        np.array([0.0, 0.0, 3.0], np.float32))
-    prm = OracleParams()
+    prm = OracleParams(weight_mode=mode)
     rng = np.random.default_rng(0)
     P = cam.width * cam.height
     gD = torch.as_tensor(rng.normal(size=P))

@@ -79,6 +79,37 @@ def test_fronto_parallel_closed_form(mode, lam):
         assert np.all(N[2][inside] == -1.0)
 
 
+def test_fronto_parallel_gaussian_closed_form():
+    """Mode "G" (Eq. 5): on a fronto-parallel plane the weight is the planar
+    Gaussian of the in-plane offsets with the hit side's radius as standard
+    deviation, cut at tau; depth w (z0 + 3), normal (0, 0, -w)."""
+    x0, y0, z0 = 0.11, -0.07, 0.4
+    radii = (0.1, 0.06, 0.08, 0.05)
+    c, q, r = one_plane((x0, y0, z0), radii=radii)
+    cam = synth.tiny_camera()
+    D, N, aux = oracle.render(c, q, r, cam, 50.0, OracleParams(weight_mode="G"))
+    D = D.numpy()
+    N = N.numpy()
+    c32 = c[0].astype(np.float64)
+    r32 = r[0].astype(np.float64)
+    depth = c32[2] + 3.0
+    cut = 0
+    for j in range(cam.height):
+        for i in range(cam.width):
+            px = depth * (i + 0.5 - cam.cx) / cam.fx - c32[0]
+            py = depth * (j + 0.5 - cam.cy) / cam.fy - c32[1]
+            sx = r32[0] if px > 0 else r32[1]
+            sy = r32[2] if py > 0 else r32[3]
+            w = math.exp(-0.5 * ((px / sx) ** 2 + (py / sy) ** 2))
+            if w < 1e-4:
+                w = 0.0
+                cut += 1
+            assert D[j, i] == pytest.approx(w * depth, rel=1e-12, abs=1e-13)
+            assert N[2, j, i] == pytest.approx(-w, rel=1e-12, abs=1e-13)
+    assert 0 < cut < cam.width * cam.height
+    assert D.max() < depth                     # never opaque
+
+
 # ---------------------------------------------------------------- P2: two planes
 def test_two_stacked_planes_closed_form():
     lam = 30.0

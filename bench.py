@@ -407,7 +407,8 @@ def init_ablation_bench(args):
     maps (Sec. 3.1: fused points at stride 4 and 2 cm voxels), on the scene's
     bounding sphere (Sec. 4.3, radii 0.05), and the noisy ground truth of the
     throughput workload; the depth initialisation is also fitted without
-    splitting and with single-direction radii (the plane-radii ablation).  Each fit ends with the plane merge (Sec. 3.3, 25 degrees and
+    splitting, with single-direction radii (the plane-radii ablation) and with
+    the Gaussian splat function of Eq. 5 in place of the rectangle one.  Each fit ends with the plane merge (Sec. 3.3, 25 degrees and
     0.1 cm), timed, with its instance count beside the ground truth's.  Depth L1 over all views at lambda = 300 every 500
     iterations; fit wall-times exclude the evaluations; the initialisation
     kernels are timed on their own."""
@@ -415,6 +416,7 @@ def init_ablation_bench(args):
     from paper_2412_03451_amd import learned_init as li
     from paper_2412_03451_amd import scene_init as si
     from paper_2412_03451_amd.fit import FitConfig, SceneFit
+    from paper_2412_03451_amd.splat import SplatParams
 
     gt, init, cams, info = build_workload(100)
     V, W, H = len(cams), cams[0].width, cams[0].height
@@ -438,12 +440,13 @@ def init_ablation_bench(args):
     sphere_init, sphere_ms = timed(lambda: si.init_sphere(pts, K, seed=0))
     log(f"depth_points: {n} fused points from {V} views in {pts_ms:.2f} ms; plane_init_points {planes_ms:.3f} ms; "
         f"plane_init_sphere {sphere_ms:.3f} ms")
-    runs = {"depth": (depth_init, 1000, False), "depth, no splitting": (depth_init, 0, False),
-            "depth, single radii": (depth_init, 1000, True), "sphere": (sphere_init, 1000, False),
-            "noisy-gt": ((init.center, init.quat, init.radii), 1000, False)}
+    runs = {"depth": (depth_init, 1000, False, 0), "depth, no splitting": (depth_init, 0, False, 0),
+            "depth, single radii": (depth_init, 1000, True, 0), "depth, Gaussian splat": (depth_init, 1000, False, 2),
+            "sphere": (sphere_init, 1000, False, 0),
+            "noisy-gt": ((init.center, init.quat, init.radii), 1000, False, 0)}
     out = {}
-    for name, (planes, split_every, single) in runs.items():
-        fit = SceneFit(*planes, cams, tD, tN,
+    for name, (planes, split_every, single, mode) in runs.items():
+        fit = SceneFit(*planes, cams, tD, tN, params=SplatParams(weight_mode=mode),
                        cfg=FitConfig(check_every=250, split_every=split_every, split_thresh=0.2, single_radii=single))
         curve = [[0, round(fit.depth_l1(lam=300.0), 5)]]
         fit_s = 0.0

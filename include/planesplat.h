@@ -72,7 +72,8 @@ typedef struct ps_params {
   int32_t M;           /* nearest hits composited per ray, 1..30 */
   float tau;           /* weight filter, 0 < tau < 1 */
   float z_near;        /* near clip in metres, > 0 */
-  int32_t weight_mode; /* 0: min(1, 2 sigmoid), 1: sigmoid */
+  int32_t weight_mode; /* 0: min(1, 2 sigmoid), 1: sigmoid, 2: the Gaussian of Eq. 5
+                          (planar, standard deviations the radii of the hit's side) */
   int32_t two_sided;   /* 1: normals face the camera */
   int32_t flags;       /* bit 0: force the exact fallback ordering path (testing);
                           bits 4-5: pending hits kept per lane by the render

@@ -91,8 +91,11 @@ __global__ __launch_bounds__(64) void project_kernel(ProjArgs a) {
   rec.pvy = (float)f.pvy;
 
   // grown rectangle corners in camera coordinates (x_c = R x + t)
-  const double gx[2] = {(double)rad[0] + delta, -((double)rad[1] + delta)};
-  const double gy[2] = {(double)rad[2] + delta, -((double)rad[3] + delta)};
+  // (mode 2, the Gaussian: w >= tau inside the ellipse |P / r| <= sqrt(Q),
+  // so the rectangle of the radii times sqrt(Q))
+  const double ext = a.mode == 2 ? sqrt(delta) : 1.0, grow = a.mode == 2 ? 0.0 : delta;
+  const double gx[2] = {(double)rad[0] * ext + grow, -((double)rad[1] * ext + grow)};
+  const double gy[2] = {(double)rad[2] * ext + grow, -((double)rad[3] * ext + grow)};
   double corner[4][3];
   const double ab[4][2] = {{gx[0], gy[0]}, {gx[1], gy[0]}, {gx[1], gy[1]}, {gx[0], gy[1]}};
   for (int c = 0; c < 4; ++c) {
@@ -229,7 +232,7 @@ extern "C" int plane_project(const ps_layout* L, void* ws, const float* center, 
   if (K < L->n_planes) return ps_set_error(PS_ERR_INVALID, "plane_project: K=%d < planes referenced %d", K, L->n_planes);
   if (n_cams <= 0) return ps_set_error(PS_ERR_INVALID, "plane_project: n_cams <= 0");
   if (!(prm->tau > 0.f && prm->tau < 1.f) || !(prm->z_near > 0.f) || prm->M < 1 || prm->M > kMaxM ||
-      (prm->weight_mode != 0 && prm->weight_mode != 1))
+      (prm->weight_mode < 0 || prm->weight_mode > 2))
     return ps_set_error(PS_ERR_INVALID, "plane_project: bad ps_params");
   if (L->n_records == 0) return PS_OK;
   char* base = (char*)ws;

@@ -303,8 +303,11 @@ __device__ inline double rcp64_fast(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
-// Fringe margin: w >= tau  <=>  a* >= -delta (closed form of the weight).
+// Filter bound of the weight (closed form): modes 0 and 1, the fringe
+// margin delta with w >= tau  <=>  a* >= -delta; mode 2 (the Gaussian of
+// Eq. 5), Q with w >= tau  <=>  q <= Q.
 __device__ __host__ inline double fringe_margin(double lam, double tau, int mode) {
+  if (mode == 2) return 2.0 * log(1.0 / tau);
   const double z = (mode == 0) ? log(2.0 / tau - 1.0) : log(1.0 / tau - 1.0);
   return z / (5.0 * lam);
 }
@@ -315,6 +318,11 @@ __device__ __host__ inline double fringe_margin(double lam, double tau, int mode
 // not by a subtraction: behind a nearly opaque layer the transmittance keeps
 // its relative precision.
 __device__ inline float splat_weight(float a, float lam5, int mode, float& omw) {
+  if (mode == 2) {   // Gaussian of Eq. 5, a = q: w = exp(-q/2), 1 - w = -expm1(-q/2)
+    const float h = -0.5f * a;
+    omw = -expm1f(h);
+    return expf(h);
+  }
   const float z = lam5 * a;
   if (mode == 0) {
     if (a >= 0.f) {
@@ -340,14 +348,14 @@ __device__ inline float splat_weight_grad(float a, float w, float omw, float lam
 // Per-lane ray-plane evaluation in float64 (Eq. 4, 6, 7-9 up to a*).
 struct PairGeom {
   double den, PX, PY, t;
-  double a;        // a* = min(a_X, a_Y)
+  double a;        // a* = min(a_X, a_Y); mode 2: q = (P_X / r_X)^2 + (P_Y / r_Y)^2
   bool ok;         // valid hit in front of the near plane with w >= tau
   bool xbranch;    // a_X < a_Y: Eq. 9 takes w_X (tie -> w_Y)
 };
 
 template <class R>
 __device__ inline PairGeom eval_pair(const R& r, double u, double v, double eps_den, double z_near,
-                                     double delta) {
+                                     double delta, int mode) {
   PairGeom g;
   g.den = fma(r.Du, u, fma(r.Dv, v, r.D0));
   const double ax = fma(r.Xu, u, fma(r.Xv, v, r.X0));
@@ -357,6 +365,14 @@ __device__ inline PairGeom eval_pair(const R& r, double u, double v, double eps_
   g.t = r.h * rd;
   g.PX = ax * rd;
   g.PY = ay * rd;
+  if (mode == 2) {   // Gaussian (Eq. 5): standard deviations the radii of the hit's side
+    const double qx = g.PX / (g.PX > 0.0 ? (double)r.rxp : (double)r.rxm);
+    const double qy = g.PY / (g.PY > 0.0 ? (double)r.ryp : (double)r.rym);
+    g.a = qx * qx + qy * qy;
+    g.xbranch = true;
+    g.ok = okd && (g.t > z_near) && (g.a <= delta);
+    return g;
+  }
   const double aX = (g.PX > 0.0) ? (double)r.rxp - g.PX : (double)r.rxm + g.PX;
   const double aY = (g.PY > 0.0) ? (double)r.ryp - g.PY : (double)r.rym + g.PY;
   g.xbranch = aX < aY;

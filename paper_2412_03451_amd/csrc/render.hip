@@ -307,7 +307,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
       staged(S, j, rec, nrm);
       const int ri = S.rec[j];
       evals += __popcll(ballot(!done));
-      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
       const bool hit = g.ok && !done;
       const float t32 = (float)g.t;
       const float a32 = (float)g.a;
@@ -378,7 +378,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
         staged(S, j, rec, nrm);
         const int ri = S.rec[j];
         evals += __popcll(ballot(need));
-        const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+        const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
         if (need && g.ok) {
           const float t32 = (float)g.t;
           const float a32 = (float)g.a;
@@ -607,7 +607,7 @@ __device__ inline void replay(const RenderArgs& a, const ItemCtx& c, BwdSink& s,
         rec.rxp = h5.x; rec.rxm = h5.y; rec.ryp = h5.z; rec.rym = h5.w;
         nrm[0] = h6.x; nrm[1] = h6.y; nrm[2] = h6.z;
       }
-      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
       const float t32 = (float)g.t;
       const float a32 = (float)g.a;
       float pl[1];
@@ -642,7 +642,7 @@ __device__ inline void load_lists(const RenderArgs& a, const ItemCtx& c, BwdSink
         rec.rxp = h5.x; rec.rxm = h5.y; rec.ryp = h5.z; rec.rym = h5.w;
         nrm[0] = h6.x; nrm[1] = h6.y; nrm[2] = h6.z;
       }
-      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
       float pl[1];
       s.payload((float)g.t, nrm, pl);
       s.commit((float)g.t, as, pos, pl);
@@ -804,17 +804,30 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
           staged(stage, j, rec, nrm);
           const float2 pv = stage.pv[j];
           const float T = L.T[k][lane], gw = L.cg[k][lane];
-          const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
+          const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
           const float t = (float)g.t, a32 = (float)g.a;
           const float PX = (float)g.PX, PY = (float)g.PY, den = (float)g.den;
           float omw;
           const float w = splat_weight(a32, lam5, a.mode, omw);
           const float Tw = T * w;
-          const float ga = gw * splat_weight_grad(a32, w, omw, lam5, a.mode);
-          const float gaX = g.xbranch ? ga : 0.f, gaY = g.xbranch ? 0.f : ga;
           const bool xp = g.PX > 0.0, yp = g.PY > 0.0;
-          const float gPX = xp ? -gaX : gaX;
-          const float gPY = yp ? -gaY : gaY;
+          float gPX, gPY, grx, gry;   // dL/dP_X, dL/dP_Y, dL/d(radius of the hit's side) along X, Y
+          if (a.mode == 2) {
+            // w = exp(-q/2), q = (P_X / s_X)^2 + (P_Y / s_Y)^2
+            const float gq = -0.5f * gw * w;
+            const float sx = xp ? rec.rxp : rec.rxm, sy = yp ? rec.ryp : rec.rym;
+            const float ux = PX / sx, uy = PY / sy;
+            gPX = 2.f * gq * ux / sx;
+            gPY = 2.f * gq * uy / sy;
+            grx = -2.f * gq * ux * ux / sx;
+            gry = -2.f * gq * uy * uy / sy;
+          } else {
+            const float ga = gw * splat_weight_grad(a32, w, omw, lam5, a.mode);
+            grx = g.xbranch ? ga : 0.f;
+            gry = g.xbranch ? 0.f : ga;
+            gPX = xp ? -grx : grx;
+            gPY = yp ? -gry : gry;
+          }
           // d.vx = (P_X + (p - o).vx) / t, d.vy likewise (x = o + t d)
           const float it = __builtin_amdgcn_rcpf(t);
           const float G = Tw * gD + (gPX * (PX + pv.x) + gPY * (PY + pv.y)) * it;
@@ -828,10 +841,10 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
           A[6] = Tw * gN0;
           A[7] = Tw * gN1;
           A[8] = Tw * gN2;
-          A[9] = xp ? gaX : 0.f;
-          A[10] = xp ? 0.f : gaX;
-          A[11] = yp ? gaY : 0.f;
-          A[12] = yp ? 0.f : gaY;
+          A[9] = xp ? grx : 0.f;
+          A[10] = xp ? 0.f : grx;
+          A[11] = yp ? gry : 0.f;
+          A[12] = yp ? 0.f : gry;
           ++k;
           npos = k < nE ? L.pos[k][lane] : 0x7fffffff;
         }
@@ -982,7 +995,7 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
   if (!cams || !lambda || !prm) return ps_set_error(PS_ERR_INVALID, "%s: null pointer", who);
   if (n_cams <= 0) return ps_set_error(PS_ERR_INVALID, "%s: n_cams <= 0", who);
   if (!(prm->tau > 0.f && prm->tau < 1.f) || !(prm->z_near > 0.f) || prm->M < 1 || prm->M > kMaxM ||
-      (prm->weight_mode != 0 && prm->weight_mode != 1))
+      (prm->weight_mode < 0 || prm->weight_mode > 2))
     return ps_set_error(PS_ERR_INVALID, "%s: bad ps_params", who);
   char* base = (char*)ws;
   memset(&a, 0, sizeof(a));

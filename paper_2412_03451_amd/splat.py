@@ -29,7 +29,7 @@ class SplatParams:
     M: int = 30
     tau: float = 1e-4
     z_near: float = 0.01
-    weight_mode: int = 0   # 0: min(1, 2 sigmoid), 1: sigmoid
+    weight_mode: int = 0   # 0: min(1, 2 sigmoid), 1: sigmoid, 2: Gaussian of Eq. 5
     two_sided: int = 1
     flags: int = 0         # bit 0: exact fallback path; bits 4-5: pending size; bit 6: walk statistics
 

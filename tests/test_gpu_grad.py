@@ -49,14 +49,14 @@ def _check_grads(gpu, ref, abss, label, c=32.0):
         assert cs >= 1 - 1e-8
 
 
-@pytest.mark.parametrize("mode,lam", [(0, oracle.lambda_at(0)), (0, 60.0), (0, 300.0), (1, 20.0)])
+@pytest.mark.parametrize("mode,lam", [(0, oracle.lambda_at(0)), (0, 60.0), (0, 300.0), (1, 20.0), (2, 10.0)])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
 def test_backward_tiny_scene(mode, lam, tile):
     from paper_2412_03451_amd.splat import Renderer, SplatParams
     ps = synth.random_planes(64, seed=0, independent_radii=True)
     tgt = synth.perturb_planes(ps, seed=1, center_sigma=0.05, rot_sigma_deg=5.0)
     cam = synth.tiny_camera()
-    prm = oracle.OracleParams(weight_mode="A" if mode == 0 else "B")
+    prm = oracle.OracleParams(weight_mode="ABG"[mode])
     gD, gN = _upstream(ps, tgt, cam, f32(lam), prm)
     grads, abss = oracle.per_pixel_abs_grad(ps.center, ps.quat, ps.radii, cam, f32(lam), gD, gN, prm)
     r = Renderer.single_scene([cam], ps.K, tile=tile, params=SplatParams(weight_mode=mode))

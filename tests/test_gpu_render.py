@@ -50,15 +50,16 @@ def _check_views(r, D, N, ps, cams, lam, prm=oracle.OracleParams(), label=""):
     return worst
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("lam", [oracle.lambda_at(0), 300.0])
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8)])
 def test_forward_tiny_scene(mode, lam, tile):
+    """Modes 0 and 1 (readings of Eq. 7-9) and 2 (the Gaussian of Eq. 5)."""
     from paper_2412_03451_amd.splat import SplatParams
     ps = synth.random_planes(64, seed=0)
     cam = synth.tiny_camera()
     r, D, N = _render_gpu(ps, [cam], lam, tile, SplatParams(weight_mode=mode))
-    prm = oracle.OracleParams(weight_mode="A" if mode == 0 else "B")
+    prm = oracle.OracleParams(weight_mode="ABG"[mode])
     _check_views(r, D, N, ps, [cam], lam, prm, f"mode {mode} lam {lam:.3g} tile {tile}")
 
 

@@ -25,6 +25,7 @@ struct ProjArgs {
   const float* lambda;
   int n_cams;
   float tau, z_near;
+  double flog;   // filter_log(tau, mode)
   int mode, two_sided;
   Rec* recs;
   BinRec* brecs;
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(64) void project_kernel(ProjArgs a) {
     return;
   }
   const double lam = (double)a.lambda[0];
-  const double delta = fringe_margin(lam, (double)a.tau, a.mode);
+  const double delta = fringe_margin(lam, a.flog, a.mode);
   const float rad[4] = {a.radii[4 * k + 0], a.radii[4 * k + 1], a.radii[4 * k + 2], a.radii[4 * k + 3]};
 
   Rec rec;
@@ -243,6 +244,7 @@ extern "C" int plane_project(const ps_layout* L, void* ws, const float* center, 
   a.center = center; a.quat = quat; a.radii = radii;
   a.cams = cams; a.lambda = lambda; a.n_cams = n_cams;
   a.tau = prm->tau; a.z_near = prm->z_near; a.mode = prm->weight_mode; a.two_sided = prm->two_sided;
+  a.flog = filter_log((double)prm->tau, prm->weight_mode);
   a.recs = (Rec*)(base + L->region[R_REC]);
   a.brecs = (BinRec*)(base + L->region[R_BINREC]);
   hipLaunchKernelGGL(project_kernel, dim3((a.R + 63) / 64), dim3(64), 0, (hipStream_t)stream, a);

@@ -304,12 +304,17 @@ __device__ inline double rcp64_fast(double x) {
 }
 
 // Filter bound of the weight (closed form): modes 0 and 1, the fringe
-// margin delta with w >= tau  <=>  a* >= -delta; mode 2 (the Gaussian of
-// Eq. 5), Q with w >= tau  <=>  q <= Q.
-__device__ __host__ inline double fringe_margin(double lam, double tau, int mode) {
+// margin delta with w >= tau  <=>  a* >= -delta, delta = z / (5 lambda) with
+// z = ln(2/tau - 1) (mode 0) or ln(1/tau - 1) (mode 1); mode 2 (the Gaussian
+// of Eq. 5), Q with w >= tau  <=>  q <= Q, Q = 2 ln(1/tau).  The logarithm
+// is a constant of the launch, taken on the host (filter_log); the kernels
+// only divide by 5 lambda.
+inline double filter_log(double tau, int mode) {
   if (mode == 2) return 2.0 * log(1.0 / tau);
-  const double z = (mode == 0) ? log(2.0 / tau - 1.0) : log(1.0 / tau - 1.0);
-  return z / (5.0 * lam);
+  return (mode == 0) ? log(2.0 / tau - 1.0) : log(1.0 / tau - 1.0);
+}
+__device__ inline double fringe_margin(double lam, double flog, int mode) {
+  return mode == 2 ? flog : flog / (5.0 * lam);
 }
 
 // Splat weight from a* (Eq. 7-9; mode 0 clamps the printed 2 sigmoid at 1)
@@ -353,9 +358,9 @@ struct PairGeom {
   bool xbranch;    // a_X < a_Y: Eq. 9 takes w_X (tie -> w_Y)
 };
 
-template <class R>
+template <bool GAUSS, class R>
 __device__ inline PairGeom eval_pair(const R& r, double u, double v, double eps_den, double z_near,
-                                     double delta, int mode) {
+                                     double delta) {
   PairGeom g;
   g.den = fma(r.Du, u, fma(r.Dv, v, r.D0));
   const double ax = fma(r.Xu, u, fma(r.Xv, v, r.X0));
@@ -365,7 +370,7 @@ __device__ inline PairGeom eval_pair(const R& r, double u, double v, double eps_
   g.t = r.h * rd;
   g.PX = ax * rd;
   g.PY = ay * rd;
-  if (mode == 2) {   // Gaussian (Eq. 5): standard deviations the radii of the hit's side
+  if (GAUSS) {   // weight mode 2, the Gaussian (Eq. 5): standard deviations the radii of the hit's side
     const double qx = g.PX / (g.PX > 0.0 ? (double)r.rxp : (double)r.rxm);
     const double qy = g.PY / (g.PY > 0.0 ? (double)r.ryp : (double)r.rym);
     g.a = qx * qx + qy * qy;
@@ -455,6 +460,13 @@ __device__ inline int find_slot_by_pix(const ps_slot* __restrict__ sl, int S, in
     if (sl[mid].pix_off <= pix_off) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+template <class R>
+__device__ inline PairGeom eval_pair_mode(const R& r, double u, double v, double eps_den, double z_near,
+                                          double delta, int mode) {
+  return mode == 2 ? eval_pair<true>(r, u, v, eps_den, z_near, delta)
+                   : eval_pair<false>(r, u, v, eps_den, z_near, delta);
 }
 
 // Strict order of hits: float32 depth, then record index (= plane order).

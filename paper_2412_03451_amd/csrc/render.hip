@@ -46,6 +46,7 @@ struct RenderArgs {
   int n_cams;
   const float* lambda;
   float tau, z_near;
+  double flog;              // filter_log(tau, mode)
   int M, mode, flags, two_sided;
   long long* counters;
   long long* diag;          // per-block statistics (flags bit 6)
@@ -280,7 +281,7 @@ __device__ __forceinline__ void drain(const RenderArgs& a, const ItemCtx& c, int
 // Walk the tile list of one 8x8 block and hand every committed hit, in exact
 // per-ray order, to sink.commit(t, a*, list position, payload), the payload
 // formed by sink.payload(t, normal of the plane).
-template <int P, class Sink>
+template <int P, bool GAUSS, class Sink>
 __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink& sink, float lam5,
                                      double delta, long long& evals, long long& steps) {
   Pending<P> pd;
@@ -307,7 +308,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
       staged(S, j, rec, nrm);
       const int ri = S.rec[j];
       evals += __popcll(ballot(!done));
-      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
+      const PairGeom g = eval_pair<GAUSS>(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
       const bool hit = g.ok && !done;
       const float t32 = (float)g.t;
       const float a32 = (float)g.a;
@@ -378,7 +379,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
         staged(S, j, rec, nrm);
         const int ri = S.rec[j];
         evals += __popcll(ballot(need));
-        const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
+        const PairGeom g = eval_pair<GAUSS>(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
         if (need && g.ok) {
           const float t32 = (float)g.t;
           const float a32 = (float)g.a;
@@ -449,7 +450,7 @@ __device__ void block_loss(const RenderArgs& a, int item, const ItemCtx& c, bool
   }
 }
 
-template <int P>
+template <int P, bool GAUSS>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   __shared__ StageLds stage;
   if (a.counters[C_OVERFLOW]) return;
@@ -468,10 +469,10 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   c.stage = &stage;
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
-  const double delta = fringe_margin((double)lam, (double)a.tau, a.mode);
+  const double delta = fringe_margin((double)lam, a.flog, a.mode);
   FwdSink s{1.f, 0.f, 0.f, 0.f, 0.f, 0, lam5, a.mode, &a, c.pix};
   long long evals = 0, steps = 0;
-  walk<P>(a, c, s, lam5, delta, evals, steps);
+  walk<P, GAUSS>(a, c, s, lam5, delta, evals, steps);
   if (diag) {
     int commits = s.count;
     commits = wave_allreduce(commits, [](int x, int y) { return x + y; });
@@ -607,7 +608,7 @@ __device__ inline void replay(const RenderArgs& a, const ItemCtx& c, BwdSink& s,
         rec.rxp = h5.x; rec.rxm = h5.y; rec.ryp = h5.z; rec.rym = h5.w;
         nrm[0] = h6.x; nrm[1] = h6.y; nrm[2] = h6.z;
       }
-      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
+      const PairGeom g = eval_pair_mode(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
       const float t32 = (float)g.t;
       const float a32 = (float)g.a;
       float pl[1];
@@ -642,7 +643,7 @@ __device__ inline void load_lists(const RenderArgs& a, const ItemCtx& c, BwdSink
         rec.rxp = h5.x; rec.rxm = h5.y; rec.ryp = h5.z; rec.rym = h5.w;
         nrm[0] = h6.x; nrm[1] = h6.y; nrm[2] = h6.z;
       }
-      const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
+      const PairGeom g = eval_pair_mode(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
       float pl[1];
       s.payload((float)g.t, nrm, pl);
       s.commit((float)g.t, as, pos, pl);
@@ -659,7 +660,7 @@ __device__ inline void zero_row(const RenderArgs& a, uint32_t em, int sub) {
 // Partial rows: every (list entry, 8x8 block) row of the tile is written by
 // its block, exactly once in the first pass (the gradient of a candidate the
 // block hits, zeros otherwise); further passes add to it.
-template <int P>
+template <int P, bool GAUSS>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   __shared__ BwdLds L;
   __shared__ StageLds stage;
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   for (int i = lane; i < kBigSort / 32; i += 64) L.vis[i] = 0u;
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
-  const double delta = fringe_margin((double)lam, (double)a.tau, a.mode);
+  const double delta = fringe_margin((double)lam, a.flog, a.mode);
   float gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f;
   if (c.inimg) {
     gD = a.g_depth[c.pix];
@@ -713,7 +714,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
       hits = c.inimg ? a.count[c.pix] : 0;
       load_lists(a, c, s, hits, one_batch, delta);
     } else if (pass == 0) {
-      walk<P>(a, c, s, lam5, delta, evals, steps);
+      walk<P, GAUSS>(a, c, s, lam5, delta, evals, steps);
       hits = s.count;
     } else {
       replay(a, c, s, hits, one_batch, delta);
@@ -804,7 +805,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
           staged(stage, j, rec, nrm);
           const float2 pv = stage.pv[j];
           const float T = L.T[k][lane], gw = L.cg[k][lane];
-          const PairGeom g = eval_pair(rec, c.u, c.v, c.eps, (double)a.z_near, delta, a.mode);
+          const PairGeom g = eval_pair<GAUSS>(rec, c.u, c.v, c.eps, (double)a.z_near, delta);
           const float t = (float)g.t, a32 = (float)g.a;
           const float PX = (float)g.PX, PY = (float)g.PY, den = (float)g.den;
           float omw;
@@ -812,7 +813,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
           const float Tw = T * w;
           const bool xp = g.PX > 0.0, yp = g.PY > 0.0;
           float gPX, gPY, grx, gry;   // dL/dP_X, dL/dP_Y, dL/d(radius of the hit's side) along X, Y
-          if (a.mode == 2) {
+          if (GAUSS) {
             // w = exp(-q/2), q = (P_X / s_X)^2 + (P_Y / s_Y)^2
             const float gq = -0.5f * gw * w;
             const float sx = xp ? rec.rxp : rec.rxm, sy = yp ? rec.ryp : rec.rym;
@@ -1014,6 +1015,7 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
   a.n_cams = n_cams;
   a.lambda = lambda;
   a.tau = prm->tau; a.z_near = prm->z_near; a.M = prm->M; a.mode = prm->weight_mode;
+  a.flog = filter_log((double)prm->tau, prm->weight_mode);
   a.flags = prm->flags; a.two_sided = prm->two_sided;
   a.counters = (long long*)(base + L->region[R_COUNTERS]);
   a.diag = (long long*)(base + L->region[R_DIAG]);
@@ -1024,27 +1026,43 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
 
 }  // namespace
 
+template <bool GAUSS>
+static void launch_fwd_g(RenderArgs& a, hipStream_t st) {
+  switch (pending_of(a.flags)) {
+    case 4: hipLaunchKernelGGL((render_fwd_kernel<4, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((render_fwd_kernel<8, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    case 12: hipLaunchKernelGGL((render_fwd_kernel<12, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((render_fwd_kernel<6, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+  }
+}
+template <bool GAUSS>
+static void launch_bwd_g(RenderArgs& a, hipStream_t st) {
+  switch (pending_of(a.flags)) {
+    case 4: hipLaunchKernelGGL((render_bwd_kernel<4, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((render_bwd_kernel<8, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    case 12: hipLaunchKernelGGL((render_bwd_kernel<12, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    default: hipLaunchKernelGGL((render_bwd_kernel<6, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+  }
+}
+
+// The Gaussian weight (mode 2) has kernels of its own, so the other modes
+// carry no per-candidate test of the mode.
 static int launch_fwd(RenderArgs& a, void* stream) {
   if (a.n_items == 0) return PS_OK;
-  switch (pending_of(a.flags)) {
-    case 4: hipLaunchKernelGGL(render_fwd_kernel<4>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
-    case 8: hipLaunchKernelGGL(render_fwd_kernel<8>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
-    case 12: hipLaunchKernelGGL(render_fwd_kernel<12>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
-    default: hipLaunchKernelGGL(render_fwd_kernel<6>, dim3(a.n_items), dim3(64), 0, (hipStream_t)stream, a); break;
-  }
+  if (a.mode == 2)
+    launch_fwd_g<true>(a, (hipStream_t)stream);
+  else
+    launch_fwd_g<false>(a, (hipStream_t)stream);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
-
 static int launch_bwd(RenderArgs& a, int K, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (a.n_items > 0) {
-    switch (pending_of(a.flags)) {
-      case 4: hipLaunchKernelGGL(render_bwd_kernel<4>, dim3(a.n_items), dim3(64), 0, st, a); break;
-      case 8: hipLaunchKernelGGL(render_bwd_kernel<8>, dim3(a.n_items), dim3(64), 0, st, a); break;
-      case 12: hipLaunchKernelGGL(render_bwd_kernel<12>, dim3(a.n_items), dim3(64), 0, st, a); break;
-      default: hipLaunchKernelGGL(render_bwd_kernel<6>, dim3(a.n_items), dim3(64), 0, st, a); break;
-    }
+    if (a.mode == 2)
+      launch_bwd_g<true>(a, st);
+    else
+      launch_bwd_g<false>(a, st);
   }
   if (K > 0) hipLaunchKernelGGL(bwd_reduce_kernel, dim3(K), dim3(256), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());

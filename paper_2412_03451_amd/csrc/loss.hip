@@ -55,17 +55,17 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a) {
   }
 }
 
-// One 256-thread workgroup per job: strided partial sums, wave sums, then the
-// four wave results added in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void loss_reduce_kernel(const ps_slot* slots, int S, int n_items,
-                                                          const double* part, float* loss) {
-  __shared__ double lds[4][4];
+// One 1024-thread workgroup per job: strided partial sums, wave sums, then
+// the 16 wave results added in a fixed order (deterministic).
+__global__ __launch_bounds__(1024) void loss_reduce_kernel(const ps_slot* slots, int S, int n_items,
+                                                           const double* part, float* loss) {
+  __shared__ double lds[16][4];
   const int s = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int i0 = slots[s].item_begin;
   const int i1 = (s + 1 < S) ? slots[s + 1].item_begin : n_items;
   double acc[4] = {0, 0, 0, 0};
-  for (int i = i0 + tid; i < i1; i += 256) {
+  for (int i = i0 + tid; i < i1; i += 1024) {
     const double4 p = *reinterpret_cast<const double4*>(part + 4 * (size_t)i);
     acc[0] += p.x; acc[1] += p.y; acc[2] += p.z; acc[3] += p.w;
   }
@@ -73,8 +73,11 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const ps_slot* slots, 
   if (lane == 0)
     for (int q = 0; q < 4; ++q) lds[wid][q] = acc[q];
   __syncthreads();
-  if (tid == 0)
-    for (int q = 0; q < 4; ++q) loss[4 * s + q] = (float)(((lds[0][q] + lds[1][q]) + lds[2][q]) + lds[3][q]);
+  if (tid < 4) {
+    double t = lds[0][tid];
+    for (int w = 1; w < 16; ++w) t += lds[w][tid];
+    loss[4 * s + tid] = (float)t;
+  }
 }
 
 }  // namespace
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const ps_slot* slots, 
 // region (used by the loss calls and by the forward that forms the loss).
 int ps_loss_reduce(const ps_layout* L, void* ws, float* loss, void* stream) {
   char* base = (char*)ws;
-  hipLaunchKernelGGL(loss_reduce_kernel, dim3(L->n_slots), dim3(256), 0, (hipStream_t)stream,
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(L->n_slots), dim3(1024), 0, (hipStream_t)stream,
                      (const ps_slot*)(base + L->region[R_SLOTS]), L->n_slots, L->n_items,
                      (const double*)(base + L->region[R_LOSS]), loss);
   PS_HIP_CHECK(hipGetLastError());

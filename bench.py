@@ -68,13 +68,23 @@ def build_workload(n_views: int, seed: int = 0):
     return gt, init, cams, info
 
 
-def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
-    """The float64 oracle on a bounded sample of one view: forward + loss +
-    backward for a block of pixel rows, timed on the host cores."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_rate(init, cam, lam, budget_s: float, threads: int):
+    """Pixels x planes per second of the float64 oracle (forward + loss +
+    backward) on blocks of two pixel rows of one view, for `budget_s`."""
     import torch
     import oracle
-    torch.set_num_threads(os.cpu_count() or 1)
-    cam = cams[0]
+    torch.set_num_threads(threads)
     rows = 2
     rng = np.random.default_rng(0)
     P = cam.width * cam.height
@@ -91,13 +101,28 @@ def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
         L.backward()
         done_px += pix.numel()
     dt = time.perf_counter() - t0
+    return done_px * init.K / dt, done_px, dt, torch.get_num_threads()
+
+
+def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
+    """The float64 oracle on a bounded sample of one view: forward + loss +
+    backward for blocks of pixel rows, timed on the host cores (three
+    quarters of the budget on every core, the rest on one core)."""
+    cam = cams[0]
+    n = os.cpu_count() or 1
+    rate, px, dt, used = _oracle_rate(init, cam, lam, 0.75 * budget_s, n)
+    rate1, px1, dt1, _ = _oracle_rate(init, cam, lam, 0.25 * budget_s, 1)
+    step_s = cam.width * cam.height * init.K / rate
     return {
-        "value": done_px * init.K / dt / 1e6,
+        "value": rate / 1e6,
         "unit": "Mpixel*planes/s",
-        "cores": torch.get_num_threads(),
+        "cores": used,
         "kind": "oracle",
-        "sample": f"{done_px} pixels (rows of view 0, 640x480) x {init.K} planes, float64 forward+loss+backward, "
-                  f"{dt:.1f} s on {os.cpu_count()} host cores ({platform.processor() or platform.machine()})",
+        "sample": f"{px} pixels (rows of view 0, {cam.width}x{cam.height}) x {init.K} planes, float64 "
+                  f"forward+loss+backward, {dt:.1f} s on {used} threads of {n} host cores ({cpu_model()})",
+        "value_1_thread": rate1 / 1e6,
+        "sample_1_thread": f"{px1} pixels in {dt1:.1f} s on one thread",
+        "fit_5000_steps_s_extrapolated": round(5000 * step_s, 1),
     }
 
 
@@ -229,6 +254,10 @@ def batched_bench(args):
     if fit.overflowed():
         raise RuntimeError("pair capacity exceeded during the timed batched steps")
     ms = e0.elapsed_time(e1) / args.steps
+    # the same steps again, phase by phase, with the render statistics
+    fit.restore(start_state)
+    phase_ms, _, cnt = sample_phases(fit, args.steps, min(args.phase_steps, args.steps), st)
+    roof, hits, evals = render_roofline(phase_ms, cnt)
     tiles = {}
     for sc in scenes:
         k = f"{sc.tile[0]}x{sc.tile[1]}" if sc.tile else "16x16"
@@ -241,6 +270,10 @@ def batched_bench(args):
                                f"one view per room per step, lambda from ite 0", "rooms": len(scenes),
                    "planes": int(fit.K), "pixels_per_step": int(fit.rend.n_pixels), "tiles": tiles,
                    "pair_capacity": int(fit.rend.L.pair_capacity)},
+        "phase_ms": {k: round(x, 4) for k, x in phase_ms.items()},
+        "render_stats": {"composited_hits": hits, "pairs_evaluated": evals,
+                         "hits_per_evaluated_pair": round(hits / max(1, evals), 4)},
+        "roofline": roof,
     }
 
 
@@ -480,6 +513,118 @@ def init_ablation_bench(args):
     }
 
 
+def sleep_cycles_for(ms: float, stream) -> int:
+    """Cycles of torch's spin kernel that keep the stream busy for about `ms`."""
+    import torch
+    torch.cuda._sleep(1000)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    torch.cuda._sleep(1_000_000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return max(1000, int(1_000_000 * ms / max(e0.elapsed_time(e1), 1e-3)))
+
+
+def sample_phases(fit, steps: int, n_samples: int, stream):
+    """Per-phase durations and render statistics sampled over a trajectory:
+    every `stride`-th of `steps` steps runs eagerly after a diagnostics pass
+    on its state, the other steps are graph replays (same bits).  Before each
+    phase of a sampled step the stream spins for ~0.5 ms while the host
+    queues the phase's launches, so the events around the phase (on the
+    stream the kernels are launched on) time its kernels back to back, not
+    the host's launch latency.
+    Returns (phase_ms, sum of the phases, counters averaged over the samples)."""
+    import torch
+    names = ("project", "bin", "fwd", "bwd", "adam")   # "fwd": forward with the render loss
+    ev = {n: [] for n in names}
+    n_samples = max(1, min(n_samples, steps))
+    stride = max(1, steps // n_samples)
+    cycles = sleep_cycles_for(0.5, stream)
+    log(f"timing {n_samples} eager steps phase by phase, one every {stride} steps")
+    stats = []
+    for i in range(steps):
+        if i % stride or len(stats) >= n_samples:
+            fit.graph.replay()
+            continue
+        stats.append(fit.diagnose())
+        ends, starts = [], []
+
+        def mark():
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            ends.append(e)
+            if len(ends) <= len(names):
+                torch.cuda._sleep(cycles)
+                b = torch.cuda.Event(enable_timing=True)
+                b.record(stream)
+                starts.append(b)
+        fit._step(mark=mark)
+        torch.cuda.synchronize()
+        for j, n in enumerate(names):
+            ev[n].append(starts[j].elapsed_time(ends[j + 1]))
+    phase_ms = {n: float(np.mean(x)) for n, x in ev.items()}
+    phase_sum = float(sum(phase_ms.values()))
+    cnt = {k: float(np.mean([st[k] for st in stats])) for k in stats[0] if not isinstance(stats[0][k], list)}
+    cnt["max_steps"] = max(st["max_steps"] for st in stats)
+    cnt["max_wave_ticks"] = max(st["max_wave_ticks"] for st in stats)
+    cnt["bwd_max_block_ticks"] = max(st["bwd_max_block_ticks"] for st in stats)
+    return phase_ms, phase_sum, cnt
+
+
+def render_roofline(phase_ms, cnt, traffic=None, peaks=None):
+    """Roofline of the dominant render phase: algorithmic lane operations of
+    the sampled launches (evaluated pairs and composited hits, the kernels'
+    own counts) / the phase's mean launch time, against the vector ALU's
+    non-packed issue rate."""
+    hits = int(round(cnt["composited_hits"]))
+    evals = int(round(cnt["evals"]))
+    dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
+    per_hit = OPS_PER_HIT_FWD if dom == "fwd" else OPS_PER_HIT_BWD
+    ops = evals * OPS_PER_EVAL + hits * per_hit
+    achieved = ops / (phase_ms[dom] * 1e-3) / 1e12
+    roof = {
+        "kernel": "render_fwd_kernel" if dom == "fwd" else "render_bwd_kernel+bwd_reduce_kernel",
+        "bound": "alu",
+        "achieved": round(achieved, 4),
+        "peak": round(MI355X_VALU_TOPS, 2),
+        "unit": "T lane-op/s",
+        "frac": round(achieved / MI355X_VALU_TOPS, 5),
+        "traffic": traffic,
+        "launch_ms": round(phase_ms[dom], 4),
+        "algorithmic_units": f"{evals} evaluated pairs x {OPS_PER_EVAL} + {hits} composited hits x {per_hit} "
+                             f"lane operations",
+    }
+    if peaks:
+        roof["peak_measured"] = peaks
+    return roof, hits, evals
+
+
+def measured_peaks():
+    """The chip's rates measured in the same process: the vector ALU issue
+    rate for fp32 and fp64 fused multiply-adds (ps_valu_probe) and the HBM
+    rate of a 1 GiB device copy (read + write bytes / time)."""
+    import torch
+    from paper_2412_03451_amd.splat import valu_probe
+    f32, _ = valu_probe(0)
+    f64, _ = valu_probe(1)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    st = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        dst.copy_(src)
+        e1.record(st)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    hbm = 2 * src.numel() * 4 / best / 1e9
+    del src, dst
+    return {"valu_fp32_fma_T_lane_op_s": round(f32, 2), "valu_fp64_fma_T_lane_op_s": round(f64, 2),
+            "hbm_copy_GB_s": round(hbm, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -602,62 +747,13 @@ def main():
         raise RuntimeError("pair capacity exceeded during the timed steps")
     final_loss = fit._graph_loss.sum(0).cpu().tolist()
 
-    # per-phase durations and walk statistics, sampled over the same
-    # trajectory: every `stride`-th step runs eagerly with events between the
-    # phases (on the stream the kernels are launched on) after a diagnostics
-    # pass on its state; the other steps are replays (same bits)
+    # per-phase durations and walk statistics, sampled over the same trajectory
     fit.restore(start_state)
-    names = ("project", "bin", "fwd", "bwd", "adam")   # "fwd": forward with the render loss
-    ev = {n: [] for n in names}
-    n_samples = max(1, min(args.phase_steps, args.steps))
-    stride = max(1, args.steps // n_samples)
-    log(f"timing {n_samples} eager steps phase by phase, one every {stride} steps")
-    stats = []
-    for i in range(args.steps):
-        if i % stride or len(stats) >= n_samples:
-            fit.graph.replay()
-            continue
-        stats.append(fit.diagnose())
-        marks = []
-
-        def mark():
-            e = torch.cuda.Event(enable_timing=True)
-            e.record(stream)
-            marks.append(e)
-        fit._step(mark=mark)
-        torch.cuda.synchronize()
-        for j, n in enumerate(names):
-            ev[n].append(marks[j].elapsed_time(marks[j + 1]))
-    phase_ms = {n: float(np.mean(x)) for n, x in ev.items()}
-    eager_ms = float(np.mean([sum(ev[n][k] for n in names) for k in range(len(ev["fwd"]))]))
-    cnt = {k: float(np.mean([st[k] for st in stats])) for k in stats[0] if not isinstance(stats[0][k], list)}
-    cnt["max_steps"] = max(st["max_steps"] for st in stats)
-    cnt["max_wave_ticks"] = max(st["max_wave_ticks"] for st in stats)
-    cnt["bwd_max_block_ticks"] = max(st["bwd_max_block_ticks"] for st in stats)
-    hits = int(round(cnt["composited_hits"]))
-    evals = int(round(cnt["evals"]))
-
+    phase_ms, phase_sum, cnt = sample_phases(fit, args.steps, args.phase_steps, stream)
     pix = V * W * H
     value = pix * K / (ms_step * 1e-3) / 1e6
-    # roofline of the dominant kernel: algorithmic lane operations per launch
-    # (evaluated pairs and composited hits of the step's view) / launch time
     dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
-    per_hit = OPS_PER_HIT_FWD if dom == "fwd" else OPS_PER_HIT_BWD
-    ops = evals * OPS_PER_EVAL + hits * per_hit
-    achieved = ops / (phase_ms[dom] * 1e-3) / 1e12
-    traffic = measured_traffic(dom)
-    roof = {
-        "kernel": "render_fwd_kernel" if dom == "fwd" else "render_bwd_kernel+bwd_reduce_kernel",
-        "bound": "alu",
-        "achieved": round(achieved, 4),
-        "peak": round(MI355X_VALU_TOPS, 2),
-        "unit": "T lane-op/s",
-        "frac": round(achieved / MI355X_VALU_TOPS, 5),
-        "traffic": traffic,
-        "launch_ms": round(phase_ms[dom], 4),
-        "algorithmic_units": f"{evals} evaluated pairs x {OPS_PER_EVAL} + {hits} composited hits x {per_hit} "
-                             f"lane operations",
-    }
+    roof, hits, evals = render_roofline(phase_ms, cnt, measured_traffic(dom), measured_peaks())
     n_items = max(1, int(fit.rend.L.n_items))
     out = {
         "metric": "fwd+bwd Mpixel*planes/s",
@@ -678,10 +774,11 @@ def main():
                                f"{args.start_ite + args.steps - 1} (lambda of Eq. 10), graph-replayed steps",
                    "planes": K, "views_per_step": V, "width": W, "height": H,
                    "pairs_per_step": int(cnt["pairs"])},
-        "eager_ms_per_step": round(eager_ms, 4),
+        "phase_sum_ms": round(phase_sum, 4),
         "phase_ms": {k: round(x, 4) for k, x in phase_ms.items()},
         "final_loss": [round(x, 3) for x in final_loss[:3]],
         "render_stats": {"pending": args.pending, "composited_hits": hits, "pairs_evaluated": evals,
+                         "hits_per_evaluated_pair": round(hits / max(1, evals), 4),
                          "round_path_pixels": int(cnt["slow_pixels"]),
                          "bwd_extra_passes": int(cnt["bwd_extra_passes"]),
                          "walk_steps": int(cnt["steps"]), "walk_steps_max_block": int(cnt["max_steps"]),

@@ -375,6 +375,17 @@ int plane_tie_radii(float* g_radii, int K, void* stream);
 #define PS_N_COUNTERS 20
 int ps_read_counters(const ps_layout* L, void* ws, int64_t out[PS_N_COUNTERS], void* stream);
 
+/* Issue-rate probe of the vector ALU (measurement only, not a step of the
+ * method).  The render kernels' roofline counts lane operations against the
+ * non-packed issue rate; this launch measures that rate.  kind 0: fp32,
+ * kind 1: fp64.  `blocks` workgroups of 256 lanes each run `iters` rounds of
+ * 8 independent fused multiply-adds, so one launch performs
+ * blocks * 256 * iters * 8 lane operations; time it with events on `stream`.
+ * Every lane writes one value of the chain sum to `sink` (device,
+ * blocks * 256 elements of 4 or 8 bytes, caller-owned; sink_bytes is checked).
+ * PS_ERR_INVALID for a bad kind, size or pointer. */
+int ps_valu_probe(int kind, int blocks, int iters, void* sink, size_t sink_bytes, void* stream);
+
 /* Message of the last error on this thread. */
 const char* ps_last_error(void);
 

@@ -333,3 +333,24 @@ def split_planes(center, quat, radii, acc, cnt, scale=None, thresh: float = 0.2)
                           _stream()))
     n = int(k_out.item())
     return oc[:n].contiguous(), oq[:n].contiguous(), orr[:n].contiguous(), parent[:n].contiguous(), first
+
+
+def valu_probe(kind: int, blocks: int = 8192, iters: int = 4096, reps: int = 3):
+    """Measured vector-ALU issue rate in T lane-op/s (ps_valu_probe; kind 0
+    fp32, 1 fp64): the best of `reps` timed launches on the current stream,
+    after one untimed launch.  Returns (rate, sink tensor)."""
+    lib = _lib.load()
+    dt = torch.float32 if kind == 0 else torch.float64
+    sink = torch.empty(blocks * 256, dtype=dt, device="cuda")
+    nbytes = sink.numel() * sink.element_size()
+    st = torch.cuda.current_stream()
+    check(lib.ps_valu_probe(kind, blocks, iters, _ptr(sink), nbytes, _stream()))
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        check(lib.ps_valu_probe(kind, blocks, iters, _ptr(sink), nbytes, _stream()))
+        e1.record(st)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    return blocks * 256 * iters * 8 / best / 1e12, sink

@@ -74,3 +74,16 @@ def test_layout_and_argument_errors():
     rc = lib.adam_step_planes(None, None, None, None, None, None, None, None, 5, None, 1e-3, 1e-3, 1e-3,
                               0.9, 0.999, 1e-8, 1e-4, None)
     assert rc == _lib.PS_ERR_INVALID
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_valu_probe_argument_errors():
+    """Rejected on the host before any launch: a kind other than 0 or 1, or
+    a sink smaller than blocks * 256 values."""
+    from paper_2412_03451_amd import _lib
+    lib = _lib.load()
+    dummy = ctypes.c_void_p(256)
+    assert lib.ps_valu_probe(2, 1, 1, dummy, 1 << 20, None) == _lib.PS_ERR_INVALID
+    assert lib.ps_valu_probe(0, 2, 1, dummy, 2 * 256 * 4 - 1, None) == _lib.PS_ERR_INVALID
+    assert lib.ps_valu_probe(1, 1, 1, dummy, 256 * 8 - 1, None) == _lib.PS_ERR_INVALID
+    assert lib.ps_valu_probe(0, 1, 0, dummy, 1 << 20, None) == _lib.PS_ERR_INVALID

@@ -12,6 +12,8 @@ from .scenes import (  # noqa: F401
     perturb_planes,
     tiny_camera,
     scaled_camera,
+    degenerate_planes,
+    stacked_planes,
     room_planes,
     room_trajectory,
     room_init_planes,

@@ -150,6 +150,44 @@ def scaled_camera(cam: Camera, width: int, height: int, f: float) -> Camera:
     return Camera(width, height, f, f, width / 2.0, height / 2.0, cam.R.copy(), cam.t.copy())
 
 
+def degenerate_planes(seed: int = 11, n_random: int = 24) -> PlaneSet:
+    """Planes in awkward positions for the tiny camera (center (0, 0, -3),
+    looking along +z), followed by `n_random` random planes:
+      0  a floor at y = 0.3 whose local Y axis runs along -z, reaching 2 m
+         behind and 2 m in front of the camera;
+      1  the plane x = 0, which contains the camera center;
+      2  a plane at x = 0.15 whose normal is 80 degrees off the view axis;
+      3  a small fronto-parallel plane 5 cm in front of the camera;
+      4  a fronto-parallel plane 5 mm in front of the camera;
+      5  a plane 1 m behind the camera;
+      6  an oblique plane through a point 1 cm in front of the camera."""
+    s = math.sqrt(0.5)
+    c40, s40 = math.cos(math.radians(40.0)), math.sin(math.radians(40.0))
+    quat = [[s, -s, 0, 0], [s, 0, s, 0], [c40, 0, s40, 0], [1, 0, 0, 0], [1, 0, 0, 0], [1, 0, 0, 0],
+            [0.95, 0.31, 0, 0]]
+    center = [[0, 0.3, -3], [0, 0, 0], [0.15, 0, 0], [0.02, -0.01, -2.95], [0, 0, -2.995], [0, 0, -4],
+              [0, 0, -2.99]]
+    radii = [[2, 2, 2, 2], [1, 1, 1, 1], [0.5, 0.5, 1.0, 1.0], [0.01, 0.02, 0.015, 0.01], [0.3, 0.3, 0.3, 0.3],
+             [2, 2, 2, 2], [1.0, 0.8, 1.0, 0.6]]
+    base = random_planes(n_random, seed=seed, independent_radii=True)
+    return PlaneSet(np.concatenate([np.array(center, np.float32), base.center]),
+                    np.concatenate([np.array(quat, np.float32), base.quat]),
+                    np.concatenate([np.array(radii, np.float32), base.radii]))
+
+
+def stacked_planes(K: int, seed: int = 0) -> PlaneSet:
+    """K small, nearly fronto-parallel rectangles stacked in depth in front of
+    the tiny camera: centers (U[-0.2, 0.2], U[-0.2, 0.2], U[0, 5]), quaternions
+    (1, N(0, 0.1^2) x 3), radii U[0.005, 0.02].  Seen through an 8x8 image at
+    lambda(0) every one of them reaches every pixel through its fringe, so one
+    tile lists all K."""
+    rng = np.random.default_rng(seed)
+    center = np.stack([rng.uniform(-0.2, 0.2, K), rng.uniform(-0.2, 0.2, K), rng.uniform(0.0, 5.0, K)], 1)
+    quat = np.concatenate([np.ones((K, 1)), rng.normal(0.0, 0.1, (K, 3))], 1)
+    radii = rng.uniform(0.005, 0.02, (K, 4))
+    return PlaneSet(center.astype(np.float32), quat.astype(np.float32), radii.astype(np.float32))
+
+
 # ----------------------------------------------------------------------------
 # synthetic indoor room: box room + furniture boxes, faces split into cells
 # ----------------------------------------------------------------------------

@@ -1,0 +1,121 @@
+"""GPU parity on the method's degenerate cases and at the binning's size limit
+(run on an MI355X), against the float64 oracle with the bars of the render
+and gradient tests:
+
+* planes that straddle the camera, contain its center, sit inside the near
+  distance, lie behind it, are seen nearly edge-on, or sit 5 cm in front of
+  it with a fringe covering the whole image (Eq. 4 with the near-distance and
+  grazing-ray readings);
+* one tile whose list holds the maximum of 4096 (tile, plane) pairs, every
+  pixel compositing its M = 30 nearest semi-transparent hits out of them, and
+  one pair more, which tile_bin must refuse.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import U32, cosine, depth_err, f32, grad_check, normal_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def _render(ps, cam, lam, tile=(16, 16), capacity=None):
+    from paper_2412_03451_amd.splat import Renderer, SplatParams
+    r = Renderer.single_scene([cam], ps.K, tile=tile, params=SplatParams(), pair_capacity=capacity)
+    c, q, rr = _dev(ps.center), _dev(ps.quat), _dev(ps.radii)
+    lt = torch.tensor([lam], dtype=torch.float32, device="cuda")
+    D, N = r.render(c, q, rr, lt)
+    torch.cuda.synchronize()
+    return r, (c, q, rr, lt), D, N
+
+
+def _check_forward(r, D, N, ps, cam, lam, label):
+    Dg = r.job_depth(D, 0).cpu().numpy()
+    Ng = r.job_normal(N, 0).cpu().numpy()
+    Dr, Nr, aux = oracle.render(ps.center, ps.quat, ps.radii, cam, f32(lam))
+    ed = depth_err(Dg, Dr.numpy())
+    en = normal_err(Ng, Nr.numpy())
+    print(f"{label}: covered {float((aux['count'] > 0).float().mean()):.3f}, max count {int(aux['count'].max())}, "
+          f"max depth err {ed.max():.3g}, max normal err {en.max():.3g} (units of 1e-5)", flush=True)
+    assert np.isfinite(Dg).all() and np.isfinite(Ng).all()
+    assert ed.max() <= 1.0, np.unravel_index(np.argmax(ed), ed.shape)
+    assert en.max() <= 1.0
+    return aux
+
+
+def _check_backward(r, args, ps, cam, lam, seed, label):
+    rng = np.random.default_rng(seed)
+    gD = rng.normal(size=cam.width * cam.height).astype(np.float32)
+    gN = rng.normal(size=(3, cam.width * cam.height)).astype(np.float32)
+    grads, abss = oracle.per_pixel_abs_grad(ps.center, ps.quat, ps.radii, cam, f32(lam), gD, gN)
+    out = r.backward(*args, _dev(gD).reshape(-1), _dev(gN).reshape(-1))
+    torch.cuda.synchronize()
+    for name, g, gr, s in zip(("center", "quat", "radii"), out, grads, abss):
+        g = g.cpu().numpy()
+        assert np.isfinite(g).all(), name
+        err, tol = grad_check(g, gr.numpy(), s.numpy())
+        ratio = err / np.maximum(tol, 1e-300)
+        cs = cosine(g, gr.numpy())
+        print(f"{label} {name}: max err/tol {ratio.max():.3g}, cosine-1 {cs - 1:.3g}", flush=True)
+        assert np.all(err <= tol), (name, np.unravel_index(np.argmax(ratio), ratio.shape))
+        assert cs >= 1 - 1e-8
+
+
+@pytest.mark.parametrize("lam", [oracle.lambda_at(0), 300.0])
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_degenerate_geometry_forward(lam, tile):
+    ps = synth.degenerate_planes()
+    cam = synth.tiny_camera()
+    print(f"degenerate planes K={ps.K} lambda={lam:.4g} tile={tile}", flush=True)
+    r, _, D, N = _render(ps, cam, lam, tile)
+    _check_forward(r, D, N, ps, cam, lam, f"degenerate lam {lam:.3g} tile {tile}")
+
+
+@pytest.mark.parametrize("lam", [oracle.lambda_at(0), 60.0])
+def test_degenerate_geometry_backward(lam):
+    ps = synth.degenerate_planes()
+    cam = synth.tiny_camera()
+    print(f"degenerate planes backward K={ps.K} lambda={lam:.4g}", flush=True)
+    r, args, D, N = _render(ps, cam, lam)
+    _check_backward(r, args, ps, cam, lam, seed=5, label=f"degenerate lam {lam:.3g}")
+    # the planes never hit get exactly zero gradient
+    out = r.backward(*args, _dev(np.ones(cam.width * cam.height, np.float32)),
+                     _dev(np.ones(3 * cam.width * cam.height, np.float32)))
+    for g in out:
+        assert float(g[[1, 4, 5]].abs().max()) == 0.0
+
+
+def test_tile_list_at_the_size_limit():
+    """4096 planes in one 8x8 tile: the largest list tile_bin accepts (sorted
+    by the large-list pass), 30 semi-transparent hits per pixel."""
+    from paper_2412_03451_amd.splat import Renderer
+    K = 4096
+    ps = synth.stacked_planes(K, seed=0)
+    cam = synth.tiny_camera(8, 8, 100.0)
+    lam = oracle.lambda_at(0)
+    print(f"single tile K={K} lambda={lam:.4g}", flush=True)
+    r, args, D, N = _render(ps, cam, lam, (8, 8), capacity=K + 64)
+    cnt = r.counters()
+    assert cnt["pairs"] == K and cnt["max_tile"] == K, cnt
+    aux = _check_forward(r, D, N, ps, cam, lam, "single tile 4096")
+    assert int(aux["count"].min()) == 30
+    _check_backward(r, args, ps, cam, lam, seed=6, label="single tile 4096")
+
+
+def test_tile_list_over_the_size_limit_is_refused():
+    from paper_2412_03451_amd._lib import PS_ERR_CAPACITY, PlaneSplatError
+    K = 4097
+    ps = synth.stacked_planes(K, seed=0)
+    cam = synth.tiny_camera(8, 8, 100.0)
+    print(f"single tile K={K}: expect a capacity error", flush=True)
+    with pytest.raises(PlaneSplatError) as e:
+        _render(ps, cam, oracle.lambda_at(0), (8, 8), capacity=K + 64)
+    assert e.value.code == PS_ERR_CAPACITY
+    assert "4096" in str(e.value)

@@ -396,3 +396,38 @@ def test_transmittance_behind_nearly_opaque_layers():
         T *= 1.0 / (1.0 + math.exp(z))           # sigmoid(-z)
     assert T < 1e-15
     assert float(aux["T"][j, i]) == pytest.approx(T, rel=1e-12)
+
+
+def test_floor_through_the_camera_closed_form():
+    """Plane 0 of the degenerate set: the floor y = 0.3 (camera frame) whose
+    rectangle runs from 2 m behind to 2 m in front of the camera.  A pixel
+    below the horizon sees it at z-depth t = 0.3 f / (v + 1/2 - c_y); where
+    the hit lies inside the rectangle (|x| < 2, t < 2) the weight is 1, so
+    D = t and the normal, turned to the camera, is (0, -1, 0).  Pixels above
+    the horizon meet the plane behind the camera: nothing.  The plane through
+    the camera center (t = 0), the one 5 mm away (inside the near distance)
+    and the one behind the camera render nothing at all."""
+    ps = synth.degenerate_planes()
+    cam = synth.tiny_camera()
+    lam = 50.0
+
+    def sub(i):
+        return ps.center[i:i + 1], ps.quat[i:i + 1], ps.radii[i:i + 1]
+    D, N, aux = oracle.render(*sub(0), cam, lam)
+    D = D.numpy().reshape(cam.height, cam.width)
+    N = N.numpy().reshape(3, cam.height, cam.width).transpose(1, 2, 0)
+    v = np.arange(cam.height)[:, None] + 0.5 - cam.cy
+    u = np.arange(cam.width)[None, :] + 0.5 - cam.cx
+    y0 = float(ps.center[0, 1])    # 0.3 rounded to float32
+    t = np.where(v > 0, y0 * cam.fy / np.where(v > 0, v, 1.0), -1.0) * np.ones_like(u)
+    x = t * u / cam.fx
+    inside = (t > 0) & (t < 1.99) & (np.abs(x) < 1.99)
+    assert inside.sum() > 500
+    np.testing.assert_allclose(D[inside], t[inside], rtol=1e-12)
+    np.testing.assert_allclose(N[inside], np.broadcast_to([0.0, -1.0, 0.0], N[inside].shape), rtol=0, atol=1e-12)
+    above = np.broadcast_to(v < 0, D.shape)
+    assert np.all(D[above] == 0.0) and np.all(N[above] == 0.0)
+    for i in (1, 4, 5):
+        Di, Ni, aux = oracle.render(*sub(i), cam, lam)
+        assert float(Di.abs().max()) == 0.0 and float(Ni.abs().max()) == 0.0
+        assert int(aux["count"].max()) == 0

@@ -35,7 +35,7 @@ from .render import (  # noqa: F401
 )
 from .loss import render_loss, loss_terms  # noqa: F401
 from .adam import adam_step  # noqa: F401
-from .grad import render_backward, per_pixel_abs_grad  # noqa: F401
+from .grad import render_backward, per_pixel_abs_grad, weight_path_magnitude  # noqa: F401
 from . import initnet  # noqa: F401
 from .split import split_planes  # noqa: F401
 from . import depth_init  # noqa: F401

@@ -33,15 +33,22 @@ def grad_tol(ref, abssum, rel=1e-4, c=32.0, floor=1e-30):
     return rel * np.abs(ref) + c * U32 * abssum + floor
 
 
-def grad_check(gpu, ref, abssum, rel=1e-4, c=32.0):
+def grad_check(gpu, ref, abssum, rel=1e-4, c=32.0, cond=None, c_cond=64.0):
     """(err, tol) per coordinate.  Besides grad_tol, a coordinate is compared
     no finer than 1e-4 of one float32 roundoff of its group's largest
     gradient: below that (hidden planes behind ~30 layers reach 1e-14 of the
     largest gradient) float32 intermediates such as c_j - S_{j+1} of the
-    compositing adjoint cannot resolve it."""
+    compositing adjoint cannot resolve it.  With cond (the oracle's
+    weight_path_magnitude) the bound adds c_cond float32 roundoffs of it:
+    dL/dw_j = T_j (c_j - S_{j+1}) cancels inside one pixel when a hit lies
+    just in front of a similar one, and its float32 value is off by roundoffs
+    of c_j and of S_{j+1}, which sums up to M = 30 hits (64: two roundoffs
+    per composited hit, and some)."""
     gpu = np.asarray(gpu, np.float64)
     ref = np.asarray(ref, np.float64)
     tol = grad_tol(ref, np.asarray(abssum, np.float64), rel, c) + rel * U32 * np.abs(ref).max()
+    if cond is not None:
+        tol = tol + c_cond * U32 * np.asarray(cond, np.float64)
     err = np.abs(gpu - ref)
     return err, tol
 

@@ -116,3 +116,74 @@ def test_autotuner_caches_choice(tmp_path):
     assert at2.lookup(W, H, K) == (tile, pending)
     assert cache_key(W, H, K) in at2.table
     assert len(at2.table[cache_key(W, H, K)]["tried"]) == 5
+
+
+def test_full_size_batch_sampled_pixels():
+    """The 64-room batch at full size, in the benchmark's launch shape (one
+    job per room, 16x16 tiles, one launch per phase, lambda(0)): rooms of
+    200-4000 planes at 320x240 or 640x480.  Forward on 150 sampled pixels of
+    four rooms against the oracle; backward with the upstream gradient on
+    those pixels only, against the oracle's gradient of the same pixels
+    (per-coordinate bound 1e-4 |g_ref| + 32 u32 S plus 64 roundoffs of the
+    weight path's magnitude, as for the full-size room view); the planes of
+    every other room get exactly zero gradient."""
+    from paper_2412_03451_amd.splat import Job, Renderer
+    from test_gpu_grad import _check_grads
+    specs = synth.room_batch_specs(64, seed=0)
+    rooms, jobs, cams, off = [], [], [], 0
+    for i, sp in enumerate(specs):
+        gt, info = synth.room_planes(seed=sp["seed"], target_K=sp["K"])
+        init = synth.room_init_planes(gt, seed=sp["seed"] + 1)
+        cam = synth.room_trajectory(sp["seed"], sp["views"], info, width=sp["width"], height=sp["height"],
+                                    f=sp["f"])[0]
+        rooms.append(init)
+        cams.append(cam)
+        jobs.append(Job(off, off + init.K, i, cam.width, cam.height, (16, 16), i))
+        off += init.K
+    Ks = np.array([p.K for p in rooms])
+    big = [i for i in range(64) if cams[i].width == 640]
+    small = [i for i in range(64) if cams[i].width == 320]
+    pick = sorted({int(np.argmax(Ks)), int(np.argmin(Ks)), big[len(big) // 2], small[len(small) // 2]})
+    print(f"64 rooms, {off} planes, checked rooms {pick} (K {Ks[pick].tolist()})", flush=True)
+    c = torch.cat([_dev(p.center) for p in rooms])
+    q = torch.cat([_dev(p.quat) for p in rooms])
+    r = torch.cat([_dev(p.radii) for p in rooms])
+    lam = f32(oracle.lambda_at(0))
+    lt = torch.tensor([lam], device="cuda")
+    rb = Renderer(jobs, cams)
+    D, N = rb.render(c, q, r, lt)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(23)
+    gD = np.zeros(rb.n_pixels, np.float32)
+    gN = np.zeros((3, rb.n_pixels), np.float32)
+    samples = {}
+    for i in pick:
+        cam, P, o = cams[i], cams[i].width * cams[i].height, rb.pix_off[i]
+        pix = rng.choice(P, size=150, replace=False)
+        samples[i] = pix
+        Dr, Nr, _ = oracle.render_pixels(rooms[i].center, rooms[i].quat, rooms[i].radii, cam, lam, pix)
+        ed = depth_err(D[o:o + P].cpu().numpy()[pix], Dr.numpy())
+        en = normal_err(N[3 * o:3 * (o + P)].view(3, P).cpu().numpy()[:, pix], Nr.numpy().T)
+        print(f"room {i} (K {rooms[i].K}, {cam.width}x{cam.height}): max depth err {ed.max():.3g} "
+              f"normal {en.max():.3g} (units of 1e-5)", flush=True)
+        assert ed.max() <= 1.0 and en.max() <= 1.0
+        gD[o + pix] = rng.normal(size=pix.size).astype(np.float32)
+        gN[:, o + pix] = rng.normal(size=(3, pix.size)).astype(np.float32)
+    # per-job normal layout: [3][H W] for each job at 3 * pix_off
+    gN_flat = np.zeros(3 * rb.n_pixels, np.float32)
+    for i in range(64):
+        o, P = rb.pix_off[i], cams[i].width * cams[i].height
+        gN_flat[3 * o:3 * (o + P)] = gN[:, o:o + P].reshape(-1)
+    gpu = rb.backward(c, q, r, lt, _dev(gD), _dev(gN_flat))
+    torch.cuda.synchronize()
+    gpu = [g.cpu() for g in gpu]
+    for i in range(64):
+        a, b = jobs[i].plane_begin, jobs[i].plane_end
+        if i not in samples:
+            assert all(float(g[a:b].abs().max()) == 0.0 for g in gpu)
+            continue
+        cam, P, o = cams[i], cams[i].width * cams[i].height, rb.pix_off[i]
+        args = (rooms[i].center, rooms[i].quat, rooms[i].radii, cam, lam, gD[o:o + P], gN[:, o:o + P])
+        grads, abss = oracle.per_pixel_abs_grad(*args, chunk=25, pix=samples[i])
+        conds = oracle.weight_path_magnitude(*args, chunk=25, pix=samples[i])
+        _check_grads([g[a:b] for g in gpu], grads, abss, f"batch room {i}", conds=conds)

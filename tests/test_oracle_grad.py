@@ -116,3 +116,59 @@ def test_single_radii_gradient_is_the_pair_sum():
             assert fd == pytest.approx(tied, rel=2e-5, abs=2e-5 * (1 + abs(tied)))
             checked += 1
     assert checked >= 12
+
+
+def test_weight_path_magnitude_closed_form():
+    """One pixel of the tiny camera (ray (0.005, 0.005, 1) from (0, 0, -3))
+    through two fronto-parallel planes: plane 0 at z = 0 (t = 3) reaches the
+    pixel through its x- fringe (a* = r^{x-} + P_X < 0, w_0 = 2 s(5 lam a*)),
+    plane 1 at z = 1 (t = 4) covers it (w_1 = 1).  Both normals face the
+    camera as (0, 0, -1), so
+      M_0 = T_0 (|g_D| (t_0 + w_1 t_1) + |g_Nz| (1 + w_1)) = 7 |g_D| + 2 |g_Nz|,
+    and the magnitude of a coordinate of plane 0 is M_0 |dw_0/dtheta| with
+    |dw_0/dr^{x-}| = |dw_0/dx_0| = 10 lam s (1 - s), |dw_0/dz_0| = 0.005 of
+    that; its other center and radius coordinates, and all of plane 1
+    (w_1 = 1 flat), are 0."""
+    cam = synth.tiny_camera()
+    x0 = float(np.float32(0.3))
+    center = np.array([[x0, 0.0, 0.0], [0.0, 0.0, 1.0]], np.float32)
+    quat = np.array([[1, 0, 0, 0], [1, 0, 0, 0]], np.float32)
+    radii = np.array([[0.5, 0.2, 0.5, 0.5], [1, 1, 1, 1]], np.float32)
+    lam = 10.0
+    p = 48 * cam.width + 64
+    P = cam.width * cam.height
+    gD = np.zeros(P)
+    gN = np.zeros((3, P))
+    gD[p], gN[:, p] = -1.5, (0.25, -0.5, 0.75)
+    mc, mq, mr = oracle.weight_path_magnitude(center, quat, radii, cam, lam, gD, gN, pix=[p])
+    a = float(np.float32(0.2)) + (0.005 * 3.0 - x0)
+    s = 1.0 / (1.0 + np.exp(-5.0 * lam * a))
+    dw = 10.0 * lam * s * (1.0 - s)
+    M0 = 7.0 * 1.5 + 2.0 * 0.75
+    exp_c = np.zeros((2, 3))
+    exp_c[0, 0], exp_c[0, 2] = M0 * dw, M0 * dw * 0.005
+    exp_r = np.zeros((2, 4))
+    exp_r[0, 1] = M0 * dw
+    np.testing.assert_allclose(mc.numpy(), exp_c, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(mr.numpy(), exp_r, rtol=1e-9, atol=1e-12)
+    # plane 1 is flat at w = 1: no magnitude for its rotation either
+    assert float(mq[1].abs().max()) == 0.0 and float(mq[0].abs().max()) > 0.0
+
+
+def test_weight_path_magnitude_bounds_the_weight_path():
+    """On a random scene the magnitude dominates the gradient of the weight
+    path alone (g . c_j - g . S_{j+1} replaced by its parts' magnitudes can
+    only grow), coordinate by coordinate."""
+    ps = synth.random_planes(24, seed=5, independent_radii=True, center_range=0.5)
+    cam = synth.Camera(40, 30, 30.0, 30.0, 20.0, 15.0, np.eye(3, dtype=np.float32),
+                       np.array([0.0, 0.0, 3.0], np.float32))
+    lam = oracle.lambda_at(0)
+    rng = np.random.default_rng(3)
+    P = cam.width * cam.height
+    gD = rng.normal(size=P)
+    gN = rng.normal(size=(3, P))
+    mags = oracle.weight_path_magnitude(ps.center, ps.quat, ps.radii, cam, lam, gD, gN, chunk=300)
+    # the radius gradient runs through the weight only: bounded per coordinate
+    _, abss = oracle.per_pixel_abs_grad(ps.center, ps.quat, ps.radii, cam, lam, gD, gN, chunk=300)
+    assert np.all(mags[2].numpy() >= abss[2].numpy() * (1 - 1e-12))
+    assert float(mags[2].sum()) > 0.0

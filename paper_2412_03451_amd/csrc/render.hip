@@ -499,7 +499,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
 constexpr int kChunk = 8;    // hits per lane kept in LDS per recompute pass
 
 struct BwdLds {
-  int pos[kChunk][64];
+  int16_t pos[kChunk][64];   // list positions (< 4096)
   float a[kChunk][64];    // a* of the hit
   float T[kChunk][64];    // transmittance in front of the hit
   float cg[kChunk][64];   // c_j, then dL/dw_j after the back-to-front walk

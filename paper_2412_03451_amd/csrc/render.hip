@@ -187,8 +187,8 @@ struct Pending {
   }
 };
 
-// Stage the batch [base, base + 64) of the tile list: each lane fetches one
-// list entry (its key and the 128-byte record copy: coalesced, one memory
+// Stage the batch [base, base + kBatch) of the tile list: each of the first
+// kBatch lanes fetches one list entry (its key and the 128-byte record copy: coalesced, one memory
 // latency per batch) and stores the record head in LDS if the record's pixel
 // box overlaps the 8x8 block; the backward also keeps the in-plane offsets and
 // the emit index.  Returns the mask of overlapping candidates.
@@ -198,7 +198,7 @@ __device__ inline uint64_t stage_batch(const RenderArgs& a, const ItemCtx& c, in
   const int lane = threadIdx.x;
   const int i = base + lane;
   bool ov = false;
-  if (i < c.e) {
+  if (lane < kBatch && i < c.e) {
     const uint64_t key = a.keys[i];
     const float4* src = reinterpret_cast<const float4*>(&a.recs_s[i]);
     const float4 h0 = src[0], h1 = src[1], h2 = src[2], h3 = src[3];
@@ -244,7 +244,7 @@ __device__ inline void staged(const StageLds& S, int j, RecHead& rec, float n[3]
 __device__ inline void cand_normal(const RenderArgs& a, const ItemCtx& c, int sb, int pos, float n[3]) {
   const int j = c.b + pos - sb;
   float4 h;
-  if (j >= 0 && j < 64)
+  if (j >= 0 && j < kBatch)
     h = c.stage->head[6][j];
   else
     h = reinterpret_cast<const float4*>(&a.recs_s[c.b + pos])[6];
@@ -292,10 +292,11 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
   int lr = -1;
   StageLds& S = *c.stage;
   bool stop = ballot(!done) == 0;
-  for (int base = c.b; base < c.e && !stop; base += 64) {
+  for (int base = c.b; base < c.e && !stop; base += kBatch) {
     uint64_t ovm = stage_batch<Sink::BWD>(a, c, base);
     // bound of every candidate after this batch
-    const float tlb_after = (base + 64 < c.e) ? __uint_as_float((uint32_t)(a.keys[base + 64] >> 32)) : INFINITY;
+    const float tlb_after =
+        (base + kBatch < c.e) ? __uint_as_float((uint32_t)(a.keys[base + kBatch] >> 32)) : INFINITY;
     while (ovm) {
       const int j = __ffsll((unsigned long long)ovm) - 1;
       ovm &= ovm - 1;
@@ -360,7 +361,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
     const int cap = min(P, a.M - sink.count);
     bool stop2 = false;
     int sb = c.b;   // the batch left staged in LDS
-    for (int base = c.b; base < c.e && !stop2; base += 64) {
+    for (int base = c.b; base < c.e && !stop2; base += kBatch) {
       uint64_t ovm = stage_batch<Sink::BWD>(a, c, base);
       sb = base;
       while (ovm) {
@@ -700,7 +701,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
     gN2 = a.g_normal[nb + 2 * c.HW];
   }
   // a list of at most one batch stays staged in LDS after the walk
-  const bool one_batch = n <= 64;
+  const bool one_batch = n <= kBatch;
   mark(0);
   int passes = 1;
   int hits = 0;   // hits committed by the first pass's walk
@@ -754,7 +755,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
       L.cg[m + 1][lane] = g;
     }
     mark(2);
-    // Visit the chunk's candidates in list order, in groups of up to 64:
+    // Visit the chunk's candidates in list order, in groups of up to kBatch:
     // gather the next distinct positions (wave minimum of the lanes'
     // cursors); a one-batch list is still staged, longer lists fetch the
     // group's records in parallel; then form the per-pair gradients
@@ -763,7 +764,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
     int npos = nE > 0 ? L.pos[0][lane] : 0x7fffffff;
     while (true) {
       int grp = 0, kk = k, np = npos;
-      while (grp < 64) {
+      while (grp < kBatch) {
         const int p = uniform_int(wave_min_int(np));
         if (p == 0x7fffffff) break;
         if (lane == 0) {

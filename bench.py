@@ -104,6 +104,31 @@ def _oracle_rate(init, cam, lam, budget_s: float, threads: int):
     return done_px * init.K / dt, done_px, dt, torch.get_num_threads()
 
 
+def oracle_small_step_s(reps: int = 3):
+    """Seconds of one whole float64 oracle step on the small configuration
+    (64 planes, 128x96, lambda(0)): render, Eq. 14 loss against the
+    perturbed scene's render, backward and one Adam step; best of `reps`."""
+    import torch
+    import oracle
+    import synth
+    ps = synth.random_planes(64, seed=0, independent_radii=True)
+    tgt = synth.perturb_planes(ps, seed=1, center_sigma=0.05, rot_sigma_deg=5.0)
+    cam = synth.tiny_camera()
+    lam = float(np.float32(oracle.lambda_at(0)))
+    Dt, Nt, _ = oracle.render(tgt.center, tgt.quat, tgt.radii, cam, 300.0)
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        c, q, r = (torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in (ps.center, ps.quat, ps.radii))
+        D, N, _ = oracle.render(c, q, r, cam, lam)
+        oracle.render_loss(D, N, Dt, Nt).backward()
+        for x in (c, q, r):
+            z = np.zeros(tuple(x.shape))
+            oracle.adam_step(x.detach().numpy(), x.grad.numpy(), z, z, 1)
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
 def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
     """The float64 oracle on a bounded sample of one view: forward + loss +
     backward for blocks of pixel rows, timed on the host cores (three
@@ -123,6 +148,7 @@ def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
         "value_1_thread": rate1 / 1e6,
         "sample_1_thread": f"{px1} pixels in {dt1:.1f} s on one thread",
         "fit_5000_steps_s_extrapolated": round(5000 * step_s, 1),
+        "small_config_step_s": round(oracle_small_step_s(), 3),
     }
 
 

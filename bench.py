@@ -133,10 +133,12 @@ def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
     """The float64 oracle on a bounded sample of one view: forward + loss +
     backward for blocks of pixel rows, timed on the host cores (three
     quarters of the budget on every core, the rest on one core)."""
+    import torch
     cam = cams[0]
     n = os.cpu_count() or 1
     rate, px, dt, used = _oracle_rate(init, cam, lam, 0.75 * budget_s, n)
     rate1, px1, dt1, _ = _oracle_rate(init, cam, lam, 0.25 * budget_s, 1)
+    torch.set_num_threads(n)
     step_s = cam.width * cam.height * init.K / rate
     return {
         "value": rate / 1e6,

@@ -375,6 +375,14 @@ int plane_tie_radii(float* g_radii, int K, void* stream);
 #define PS_N_COUNTERS 20
 int ps_read_counters(const ps_layout* L, void* ws, int64_t out[PS_N_COUNTERS], void* stream);
 
+/* Opt-in check for NaN and infinity (the other calls never test their
+ * inputs).  Counts the non-finite values among x[0..n) (device, float32) into
+ * *d_count (device, caller-owned int64; the call clears it first, with a
+ * kernel, so the call may be captured in a graph).  With h_count non-null the
+ * count is also copied to *h_count and the stream is synchronised.
+ * PS_ERR_INVALID for n < 0, a null d_count, or a null x with n > 0. */
+int ps_check_finite(const float* x, int64_t n, int64_t* d_count, int64_t* h_count, void* stream);
+
 /* Issue-rate probe of the vector ALU (measurement only, not a step of the
  * method).  The render kernels' roofline counts lane operations against the
  * non-packed issue rate; this launch measures that rate.  kind 0: fp32,

@@ -24,7 +24,8 @@ import numpy as np
 import torch
 
 from ._lib import check
-from .splat import Job, Renderer, SplatParams, _ptr, _stream, adam_step, grad_accumulate, split_planes, tie_radii
+from .splat import (Job, Renderer, SplatParams, _ptr, _stream, adam_step, check_finite, grad_accumulate, split_planes,
+                    tie_radii)
 
 
 def view_schedule(n_views: int, n_rows: int, per_step: int = 1, seed: int = 0) -> np.ndarray:
@@ -54,6 +55,8 @@ class FitConfig:
     split_every: int = 0                # plane splitting every n iterations (Sec. 3.3: 1000); 0: off
     split_thresh: float = 0.2           # average |dL/dr| over a pair of radii that triggers a split
     single_radii: bool = False          # ablation (Sec. 4.3): one radius per axis, r+ = r- (from their mean)
+    check_finite: bool = False          # before a run and after every checked run of steps, fail on NaN or
+                                        # infinity in the planes (the kernels do not test their inputs)
 
 
 @dataclass
@@ -310,6 +313,10 @@ class BatchFit:
         checked run of steps (host side, after a synchronisation)."""
         done = 0
         grows = 0
+        if self.cfg.check_finite:
+            bad = check_finite(self.c, self.q, self.r)
+            if bad:
+                raise FloatingPointError(f"{bad} non-finite plane parameters before the run")
         while done < n_steps:
             if grows > 8:
                 raise RuntimeError("pair lists keep overflowing after growing the workspace: a tile list "
@@ -344,6 +351,10 @@ class BatchFit:
                 grows += 1
                 continue
             done += chunk
+            if self.cfg.check_finite:
+                bad = check_finite(self.c, self.q, self.r)
+                if bad:
+                    raise FloatingPointError(f"{bad} non-finite plane parameters after {done} steps of this run")
             if self.cfg.split_every:
                 self.since_split += chunk
                 if self.since_split >= self.cfg.split_every:

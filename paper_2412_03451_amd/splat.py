@@ -354,3 +354,20 @@ def valu_probe(kind: int, blocks: int = 8192, iters: int = 4096, reps: int = 3):
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1) * 1e-3)
     return blocks * 256 * iters * 8 / best / 1e12, sink
+
+
+def check_finite(*tensors) -> int:
+    """Number of NaN or infinite values in the given float32 device tensors
+    (ps_check_finite; synchronises the stream)."""
+    lib = _lib.load()
+    if not tensors:
+        return 0
+    d = torch.empty(1, dtype=torch.int64, device=tensors[0].device)
+    total = 0
+    for t in tensors:
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("check_finite: contiguous float32 tensors only")
+        h = C.c_int64(0)
+        check(lib.ps_check_finite(_ptr(t), int(t.numel()), _ptr(d), C.byref(h), _stream()))
+        total += int(h.value)
+    return total

@@ -87,3 +87,14 @@ def test_valu_probe_argument_errors():
     assert lib.ps_valu_probe(0, 2, 1, dummy, 2 * 256 * 4 - 1, None) == _lib.PS_ERR_INVALID
     assert lib.ps_valu_probe(1, 1, 1, dummy, 256 * 8 - 1, None) == _lib.PS_ERR_INVALID
     assert lib.ps_valu_probe(0, 1, 0, dummy, 1 << 20, None) == _lib.PS_ERR_INVALID
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_check_finite_argument_errors():
+    """Rejected on the host before any launch."""
+    from paper_2412_03451_amd import _lib
+    lib = _lib.load()
+    dummy = ctypes.c_void_p(256)
+    assert lib.ps_check_finite(dummy, -1, dummy, None, None) == _lib.PS_ERR_INVALID
+    assert lib.ps_check_finite(dummy, 10, None, None, None) == _lib.PS_ERR_INVALID
+    assert lib.ps_check_finite(None, 10, dummy, None, None) == _lib.PS_ERR_INVALID

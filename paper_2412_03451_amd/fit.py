@@ -354,7 +354,10 @@ class BatchFit:
             if self.cfg.check_finite:
                 bad = check_finite(self.c, self.q, self.r)
                 if bad:
-                    raise FloatingPointError(f"{bad} non-finite plane parameters after {done} steps of this run")
+                    # back to the state saved before this run of steps (it was checked)
+                    self.restore(saved)
+                    raise FloatingPointError(f"{bad} non-finite plane parameters after {done} steps of this run; "
+                                             f"state restored to step {done - chunk}")
             if self.cfg.split_every:
                 self.since_split += chunk
                 if self.since_split >= self.cfg.split_every:

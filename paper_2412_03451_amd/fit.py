@@ -308,6 +308,53 @@ class BatchFit:
     def overflowed(self) -> bool:
         return bool(self.rend.counters()["overflow_since_init"])
 
+    # ------------------------------------------------------------------ checkpoint
+    def save(self, path: str):
+        """Write a checkpoint: plane parameters, Adam moments, the iteration
+        counter (lambda of Eq. 10, the Adam step and the view of the next step
+        follow from it), the split accumulators, the scenes' plane ranges and
+        the split history.  A file of tensors only (read back with
+        torch.load(weights_only=True))."""
+        torch.cuda.synchronize()
+        splits = torch.tensor(self.splits, dtype=torch.int64).reshape(-1, 3)
+        torch.save({"c": self.c.cpu(), "q": self.q.cpu(), "r": self.r.cpu(), "m": self.m.cpu(), "v": self.v.cpu(),
+                    "ite": self.ite.cpu(), "acc": self.acc.cpu(), "cnt": self.cnt.cpu(),
+                    "k_off": torch.as_tensor(np.asarray(self.k_off, np.int64)),
+                    "since_split": torch.tensor([self.since_split], dtype=torch.int64), "splits": splits}, path)
+
+    def load(self, path: str):
+        """Resume from a checkpoint of a fit over the same scenes (targets,
+        cameras and configuration); continuing gives the same bits as the
+        uninterrupted fit.  If splitting changed the plane counts, the jobs and
+        the workspace are rebuilt for them."""
+        d = torch.load(path, map_location="cpu", weights_only=True)
+        k_off = d["k_off"].numpy()
+        if len(k_off) != len(self.k_off):
+            raise ValueError(f"checkpoint holds {len(k_off) - 1} scenes, this fit {len(self.k_off) - 1}")
+        dev = self.device
+        if np.array_equal(k_off, np.asarray(self.k_off)):
+            # same plane set: copy into the buffers a captured step uses
+            for dst, key in ((self.c, "c"), (self.q, "q"), (self.r, "r"), (self.m, "m"), (self.v, "v"),
+                             (self.ite, "ite"), (self.acc, "acc"), (self.cnt, "cnt")):
+                dst.copy_(d[key].to(dev))
+        else:
+            self.c, self.q, self.r = (d[k].to(dev).contiguous() for k in ("c", "q", "r"))
+            self.m, self.v = d["m"].to(dev).contiguous(), d["v"].to(dev).contiguous()
+            self.acc, self.cnt = d["acc"].to(dev).contiguous(), d["cnt"].to(dev).contiguous()
+            self.ite.copy_(d["ite"].to(dev))
+            self.K = int(self.c.shape[0])
+            self.k_off = k_off
+            self.jobs = [Job(int(k_off[j.scene]), int(k_off[j.scene + 1]), j.cam, j.width, j.height, j.tile, j.scene)
+                         for j in self.jobs]
+            self.rend = Renderer(self.jobs, self.rend.cams, device=dev, pair_capacity=self.rend.L.pair_capacity,
+                                 params=self.params)
+            self._eval = {}
+            self.graph = None
+            self.size_capacity()
+        self.since_split = int(d["since_split"][0])
+        self.splits = [tuple(int(x) for x in row) for row in d["splits"].tolist()]
+        return self
+
     def run(self, n_steps: int, graph: bool = True, callback=None):
         """Advance n_steps iterations.  callback(fit, done) runs after every
         checked run of steps (host side, after a synchronisation)."""

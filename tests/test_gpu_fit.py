@@ -85,3 +85,27 @@ def test_fit_lowers_depth_error(scene):
     after = f.depth_l1(lam=300.0)
     print(f"depth L1 {before:.4f} -> {after:.4f} m", flush=True)
     assert after < 0.8 * before
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_checkpoint_resume_is_bitwise(scene, tmp_path, split):
+    """A fit saved after 12 steps and resumed by a new fit object continues
+    with the same bits as the uninterrupted fit: without splitting (same
+    plane set, the captured step's buffers are refilled) and with splitting
+    every 10 steps at a low threshold (the plane count changed before the
+    checkpoint; the resumed fit rebuilds its jobs, and both split again at
+    step 20)."""
+    kw = dict(check_every=4, split_every=10, split_thresh=1e-6) if split else dict(check_every=4)
+    a = _fit(scene, **kw)
+    a.run(12, graph=True)
+    path = str(tmp_path / "fit.pt")
+    a.save(path)
+    if split:
+        assert a.splits and a.splits[0][2] > a.splits[0][1]
+    a.run(8, graph=True)
+    b = _fit(scene, **kw)
+    b.load(path)
+    b.run(8, graph=True)
+    assert a.K == b.K and a.splits == b.splits
+    for x, y in zip(a.state(), b.state()):
+        assert torch.equal(x, y)

@@ -465,3 +465,25 @@ class SceneFit(BatchFit):
                          params=params, pair_capacity=pair_capacity, size_capacity=size_capacity, device=device)
         self.V = len(cams)
         self.W, self.H = self.size[0]
+
+
+def jsonl_logger(path: str, depth_l1: bool = False):
+    """A run() callback that appends one JSON line per checked run of steps:
+    the iteration, lambda, the plane count, the loss terms of the last step
+    per job (Eq. 14: normal cosine, normal L1, depth L1 sums), the pair count
+    and overflow flag of the last binning, the pixels that took the exact
+    fallback ordering path, and (with depth_l1) the mean depth error of every
+    scene over all its views at the current lambda."""
+    import json
+
+    def cb(fit, done):
+        cnt = fit.rend.counters()
+        rec = {"iteration": int(fit.ite.item()), "lambda": float(fit.lam.item()), "planes": int(fit.K),
+               "loss": None if fit.last_loss is None else fit.last_loss.detach().double().cpu().tolist(),
+               "pairs": int(cnt["pairs"]), "overflow_since_init": int(cnt["overflow_since_init"]),
+               "fallback_pixels": int(cnt["slow_pixels"])}
+        if depth_l1:
+            rec["depth_l1"] = [fit.depth_l1(s) for s in range(len(fit.scenes))]
+        with open(path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+    return cb

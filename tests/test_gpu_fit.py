@@ -109,3 +109,19 @@ def test_checkpoint_resume_is_bitwise(scene, tmp_path, split):
     assert a.K == b.K and a.splits == b.splits
     for x, y in zip(a.state(), b.state()):
         assert torch.equal(x, y)
+
+
+def test_jsonl_logger(scene, tmp_path):
+    """One JSON line per checked run of steps with the iteration, lambda,
+    loss terms, pair count and the depth error."""
+    import json
+    from paper_2412_03451_amd.fit import jsonl_logger
+    path = str(tmp_path / "fit.jsonl")
+    f = _fit(scene, check_every=4)
+    f.run(8, graph=True, callback=jsonl_logger(path, depth_l1=True))
+    rows = [json.loads(line) for line in open(path)]
+    assert [r["iteration"] for r in rows] == [4, 8]
+    for r in rows:
+        assert r["planes"] == f.K and r["pairs"] > 0 and r["overflow_since_init"] == 0
+        assert r["lambda"] == pytest.approx(float(np.float32(oracle.lambda_at(r["iteration"] - 1))), rel=2e-7)
+        assert np.isfinite(np.asarray(r["loss"], np.float64)).all() and 0.0 < r["depth_l1"][0] < 10.0

@@ -275,7 +275,8 @@ int ps_fit_schedule(const ps_layout* L, void* ws, int32_t* ite, const int32_t* t
  * three affine-in-pixel numerators/denominator of t, P_X, P_Y (float64), the
  * camera-facing normal, and the screen footprint of the rectangle grown by
  * the fringe margin delta(lambda) outside which w < tau.
- *   center [K][3], quat [K][4], radii [K][4]: device, K >= layout.n_planes;
+ *   center [K][3], quat [K][4], radii [K][4]: device, K >= layout.n_planes
+ *   (K = 0, every job empty: the arrays may be null and nothing is projected);
  *   cams: device array of n_cams ps_camera; lambda: device float scalar;
  *   prm: host struct.  Result lives in the workspace. */
 int plane_project(const ps_layout* L, void* ws, const float* center, const float* quat,
@@ -331,7 +332,8 @@ int loss_depth_normal_cam(const ps_layout* L, void* ws, const float* depth, cons
  * over the jobs that use a plane).  Recomputes each pixel's ordered hit list
  * (no per-pixel list is stored between calls), walks it back to front for the
  * compositing adjoint, reduces per (tile, plane) and chains to (p, q, r) in a
- * fixed order (bitwise deterministic).  Inputs as for plane_project. */
+ * fixed order (bitwise deterministic).  Inputs as for plane_project (with
+ * K = 0 the plane and gradient arrays may be null). */
 int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const float* quat,
                      const float* radii, int K, const ps_camera* cams, int n_cams,
                      const float* lambda, const ps_params* prm, const float* g_depth,
@@ -341,7 +343,8 @@ int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const fl
 /* adam_step_planes (Sec. 3.3): bias-corrected Adam on the K planes.
  * m, v: device [11*K] laid out as center (3K) | quat (4K) | radii (4K).
  * step: device int, the 1-based step number read by the kernel.  After the
- * update radii are clamped to >= r_min.  Quaternions are not renormalised. */
+ * update radii are clamped to >= r_min.  Quaternions are not renormalised.
+ * K = 0 does nothing (the arrays may then be null). */
 int adam_step_planes(float* center, float* quat, float* radii, const float* g_center,
                      const float* g_quat, const float* g_radii, float* m, float* v, int K,
                      const int32_t* step, float lr_center, float lr_quat, float lr_radii,

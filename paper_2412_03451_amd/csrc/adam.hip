@@ -48,9 +48,10 @@ extern "C" int adam_step_planes(float* center, float* quat, float* radii, const 
                                 const float* g_quat, const float* g_radii, float* m, float* v, int K,
                                 const int32_t* step, float lr_center, float lr_quat, float lr_radii,
                                 float beta1, float beta2, float eps, float r_min, void* stream) {
-  if (!center || !quat || !radii || !g_center || !g_quat || !g_radii || !m || !v || !step)
-    return ps_set_error(PS_ERR_INVALID, "adam_step_planes: null pointer");
   if (K < 0) return ps_set_error(PS_ERR_INVALID, "adam_step_planes: K < 0");
+  // an empty plane set (K = 0) may come with null arrays
+  if (K > 0 && (!center || !quat || !radii || !g_center || !g_quat || !g_radii || !m || !v || !step))
+    return ps_set_error(PS_ERR_INVALID, "adam_step_planes: null pointer");
   if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
     return ps_set_error(PS_ERR_INVALID, "adam_step_planes: bad beta / eps");
   if (K == 0) return PS_OK;

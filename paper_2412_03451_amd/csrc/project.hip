@@ -228,8 +228,9 @@ extern "C" int plane_project(const ps_layout* L, void* ws, const float* center, 
                              const float* lambda, const ps_params* prm, void* stream) {
   int rc = ps_check_ws(L, ws, "plane_project");
   if (rc) return rc;
-  if (!center || !quat || !radii || !cams || !lambda || !prm)
-    return ps_set_error(PS_ERR_INVALID, "plane_project: null pointer");
+  // an empty plane set (K = 0) may come with null plane arrays
+  if (!cams || !lambda || !prm || K < 0 || (K > 0 && (!center || !quat || !radii)))
+    return ps_set_error(PS_ERR_INVALID, "plane_project: null pointer or K < 0");
   if (K < L->n_planes) return ps_set_error(PS_ERR_INVALID, "plane_project: K=%d < planes referenced %d", K, L->n_planes);
   if (n_cams <= 0) return ps_set_error(PS_ERR_INVALID, "plane_project: n_cams <= 0");
   if (!(prm->tau > 0.f && prm->tau < 1.f) || !(prm->z_near > 0.f) || prm->M < 1 || prm->M > kMaxM ||

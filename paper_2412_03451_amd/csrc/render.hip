@@ -1076,8 +1076,9 @@ static int bwd_args(const ps_layout* L, void* ws, const float* center, const flo
                     RenderArgs& a, const char* who) {
   int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, who);
   if (rc) return rc;
-  if (!center || !quat || !radii || !g_depth || !g_normal || !g_center || !g_quat || !g_radii)
-    return ps_set_error(PS_ERR_INVALID, "%s: null pointer", who);
+  // an empty plane set (K = 0) may come with null plane and gradient arrays
+  if (!g_depth || !g_normal || K < 0 || (K > 0 && (!center || !quat || !radii || !g_center || !g_quat || !g_radii)))
+    return ps_set_error(PS_ERR_INVALID, "%s: null pointer or K < 0", who);
   if (K < L->n_planes) return ps_set_error(PS_ERR_INVALID, "%s: K=%d < planes referenced %d", who, K, L->n_planes);
   a.g_depth = g_depth; a.g_normal = g_normal;
   a.center = center; a.quat = quat; a.K = K;

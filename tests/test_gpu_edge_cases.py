@@ -119,3 +119,55 @@ def test_tile_list_over_the_size_limit_is_refused():
         _render(ps, cam, oracle.lambda_at(0), (8, 8), capacity=K + 64)
     assert e.value.code == PS_ERR_CAPACITY
     assert "4096" in str(e.value)
+
+
+def test_empty_job_in_a_batch_and_empty_scene():
+    """A job with an empty plane range renders zeros and leaves the other
+    jobs and the gradients bitwise unchanged; a scene without planes (K = 0,
+    null plane arrays) renders zeros and differentiates to nothing."""
+    from paper_2412_03451_amd.splat import Job, Renderer, adam_step
+    ps = synth.random_planes(48, seed=8, independent_radii=True)
+    cams = [synth.tiny_camera(), synth.tiny_camera(96, 64, 80.0)]
+    K = ps.K
+    lam = torch.tensor([20.0], device="cuda")
+    c, q, rr = _dev(ps.center), _dev(ps.quat), _dev(ps.radii)
+    rng = np.random.default_rng(9)
+    outs = {}
+    for name, jobs in (("with_empty", [Job(0, K, 0, 128, 96), Job(K, K, 1, 96, 64), Job(0, K, 1, 96, 64)]),
+                       ("without", [Job(0, K, 0, 128, 96), Job(0, K, 1, 96, 64)])):
+        print(f"batch {name}: {len(jobs)} jobs", flush=True)
+        r = Renderer(jobs, cams)
+        D, N = r.render(c, q, rr, lam)
+        P = [j.width * j.height for j in jobs]
+        gD = torch.zeros(r.n_pixels, device="cuda")
+        gN = torch.zeros(3 * r.n_pixels, device="cuda")
+        for s, j in enumerate(jobs):
+            if j.plane_end > j.plane_begin:
+                o = r.pix_off[s]
+                g = torch.as_tensor(np.random.default_rng(100 + j.cam).normal(size=4 * P[s]).astype(np.float32),
+                                    device="cuda")
+                gD[o:o + P[s]] = g[:P[s]]
+                gN[3 * o:3 * (o + P[s])] = g[P[s]:]
+        grads = r.backward(c, q, rr, lam, gD, gN)
+        torch.cuda.synchronize()
+        outs[name] = (r, D, N, [g.clone() for g in grads])
+    r1, D1, N1, g1 = outs["with_empty"]
+    r0, D0, N0, g0 = outs["without"]
+    assert float(r1.job_depth(D1, 1).abs().max()) == 0.0 and float(r1.job_normal(N1, 1).abs().max()) == 0.0
+    for s1, s0 in ((0, 0), (2, 1)):
+        assert torch.equal(r1.job_depth(D1, s1), r0.job_depth(D0, s0))
+        assert torch.equal(r1.job_normal(N1, s1), r0.job_normal(N0, s0))
+    for a, b in zip(g1, g0):
+        assert torch.equal(a, b)
+    # no planes at all
+    print("scene without planes", flush=True)
+    e = torch.zeros(0, 3, device="cuda"), torch.zeros(0, 4, device="cuda"), torch.zeros(0, 4, device="cuda")
+    r = Renderer([Job(0, 0, 0, 128, 96)], cams[:1])
+    D, N = r.render(*e, lam)
+    assert float(D.abs().max()) == 0.0 and float(N.abs().max()) == 0.0
+    gc, gq, gr = r.backward(*e, lam, torch.ones(r.n_pixels, device="cuda"), torch.ones(3 * r.n_pixels, device="cuda"))
+    torch.cuda.synchronize()
+    assert gc.numel() == gq.numel() == gr.numel() == 0
+    m = torch.zeros(0, device="cuda")
+    adam_step(*e, gc, gq, gr, m, m.clone(), torch.ones(1, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()

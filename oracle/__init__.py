@@ -22,7 +22,7 @@ forward definition).  Sections cited:
 * learned initializer (not in the paper; readings) ... initnet.py
 
 Readings taken where the paper is silent or garbled are listed in the
-docstring of each function and collected in the design doc of the repository.
+docstring of each function.
 """
 
 from .render import (  # noqa: F401

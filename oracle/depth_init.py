@@ -7,7 +7,7 @@ surface built from monocular depth; each plane's radii are half the distance
 to its nearest neighbouring center and its rotation follows the surface
 normal.  Sec. 4.3 (plane-initialisation ablation): the alternative places
 the planes on the scene's bounding sphere, radii 0.05, normals towards the
-sphere's center.  Readings (also collected in the design doc):
+sphere's center.  Readings:
 
 * coarse surface = the voxels (edge `voxel`, grid anchored at the world
   origin) occupied by the back-projected pixels of the depth maps; one point

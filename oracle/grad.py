@@ -9,7 +9,7 @@ per_pixel_abs_grad also returns, per parameter coordinate, the sum over
 pixels of the absolute value of each pixel's contribution.  It is obtained by
 giving every pixel its own copy of the parameters, so one backward pass
 yields the per-pixel Jacobian rows.  The GPU's float32 sums over pixels are
-judged against this scale where the pixel contributions cancel.
+compared against this scale where the pixel contributions cancel.
 
 weight_path_magnitude is the matching scale for cancellation inside one
 pixel.  The adjoint of the front-to-back composite (Eq. 11-13) with respect

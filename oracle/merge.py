@@ -3,7 +3,7 @@
 Sec. 3.3 (plane merge paragraph): after the fit, primitives whose normals
 differ by less than 25 degrees and whose offsets differ by less than 0.1 cm
 are merged, the offset being the distance from the scene center to the plane
-along its normal.  Readings (also collected in the design doc):
+along its normal.  Readings:
 
 * the normal of a plane is R(q) e_z with q normalised (Eq. 3); primitives
   are two-sided, so two planes are compared with the second one's normal

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: see the package docstring.
 
 Every pixel's ray is intersected with every plane; nothing is tiled, culled
 or reordered beyond what the method states.  Readings of points the paper
-leaves open (each also listed in the design doc):
+leaves open:
 
 * Eq. 4 prints the numerator as "(p - o . n)"; it is read as (p - o) . n.
 * the pinhole ray of pixel (i, j) passes through the pixel center

@@ -5,7 +5,7 @@ plane whose average radii gradient on its X axis (r^{x+}, r^{x-}) exceeds
 0.2 is split along its Y axis, and likewise a plane whose average radii
 gradient on its Y axis exceeds 0.2 is split along its X axis.  Readings:
 
-* "average radii gradient on the X axis" = (mean of |dL/dr^{x+}| and of
+* the average radii gradient on the X axis is read as (mean of |dL/dr^{x+}| and of
   |dL/dr^{x-}| over the iterations since the last split in which the plane
   took part in the render, i.e. had a radii gradient that is not all zero)
   averaged over the two: (A[x+] + A[x-]) / (2 n_k) with A the sum of
@@ -15,7 +15,7 @@ gradient on its Y axis exceeds 0.2 is split along its X axis.  Readings:
   the scale: on the synthetic room most planes cross it at every split under
   the summed loss, and none under the per-pixel mean averaged over all
   iterations instead of the iterations the plane took part in;
-* "split along the Y axis": the cut runs parallel to the plane's Y axis
+* splitting along the Y axis is read as a cut running parallel to the plane's Y axis
   through the middle of its X extent, giving two rectangles side by side
   along X, each with half the X extent (both radii along X equal to a
   quarter of the extent, the center moved to the middle of the half), the

@@ -92,6 +92,19 @@ struct ItemCtx {
 };
 
 // 0: block inside the image; 1: block entirely outside (partial tile); 2: bad camera
+// Render item of workgroup b of n.  The dispatcher hands workgroups to the
+// eight XCDs in turn (b runs on XCD b mod 8), and each XCD has its own L2;
+// the 8x8 items of one tile are consecutive and read the same list records.
+// Inside every aligned run of 32 workgroups, item 4 j + i goes to workgroup
+// 8 i + (j mod 8) of the run: a group of four consecutive items shares one
+// XCD, and the longest-first order of the items holds at a granularity of 32.
+// The last n mod 32 workgroups map to themselves (a bijection either way).
+__device__ inline int xcd_item(int b, int n) {
+  if (b >= (n & ~31)) return b;
+  const int k = b & 31;
+  return (b & ~31) + ((k & 7) << 2) + (k >> 3);
+}
+
 __device__ inline int item_setup(const RenderArgs& a, int item, ItemCtx& c) {
   const ItemDesc d = a.items[item];
   c.b = d.b;
@@ -457,14 +470,15 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   if (a.counters[C_OVERFLOW]) return;
   const bool diag = a.flags & kFlagDiag;
   const uint64_t t_start = diag ? wall_clock64() : 0;
-  long long* dg = a.diag + (size_t)blockIdx.x * D_NUM;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  long long* dg = a.diag + (size_t)item * D_NUM;
   if (diag && threadIdx.x < D_BWD_SETUP) dg[threadIdx.x] = 0;
   ItemCtx c;
-  const int st = item_setup(a, blockIdx.x, c);
+  const int st = item_setup(a, item, c);
   if (st != 0) {
     // no render here; the loss still needs the block's partials (zero) and,
     // for a camera out of range, zero gradients
-    if (a.loss_part) block_loss(a, blockIdx.x, c, st == 2 && c.inimg, 0.f, 0.f, 0.f, 0.f);
+    if (a.loss_part) block_loss(a, item, c, st == 2 && c.inimg, 0.f, 0.f, 0.f, 0.f);
     return;
   }
   c.stage = &stage;
@@ -493,7 +507,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
     a.normal[nb + c.HW] = s.N1;
     a.normal[nb + 2 * c.HW] = s.N2;
   }
-  if (a.loss_part) block_loss(a, blockIdx.x, c, c.inimg, s.D, s.N0, s.N1, s.N2);
+  if (a.loss_part) block_loss(a, item, c, c.inimg, s.D, s.N0, s.N1, s.N2);
 }
 
 // ------------------------------------------------------------------ backward
@@ -676,10 +690,11 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
       tk = now;
     }
   };
-  long long* dg = a.diag + (size_t)blockIdx.x * D_NUM;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  long long* dg = a.diag + (size_t)item * D_NUM;
   if (diag && threadIdx.x >= D_BWD_SETUP && threadIdx.x <= D_BWD_TICKS) dg[threadIdx.x] = 0;
   ItemCtx c;
-  const int st = item_setup(a, blockIdx.x, c);
+  const int st = item_setup(a, item, c);
   if (st == 2) return;
   c.stage = &stage;
   const int lane = threadIdx.x;

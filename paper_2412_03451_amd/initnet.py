@@ -8,7 +8,6 @@ on the device as float32 masters with bfloat16 copies for the MFMA kernels.
 
 from __future__ import annotations
 
-import ctypes as C
 
 import numpy as np
 import torch

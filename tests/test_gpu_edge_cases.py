@@ -17,7 +17,7 @@ import torch
 
 import oracle
 import synth
-from helpers import U32, cosine, depth_err, f32, grad_check, normal_err
+from helpers import cosine, depth_err, f32, grad_check, normal_err
 
 pytestmark = pytest.mark.gpu
 

@@ -5,7 +5,6 @@ whose proposals are worse falls back to the plain initialisation."""
 
 import numpy as np
 import pytest
-import torch
 
 import synth
 

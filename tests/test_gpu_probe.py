@@ -4,7 +4,6 @@ after n steps is a^n x0 + b (1 - a^n) / (1 - a)."""
 
 import numpy as np
 import pytest
-import torch
 
 pytestmark = pytest.mark.gpu
 

@@ -1,7 +1,6 @@
 """P5 (lambda schedule), P8 (loss closed forms), P9 (Adam first step),
 all on the CPU oracle."""
 
-import math
 import os
 
 import numpy as np

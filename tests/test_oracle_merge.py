@@ -8,7 +8,6 @@ import numpy as np
 
 import synth
 from oracle.merge import merge_planes, normals_offsets
-from synth.scenes import quat_from_matrix
 
 
 def _rot(axis, ang):

@@ -282,3 +282,34 @@ def test_room_backward_sampled_pixels():
         conds = oracle.weight_path_magnitude(init.center, init.quat, init.radii, cam, f32(lam), gD, gN,
                                              chunk=25, pix=pix)
         _check_grads(gpu, grads, abss, f"room lambda {lam:.4g}", conds=conds)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_pending_buffer_size_does_not_change_results(mode):
+    """The pending-hit buffer size (4, 6, 8 or 12 per lane) is a tuning knob:
+    forward maps and gradients are bitwise identical for every size and for
+    the exact fallback ordering forced on every pixel (the path a lane takes
+    when its buffer overflows)."""
+    from paper_2412_03451_amd.splat import Renderer, SplatParams
+    ps = synth.random_planes(160, seed=12, independent_radii=True, center_range=0.4, extent_range=(0.2, 0.7))
+    cam = synth.tiny_camera()
+    rng = np.random.default_rng(4)
+    gD = _dev(rng.normal(size=cam.width * cam.height))
+    gN = _dev(rng.normal(size=3 * cam.width * cam.height))
+    c, q, rr = _dev(ps.center), _dev(ps.quat), _dev(ps.radii)
+    lt = torch.tensor([12.0], device="cuda")
+    outs = {}
+    for P, flags in ((6, 0), (4, 1 << 4), (8, 2 << 4), (12, 3 << 4), ("all-fallback", 1)):
+        print(f"pending {P} mode {mode}", flush=True)
+        r = Renderer.single_scene([cam], ps.K, params=SplatParams(weight_mode=mode, flags=flags))
+        D, N = r.render(c, q, rr, lt)
+        slow = r.counters()["slow_pixels"]
+        g = r.backward(c, q, rr, lt, gD, gN)
+        torch.cuda.synchronize()
+        outs[P] = (D.clone(), N.clone(), [x.clone() for x in g], slow)
+    print({P: o[3] for P, o in outs.items()}, flush=True)
+    assert outs["all-fallback"][3] == cam.width * cam.height
+    for P in (4, 8, 12, "all-fallback"):
+        assert torch.equal(outs[P][0], outs[6][0]) and torch.equal(outs[P][1], outs[6][1])
+        for a, b in zip(outs[P][2], outs[6][2]):
+            assert torch.equal(a, b)

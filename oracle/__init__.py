@@ -31,6 +31,8 @@ from .render import (  # noqa: F401
     quat_to_frame,
     render,
     render_pixels,
+    render_tiled,
+    order_key,
     footprint_tiles,
 )
 from .loss import render_loss, loss_terms  # noqa: F401

@@ -28,7 +28,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .render import OracleParams, _pairs, _t, render_pixels
+from .render import OracleParams, _pairs, _t, order_key, render_pixels
 
 F64 = torch.float64
 
@@ -101,7 +101,7 @@ def weight_path_magnitude(center, quat, radii, cam, lam, gD, gN, prm: OraclePara
         rr = radii[None].expand(n, K, 4).clone().requires_grad_(True)
         q = _pairs(cc, qq, rr, cam, lam, pc, prm)
         # the hits each pixel composites, near to far (the forward's selection)
-        key = torch.where(q["keep"], q["t"].detach().to(torch.float32).to(F64), torch.full_like(q["t"], np.inf))
+        key = torch.where(q["keep"], order_key(q["t"].detach(), prm), torch.full_like(q["t"], np.inf))
         sel = torch.sort(key, dim=1, stable=True).indices[:, :min(prm.M, K)]
         ks = q["keep"].gather(1, sel)
         w_s = torch.where(ks, q["w"].gather(1, sel), torch.zeros((), dtype=F64))

@@ -81,7 +81,10 @@ typedef struct ps_params {
                           result does not depend on it);
                           bit 6: record per-block walk statistics of the
                           forward and backward renders (ps_read_counters
-                          out[6..17] and out[19]) */
+                          out[6..17] and out[19]);
+                          bit 7: plane_render_fwd adds 256 to the hit count
+                          (its `count` output) of every pixel that took the
+                          exact fallback ordering path */
 } ps_params;
 
 /* One render job.  The caller fills the first block; ps_layout_init fills
@@ -283,7 +286,11 @@ int plane_project(const ps_layout* L, void* ws, const float* center, const float
                   const float* radii, int K, const ps_camera* cams, int n_cams,
                   const float* lambda, const ps_params* prm, void* stream);
 
-/* tile_bin: (tile, plane) pairs of every job, each pair keyed by a depth
+/* tile_bin (serves the per-ray depth order of Sec. 3.2: each ray's surviving
+ * intersections are sorted by depth, and the sorted per-tile lists let the
+ * render commit every hit in exact per-ray order; the footprint tested per
+ * tile is the region where the weight of Eq. 7-9 reaches tau): (tile, plane)
+ * pairs of every job, each pair keyed by a depth
  * lower bound of the plane over the tile, sorted per tile by (bound, record).
  * Steps: per-record tile count -> wave64 prefix scan of tile and record
  * counts -> key emission -> per-tile sort (LDS bitonic).  If pairs_needed is
@@ -327,8 +334,10 @@ int loss_depth_normal_cam(const ps_layout* L, void* ws, const float* depth, cons
                           const int64_t* tgt_off, int n_cams, float a_cos, float a_nl1, float a_d,
                           float* loss, float* g_depth, float* g_normal, void* stream);
 
-/* plane_render_bwd: gradient of sum_px g_depth*D + g_normal.N with respect to
- * center, quat, radii (device [K][3], [K][4], [K][4], overwritten; summed
+/* plane_render_bwd (the adjoint of Eq. 4-13: ray-plane intersection, splat
+ * weight and front-to-back compositing, chained to the primitive's
+ * parameters through Eq. 1-3): gradient of sum_px g_depth*D + g_normal.N with
+ * respect to center, quat, radii (device [K][3], [K][4], [K][4], overwritten; summed
  * over the jobs that use a plane).  Recomputes each pixel's ordered hit list
  * (no per-pixel list is stored between calls), walks it back to front for the
  * compositing adjoint, reduces per (tile, plane) and chains to (p, q, r) in a

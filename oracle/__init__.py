@@ -20,6 +20,7 @@ forward definition).  Sections cited:
 * initialisation from depth, sphere initialisation ... Sec. 3.1 and 4.3, depth_init.py
 * plane merge ........................................ Sec. 3.3, merge.py
 * learned initializer (not in the paper; readings) ... initnet.py
+* central finite differences of the render .......... fd.py
 
 Readings taken where the paper is silent or garbled are listed in the
 docstring of each function.
@@ -42,3 +43,4 @@ from . import initnet  # noqa: F401
 from .split import split_planes  # noqa: F401
 from . import depth_init  # noqa: F401
 from .merge import merge_planes  # noqa: F401
+from . import fd  # noqa: F401

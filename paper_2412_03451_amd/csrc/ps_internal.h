@@ -149,6 +149,7 @@ enum Counter {
 };
 static_assert(C_BT_MAX + 1 == PS_N_COUNTERS, "counter count");
 constexpr int kFlagDiag = 64;   // params.flags bit 6: forward walk statistics
+constexpr int kFlagPathDiag = 128;   // params.flags bit 7: mark fallback-path pixels in the hit counts
 
 constexpr int kMaxM = 30;
 constexpr int kSmallSort = 1024;  // tile lists up to this size sort in one small-LDS pass

@@ -294,8 +294,9 @@ __device__ __forceinline__ void drain(const RenderArgs& a, const ItemCtx& c, int
 // Walk the tile list of one 8x8 block and hand every committed hit, in exact
 // per-ray order, to sink.commit(t, a*, list position, payload), the payload
 // formed by sink.payload(t, normal of the plane).
+// Returns whether this lane took the exact fallback (its buffer overflowed).
 template <int P, bool GAUSS, class Sink>
-__device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink& sink, float lam5,
+__device__ __forceinline__ bool walk(const RenderArgs& a, const ItemCtx& c, Sink& sink, float lam5,
                                      double delta, long long& evals, long long& steps) {
   Pending<P> pd;
   pd.reset();
@@ -361,6 +362,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
     __syncthreads();
   }
   const uint64_t slow_mask = ballot(slow);
+  const bool took_fallback = slow;
   if (slow_mask && threadIdx.x == 0)
     atomicAdd((unsigned long long*)&a.counters[C_SLOW], (unsigned long long)__popcll(slow_mask));
   // Exact continuation for lanes whose buffer overflowed: rounds that each
@@ -408,6 +410,7 @@ __device__ __forceinline__ void walk(const RenderArgs& a, const ItemCtx& c, Sink
       if (exhausted) slow = false;
     }
   }
+  return took_fallback;
 }
 
 // ------------------------------------------------------------------ forward
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   const double delta = fringe_margin((double)lam, a.flog, a.mode);
   FwdSink s{1.f, 0.f, 0.f, 0.f, 0.f, 0, lam5, a.mode, &a, c.pix};
   long long evals = 0, steps = 0;
-  walk<P, GAUSS>(a, c, s, lam5, delta, evals, steps);
+  const bool took_fallback = walk<P, GAUSS>(a, c, s, lam5, delta, evals, steps);
   if (diag) {
     int commits = s.count;
     commits = wave_allreduce(commits, [](int x, int y) { return x + y; });
@@ -501,7 +504,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
   if (c.inimg) {
     a.depth[c.pix] = s.D;
     if (a.trans) a.trans[c.pix] = s.T;
-    if (a.count) a.count[c.pix] = s.count;
+    if (a.count) a.count[c.pix] = s.count + ((a.flags & kFlagPathDiag) && took_fallback ? 256 : 0);
     const int64_t nb = 3 * c.pix_off + (c.pix - c.pix_off);
     a.normal[nb] = s.N0;
     a.normal[nb + c.HW] = s.N1;

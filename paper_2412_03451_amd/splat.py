@@ -151,9 +151,11 @@ class Renderer:
         check(rc)
         self.last_pairs = int(need.value)
 
-    def forward(self, diagnostics: bool = False):
+    def forward(self, diagnostics: bool = False, mark_fallback: bool = False):
         """Depth [n_pixels] and normal [3 n_pixels]; with diagnostics also the
-        final transmittance and the number of composited hits per pixel."""
+        final transmittance and the number of composited hits per pixel (with
+        mark_fallback, plus 256 where the pixel took the exact fallback
+        ordering path)."""
         depth = torch.empty(self.n_pixels, dtype=torch.float32, device=self.device)
         normal = torch.empty(3 * self.n_pixels, dtype=torch.float32, device=self.device)
         trans = count = None
@@ -162,7 +164,7 @@ class Renderer:
             count = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
         prm = self.params.c()
         if diagnostics:
-            prm.flags |= 64
+            prm.flags |= 64 | (128 if mark_fallback else 0)
         _, _, _, lam = self._inputs
         check(self.lib.plane_render_fwd(C.byref(self.L), _ptr(self.ws), _ptr(self.cams), self.n_cams, _ptr(lam),
                                         C.byref(prm), _ptr(depth), _ptr(normal), _ptr(trans), _ptr(count),
@@ -207,6 +209,14 @@ class Renderer:
         self.project(center, quat, radii, lam)
         self.bin()
         return self.forward()
+
+    def render_diag(self, center, quat, radii, lam):
+        """render() with the diagnostics: depth, normal, final transmittance
+        and hit count per pixel, plus 256 where the pixel took the exact
+        fallback ordering path."""
+        self.project(center, quat, radii, lam)
+        self.bin()
+        return self.forward(diagnostics=True, mark_fallback=True)
 
     def loss(self, depth, normal, tgt_depth, tgt_normal, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0):
         loss = torch.empty(len(self.jobs), 4, dtype=torch.float32, device=self.device)

@@ -98,3 +98,14 @@ def test_check_finite_argument_errors():
     assert lib.ps_check_finite(dummy, -1, dummy, None, None) == _lib.PS_ERR_INVALID
     assert lib.ps_check_finite(dummy, 10, None, None, None) == _lib.PS_ERR_INVALID
     assert lib.ps_check_finite(None, 10, dummy, None, None) == _lib.PS_ERR_INVALID
+
+
+def test_every_hot_path_call_cites_the_paper():
+    """The comment in front of each of the six calls of the splatting path
+    names the passage it follows (a Sec. or an Eq. of the paper)."""
+    text = open(os.path.join(ROOT, "include", "planesplat.h")).read()
+    for n in ("plane_project", "tile_bin", "plane_render_fwd", "plane_render_bwd", "loss_depth_normal",
+              "adam_step_planes"):
+        m = re.search(r"/\*((?:(?!\*/).)*?)\*/\s*int\s+" + n + r"\s*\(", text, flags=re.S)
+        assert m, n
+        assert re.search(r"\b(Sec\.|Eq\.)\s*\d", m.group(1)), n

@@ -312,6 +312,34 @@ int plane_render_fwd(const ps_layout* L, void* ws, const ps_camera* cams, int n_
                      const float* lambda, const ps_params* prm, float* depth, float* normal,
                      float* trans, int32_t* count, void* stream);
 
+/* plane_render_fwd_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  plane_project -> tile_bin -> plane_render_fwd of ONE job (all
+ * K planes, one camera, one width x height image, one tile shape) with the
+ * workspace in a static device array of the library instead of a caller
+ * buffer; the call allocates nothing and synchronises nothing.
+ *   center [K][3], quat [K][4], radii [K][4], cam (one ps_camera), lambda
+ *   (scalar): device; prm: host; depth [H*W], normal [3*H*W]: device,
+ *   overwritten with the bits plane_render_fwd gives for the same job;
+ *   status: device int32 or NULL, set to PS_OK, or to PS_ERR_CAPACITY when
+ *   the (tile, plane) pairs exceed what the array holds (depth and normal
+ *   are then zero).
+ * Limits: the array holds PS_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, from the
+ * library's load until the process ends; the pair capacity is what remains
+ * after the per-plane and per-tile regions (about 160 000 pairs for 16x16
+ * tiles at 640x480 and K = 2000, twice that for 8x8 tiles).  Sizes whose
+ * fixed regions alone exceed the array are rejected with PS_ERR_INVALID
+ * before any launch.  Every call on one GPU uses that GPU's one array and
+ * leaves its contents behind; each call clears what it needs itself, so calls
+ * in sequence are independent, but calls that overlap on one GPU (other
+ * streams, other threads) race on the array and must be serialised by the
+ * caller.  The stream's device decides which copy of the array is used. */
+#define PS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int plane_render_fwd_noalloc(const float* center, const float* quat, const float* radii, int K,
+                             const ps_camera* cam, int width, int height, int tile_w, int tile_h,
+                             const float* lambda, const ps_params* prm, float* depth, float* normal,
+                             int32_t* status, void* stream);
+
 /* loss_depth_normal (Eq. 14): per pixel a_cos |1 - N.N^| + a_nl1 ||N - N^||_1
  * + a_d |D - D^| with its gradient g_depth [n_pixels], g_normal [3*n_pixels]
  * (device, overwritten; sgn(0) = 0).  mask: device uint8 [n_pixels] or NULL.

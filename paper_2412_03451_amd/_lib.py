@@ -98,6 +98,8 @@ _EXPORTS = {
     "ps_read_counters": (C.c_int, [C.POINTER(PsLayout), _P, C.POINTER(C.c_int64), _P]),
     "ps_valu_probe": (C.c_int, [C.c_int, C.c_int, C.c_int, _P, C.c_size_t, _P]),
     "ps_check_finite": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int64), _P]),
+    "plane_render_fwd_noalloc": (C.c_int, [_P, _P, _P, C.c_int, _P, C.c_int, C.c_int, C.c_int, C.c_int, _P,
+                                           C.POINTER(PsParams), _P, _P, _P, _P]),
     "ps_last_error": (C.c_char_p, []),
 }
 

@@ -109,3 +109,19 @@ def test_every_hot_path_call_cites_the_paper():
         m = re.search(r"/\*((?:(?!\*/).)*?)\*/\s*int\s+" + n + r"\s*\(", text, flags=re.S)
         assert m, n
         assert re.search(r"\b(Sec\.|Eq\.)\s*\d", m.group(1)), n
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_noalloc_rejects_sizes_beyond_its_scratch():
+    """plane_render_fwd_noalloc checks its fixed regions against the static
+    scratch before touching the device (no launch, no device query)."""
+    from paper_2412_03451_amd import _lib
+    lib = _lib.load()
+    dummy = ctypes.c_void_p(256)
+    prm = _lib.PsParams(30, 1e-4, 0.01, 0, 1, 0)
+    rc = lib.plane_render_fwd_noalloc(dummy, dummy, dummy, 200000, dummy, 640, 480, 16, 16, dummy,
+                                      ctypes.byref(prm), dummy, dummy, None, None)
+    assert rc == _lib.PS_ERR_INVALID and b"static" in lib.ps_last_error()
+    rc = lib.plane_render_fwd_noalloc(dummy, dummy, dummy, 10, dummy, 640, 480, 12, 16, dummy,
+                                      ctypes.byref(prm), dummy, dummy, None, None)
+    assert rc == _lib.PS_ERR_INVALID

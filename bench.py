@@ -50,10 +50,12 @@ OPS_PER_EVAL = 17
 #   per composited hit: the weight (exp, reciprocal, ~4 operations), the
 #   compositing of depth, normal and transmittance (~6), the ordered insertion (~4)
 OPS_PER_HIT_FWD = 16
-#   backward per composited hit: the forward's work for the hit in the
-#   recomputing walk, its evaluation again in the gradient pass (17), and the
-#   chain rule to the 13 per-pair accumulators (~40)
-OPS_PER_HIT_BWD = OPS_PER_HIT_FWD + OPS_PER_EVAL + 40
+#   backward: the forward's work twice (the walk that recomputes the
+#   committed sequence, then every committed hit evaluated again for its
+#   gradient), 2 x 17 per evaluated pair and 2 x 16 per composited hit, plus
+#   the chain rule to the 13 per-pair accumulators (~40 per hit)
+OPS_PER_EVAL_BWD = 2 * OPS_PER_EVAL
+OPS_PER_HIT_BWD = 2 * OPS_PER_HIT_FWD + 40
 
 
 def log(*a):
@@ -266,7 +268,9 @@ def batched_bench(args):
         scenes.append(sc)
         work += sp["width"] * sp["height"] * gt.K
     log(f"{len(scenes)} rooms ready")
-    fit = BatchFit(scenes, cfg=FitConfig(check_every=max(1, args.warmup)))
+    from paper_2412_03451_amd.splat import SplatParams
+    params = SplatParams(flags=256 if args.per_item_launch else 0)
+    fit = BatchFit(scenes, cfg=FitConfig(check_every=max(1, args.warmup)), params=params)
     fit.size_capacity()
     start_state = fit.state()
     fit.run(max(1, args.warmup), graph=True)
@@ -296,6 +300,8 @@ def batched_bench(args):
         "ms_per_step": round(ms, 4), "dtype": "f32 (f64 ray-plane geometry)", "data": "synthetic",
         "config": {"workload": f"{len(scenes)} rooms, K log-uniform 200-4000, 20-100 views, 320x240 or 640x480, "
                                f"one view per room per step, lambda from ite 0", "rooms": len(scenes),
+                   "launch": "one workgroup per 8x8 block" if args.per_item_launch else
+                             "persistent (atomic work queue) where the blocks exceed 4x the resident workgroups",
                    "planes": int(fit.K), "pixels_per_step": int(fit.rend.n_pixels), "tiles": tiles,
                    "pair_capacity": int(fit.rend.L.pair_capacity)},
         "phase_ms": {k: round(x, 4) for k, x in phase_ms.items()},
@@ -608,7 +614,8 @@ def render_roofline(phase_ms, cnt, traffic=None, peaks=None):
     evals = int(round(cnt["evals"]))
     dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
     per_hit = OPS_PER_HIT_FWD if dom == "fwd" else OPS_PER_HIT_BWD
-    ops = evals * OPS_PER_EVAL + hits * per_hit
+    per_eval = OPS_PER_EVAL if dom == "fwd" else OPS_PER_EVAL_BWD
+    ops = evals * per_eval + hits * per_hit
     achieved = ops / (phase_ms[dom] * 1e-3) / 1e12
     roof = {
         "kernel": "render_fwd_kernel" if dom == "fwd" else "render_bwd_kernel+bwd_reduce_kernel",
@@ -619,7 +626,7 @@ def render_roofline(phase_ms, cnt, traffic=None, peaks=None):
         "frac": round(achieved / MI355X_VALU_TOPS, 5),
         "traffic": traffic,
         "launch_ms": round(phase_ms[dom], 4),
-        "algorithmic_units": f"{evals} evaluated pairs x {OPS_PER_EVAL} + {hits} composited hits x {per_hit} "
+        "algorithmic_units": f"{evals} evaluated pairs x {per_eval} + {hits} composited hits x {per_hit} "
                              f"lane operations",
     }
     if peaks:
@@ -676,7 +683,12 @@ def main():
                     help="room: the fitting-step throughput (default); scene-fit: wall-time of plain fits "
                          "against batched fits from the learned initialisation at equal depth L1")
     ap.add_argument("--rooms", type=int, default=32, help="scene-fit: held-out rooms; batched: rooms")
-    ap.add_argument("--autotune", action="store_true", help="batched: tile shape per room from the autotuner")
+    ap.add_argument("--autotune", dest="autotune", action="store_true", default=True,
+                    help="batched: tile shape per room from the autotuner (default)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batched: 16x16 tiles for every room")
+    ap.add_argument("--per-item-launch", action="store_true",
+                    help="batched: one workgroup per 8x8 block instead of the persistent work-queue launch")
     ap.add_argument("--train-rooms", type=int, default=64, help="scene-fit: rooms fitted to train the initializer")
     ap.add_argument("--fit-iters", type=int, default=2000,
                     help="scene-fit: iterations of the plain fits; init-ablation: iterations of each fit")

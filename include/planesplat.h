@@ -84,7 +84,13 @@ typedef struct ps_params {
                           out[6..17] and out[19]);
                           bit 7: plane_render_fwd adds 256 to the hit count
                           (its `count` output) of every pixel that took the
-                          exact fallback ordering path */
+                          exact fallback ordering path;
+                          bit 8: the render calls launch one workgroup per 8x8
+                          block even when the blocks are more than four times
+                          what the GPU holds resident (by default such a
+                          launch is persistent:
+                          resident workgroups claim blocks from an atomic work
+                          queue, longest lists first; same results) */
 } ps_params;
 
 /* One render job.  The caller fills the first block; ps_layout_init fills

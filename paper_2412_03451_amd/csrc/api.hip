@@ -24,6 +24,8 @@ static bool tile_ok(int tw, int th) {
 extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity, ps_layout* out) {
   if (!slots || !out || n_slots <= 0)
     return ps_set_error(PS_ERR_INVALID, "ps_layout_init: null pointer or n_slots <= 0");
+  if (n_slots > 32767)   // the render items keep the job index as int16
+    return ps_set_error(PS_ERR_INVALID, "ps_layout_init: more than 32767 jobs");
   if (pair_capacity < 1 || pair_capacity > (int64_t(1) << 31) - 1)
     return ps_set_error(PS_ERR_INVALID, "ps_layout_init: pair_capacity %lld out of range",
                         (long long)pair_capacity);
@@ -97,6 +99,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
       8 * ps::D_NUM * ((size_t)items + 1),  // R_DIAG
       4 * (T + 1),                     // R_TILEPOS
       4 * (R * (size_t)max_chunks + 1),  // R_CHUNK_CNT
+      8 * 2 * 8 * 16,                  // R_QUEUE
   };
   size_t off = 0;
   for (int i = 0; i < PS_NUM_REGIONS; ++i) {
@@ -137,6 +140,9 @@ extern "C" int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void*
   const int64_t n = 2 * 64;  // counters as int32 words
   hipLaunchKernelGGL(ps_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st,
                      (int32_t*)(base + L->region[ps::R_COUNTERS]), n, 0);
+  const int64_t nq = 2 * 2 * 8 * 16;  // work-queue counters as int32 words
+  hipLaunchKernelGGL(ps_fill_i32, dim3((nq + 255) / 256), dim3(256), 0, st,
+                     (int32_t*)(base + L->region[ps::R_QUEUE]), nq, 0);
   const int64_t nd = 2 * (int64_t)ps::D_NUM * (L->n_items + 1);  // statistics as int32 words
   hipLaunchKernelGGL(ps_fill_i32, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st,
                      (int32_t*)(base + L->region[ps::R_DIAG]), nd, 0);

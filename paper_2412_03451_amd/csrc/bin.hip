@@ -149,7 +149,7 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
       const int c = a.tile_cnt[t];
       atomicAdd(&hist[length_bucket(c)], sub_per);
       a.tile_cur[t] = 0;   // scatter cursors of bin_emit
-      if (c > kSmallSort && c <= kBigSort) a.bigtiles[atomicAdd(&nbig, 1)] = t;
+      if (c > kSmallSort && c <= kMaxList) a.bigtiles[atomicAdd(&nbig, 1)] = t;
     }
   }
   __syncthreads();
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
     a.counters[C_PAIRS] = total;
     a.counters[C_MAXTILE] = mx_t;
     a.counters[C_NBIG] = nbig;
-    a.counters[C_OVERFLOW] = (total > a.capacity || mx_t > kBigSort) ? 1 : 0;
+    a.counters[C_OVERFLOW] = (total > a.capacity || mx_t > kMaxList) ? 1 : 0;
     if (a.counters[C_OVERFLOW]) a.counters[C_STICKY] = 1;
     a.counters[C_SLOW] = 0;
     a.counters[C_BWD_PASSES] = 0;
@@ -265,6 +265,7 @@ __device__ void lds_bitonic(uint64_t* k, uint32_t* v, int n, const uint64_t* __r
     kout[i] = k[i];
     vout[i] = v[i];
   }
+  if (!rout) return;
   // record copies in list order, eight lanes per 128-byte record
   for (int i = threadIdx.x; i < 8 * n; i += NT) {
     const int e = i >> 3, q = i & 7;
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
       d.height = (int16_t)sl.height;
       d.cam = sl.cam;
       d.sub = (int16_t)sub;
-      d.pad = 0;
+      d.slot = (int16_t)s;
       d.pix_off = sl.pix_off;
       a.items[pos] = d;
     }
@@ -309,6 +310,35 @@ __global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
                                a.recs, a.recs_s + off);
 }
 
+// One merge pass over a tile list made of sorted runs of length L: the runs
+// 2m and 2m + 1 merge into one run of 2L.  Keys are unique (the record index
+// is in the low bits), so each entry's place is its index in its own run plus
+// the number of smaller keys in the other run (a binary search).
+__device__ void merge_pass(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* kout,
+                           uint32_t* vout, int n, int L) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = i / L;
+    const int ps = (r & ~1) * L;                  // start of the pair
+    const bool first = (r & 1) == 0;
+    const int ob = first ? ps + L : ps;           // the other run [ob, oe)
+    const int oe = first ? min(ps + 2 * L, n) : ps + L;
+    const uint64_t key = kin[i];
+    int lo = ob, hi = max(ob, oe);
+    while (lo < hi) {                             // first entry of the other run >= key
+      const int mid = (lo + hi) >> 1;
+      if (kin[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    const int own = first ? i - ps : i - (ps + L);
+    const int o = ps + own + (lo - ob);
+    kout[o] = key;
+    vout[o] = vin[i];
+  }
+}
+
+// Tile lists longer than kSmallSort.  Up to kBigSort entries: one bitonic
+// sort in LDS.  Longer (to kMaxList): chunks of kBigSort sorted in LDS, then
+// merge passes that move the runs between the tile's unsorted and sorted
+// segments (both hold n entries), ending in the sorted one.
 __global__ __launch_bounds__(1024) void bin_sort_big_kernel(BinArgs a) {
   extern __shared__ unsigned char smem[];
   uint64_t* k = (uint64_t*)smem;
@@ -319,8 +349,40 @@ __global__ __launch_bounds__(1024) void bin_sort_big_kernel(BinArgs a) {
     const int t = a.bigtiles[b];
     const int n = a.tile_cnt[t];
     const int off = a.tile_off[t];
-    lds_bitonic<kBigSort, 1024>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off,
-                                a.recs, a.recs_s + off);
+    if (n <= kBigSort) {
+      lds_bitonic<kBigSort, 1024>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off,
+                                  a.recs, a.recs_s + off);
+      __syncthreads();
+      continue;
+    }
+    // passes needed after the chunk sorts; the chunks go to the segment from
+    // which an even number of passes ends in the sorted one
+    int passes = 0;
+    for (int L = kBigSort; L < n; L <<= 1) ++passes;
+    uint64_t* kb[2] = {a.keys_s + off, a.keys_u + off};
+    uint32_t* vb[2] = {a.emit_s + off, a.emit_u + off};
+    int cur = passes & 1;
+    for (int c0 = 0; c0 < n; c0 += kBigSort) {
+      const int m = min(kBigSort, n - c0);
+      // unsorted input chunk and its output: in place when cur == 1 (the
+      // chunk is read into LDS before it is written back)
+      lds_bitonic<kBigSort, 1024>(k, v, m, a.keys_u + off + c0, a.emit_u + off + c0, kb[cur] + c0, vb[cur] + c0,
+                                  nullptr, nullptr);
+      __syncthreads();
+    }
+    __threadfence_block();
+    for (int L = kBigSort; L < n; L <<= 1) {
+      merge_pass(kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, L);
+      cur ^= 1;
+      __threadfence_block();
+      __syncthreads();
+    }
+    // record copies in list order
+    for (int i = threadIdx.x; i < 8 * n; i += blockDim.x) {
+      const int e = i >> 3, q = i & 7;
+      const int ri = (int)(uint32_t)a.keys_s[off + e];
+      reinterpret_cast<float4*>(&a.recs_s[off + e])[q] = reinterpret_cast<const float4*>(&a.recs[ri])[q];
+    }
     __syncthreads();
   }
 }
@@ -377,7 +439,7 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
         return ps_set_error(PS_ERR_CAPACITY, "tile_bin: %lld pairs exceed capacity %lld",
                             (long long)c[C_PAIRS], (long long)L->pair_capacity);
       return ps_set_error(PS_ERR_CAPACITY, "tile_bin: a tile holds more than %d pairs; use smaller tiles",
-                          kBigSort);
+                          kMaxList);
     }
   }
   return PS_OK;

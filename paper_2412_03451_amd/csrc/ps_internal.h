@@ -98,6 +98,7 @@ enum Region {
   R_DIAG,        // int64[n_items][16]  per-block walk statistics (flags bit 6)
   R_TILEPOS,     // int[T]       first render item of each tile (longest lists first)
   R_CHUNK_CNT,   // int[R][max_chunks]  passing tiles per (record, group of 64 tiles of its box)
+  R_QUEUE,       // uint64[2][8][16]  work-queue counters of persistent render launches (one line each)
   R_NUM_USED     // further regions are reserved (size 0)
 };
 // Render items are placed longest tile list first (buckets of list length),
@@ -120,7 +121,7 @@ struct alignas(16) ItemDesc {
   int16_t width, height;     // image size of the job
   int32_t cam;               // camera index of the job
   int16_t sub;               // 8x8 block index inside the tile
-  int16_t pad;
+  int16_t slot;              // job of the block
   int64_t pix_off;           // first pixel of the job
 };
 static_assert(sizeof(ItemDesc) == 32, "ItemDesc size");
@@ -149,11 +150,14 @@ enum Counter {
 };
 static_assert(C_BT_MAX + 1 == PS_N_COUNTERS, "counter count");
 constexpr int kFlagDiag = 64;   // params.flags bit 6: forward walk statistics
+constexpr int kFlagNoPersist = 256;   // params.flags bit 8: one workgroup per item even for large batches
 constexpr int kFlagPathDiag = 128;   // params.flags bit 7: mark fallback-path pixels in the hit counts
 
 constexpr int kMaxM = 30;
 constexpr int kSmallSort = 1024;  // tile lists up to this size sort in one small-LDS pass
-constexpr int kBigSort = 4096;    // hard limit of one tile list (48 KB of LDS)
+constexpr int kBigSort = 4096;    // tile lists up to this size sort in one LDS pass (48 KB of LDS);
+                                  // longer ones sort in chunks of this size, then merge in memory
+constexpr int kMaxList = 32767;   // longest tile list: list positions are kept as int16
 
 inline __host__ __device__ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -419,44 +423,66 @@ __device__ inline double wave_sum_double(double v) {
 
 __device__ inline float sgn_f(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
-__device__ inline void loss_pixel(const LossView& a, const ps_slot& sl, int px, int py, float D, const float N[3],
-                                  double l[4]) {
-  const int64_t HW = (int64_t)sl.width * sl.height;
+// The targets of one pixel (read before the render needs them, so that their
+// latency overlaps the walk).
+struct LossTargets {
+  float Dt, Nt[3], m;
+  int64_t p, nb, HW;
+  bool valid;
+};
+
+__device__ inline LossTargets loss_targets(const LossView& a, const ps_slot& sl, int px, int py) {
+  LossTargets t;
+  t.HW = (int64_t)sl.width * sl.height;
   const int64_t local = (int64_t)py * sl.width + px;
-  const int64_t p = sl.pix_off + local;
-  const int64_t nb = 3 * sl.pix_off + local;
+  t.p = sl.pix_off + local;
+  t.nb = 3 * sl.pix_off + local;
   // targets of a camera: its own image at tgt_off[cam] (a camera whose
   // index is out of range contributes nothing)
-  const bool valid = !a.tgt_off || (sl.cam >= 0 && sl.cam < a.n_cams);
-  if (!valid) {
-    a.gD[p] = 0.f;
-    for (int c = 0; c < 3; ++c) a.gN[nb + c * HW] = 0.f;
+  t.valid = !a.tgt_off || (sl.cam >= 0 && sl.cam < a.n_cams);
+  t.Dt = 0.f;
+  t.Nt[0] = t.Nt[1] = t.Nt[2] = 0.f;
+  t.m = 0.f;
+  if (!t.valid) return t;
+  const int64_t tp = a.tgt_off ? a.tgt_off[sl.cam] + local : t.p;
+  const int64_t tnb = a.tgt_off ? 3 * a.tgt_off[sl.cam] + local : t.nb;
+  t.m = a.mask ? (a.mask[tp] ? 1.f : 0.f) : 1.f;
+  t.Dt = a.Dt[tp];
+  for (int c = 0; c < 3; ++c) t.Nt[c] = a.Nt[tnb + c * t.HW];
+  return t;
+}
+
+__device__ inline void loss_apply(const LossView& a, const LossTargets& t, float D, const float N[3], double l[4]) {
+  if (!t.valid) {
+    a.gD[t.p] = 0.f;
+    for (int c = 0; c < 3; ++c) a.gN[t.nb + c * t.HW] = 0.f;
     return;
   }
-  const int64_t tp = a.tgt_off ? a.tgt_off[sl.cam] + local : p;
-  const int64_t tnb = a.tgt_off ? 3 * a.tgt_off[sl.cam] + local : nb;
-  const float m = a.mask ? (a.mask[tp] ? 1.f : 0.f) : 1.f;
-  const float Dt = a.Dt[tp];
-  float Nt[3];
-  for (int c = 0; c < 3; ++c) Nt[c] = a.Nt[tnb + c * HW];
+  const float m = t.m;
+  const float* Nt = t.Nt;
   const double dot = (double)N[0] * Nt[0] + (double)N[1] * Nt[1] + (double)N[2] * Nt[2];
   const double e1 = 1.0 - dot;
   const float s1 = e1 > 0 ? 1.f : (e1 < 0 ? -1.f : 0.f);
-  const float ed = D - Dt;
-  a.gD[p] = m * a.a_d * sgn_f(ed);
+  const float ed = D - t.Dt;
+  a.gD[t.p] = m * a.a_d * sgn_f(ed);
   double nl1 = 0;
   for (int c = 0; c < 3; ++c) {
     const float ec = N[c] - Nt[c];
     nl1 += fabs((double)N[c] - (double)Nt[c]);
-    a.gN[nb + c * HW] = m * (-a.a_cos * s1 * Nt[c] + a.a_nl1 * sgn_f(ec));
+    a.gN[t.nb + c * t.HW] = m * (-a.a_cos * s1 * Nt[c] + a.a_nl1 * sgn_f(ec));
   }
   if (m != 0.f) {
-    const double ad = fabs((double)D - (double)Dt);
+    const double ad = fabs((double)D - (double)t.Dt);
     l[0] += a.a_cos * fabs(e1);
     l[1] += a.a_nl1 * nl1;
     l[2] += a.a_d * ad;
     l[3] += ad;
   }
+}
+
+__device__ inline void loss_pixel(const LossView& a, const ps_slot& sl, int px, int py, float D, const float N[3],
+                                  double l[4]) {
+  loss_apply(a, loss_targets(a, sl, px, py), D, N, l);
 }
 
 __device__ inline int find_slot_by_pix(const ps_slot* __restrict__ sl, int S, int64_t pix_off) {

@@ -24,6 +24,8 @@
 // (center, quat, radii) by bwd_reduce_kernel.
 #include <string.h>
 
+#include <mutex>
+
 #include "ps_internal.h"
 
 using namespace ps;
@@ -76,11 +78,17 @@ struct RenderArgs {
   LossView loss;
   double* loss_part;
   int slots_sorted;   // plane ranges nondecreasing over the slots
+  // work-queue counters of a persistent launch (8 per direction, one 128-byte
+  // line each); the queue region until the launch, null in a launch of one
+  // workgroup per item
+  unsigned long long* queue;
 };
 
 struct ItemCtx {
   int b, e;          // list range in keys[]
   int sub;           // 8x8 block index inside the tile
+  int slot;          // job of the block
+  int ox, oy;        // pixel origin of the block
   int px, py;        // this lane's pixel
   bool inimg;
   int bx0, bx1, by0, by1;  // pixel box of the block (clipped to the image)
@@ -105,11 +113,28 @@ __device__ inline int xcd_item(int b, int n) {
   return (b & ~31) + ((k & 7) << 2) + (k >> 3);
 }
 
+// Issue priority of the wave for one item, by list length: the items with
+// the longest lists set a launch's duration, and the waves sharing their SIMD
+// (short items, mostly waiting on memory) lose little by yielding to them.
+__device__ inline void item_priority(int n) {
+  if (n >= 48)
+    __builtin_amdgcn_s_setprio(3);
+  else if (n >= 32)
+    __builtin_amdgcn_s_setprio(2);
+  else if (n >= 16)
+    __builtin_amdgcn_s_setprio(1);
+  else
+    __builtin_amdgcn_s_setprio(0);
+}
+
 __device__ inline int item_setup(const RenderArgs& a, int item, ItemCtx& c) {
   const ItemDesc d = a.items[item];
   c.b = d.b;
   c.e = d.e;
   c.sub = d.sub;
+  c.slot = d.slot;
+  c.ox = d.ox;
+  c.oy = d.oy;
   const int ox = d.ox, oy = d.oy, W = d.width, H = d.height;
   const int lane = threadIdx.x;
   c.px = ox + (lane & 7);
@@ -132,71 +157,86 @@ __device__ inline int item_setup(const RenderArgs& a, int item, ItemCtx& c) {
   return (ox < W && oy < H) ? 0 : 1;
 }
 
-// Sorted buffer of pending hits (ascending (t, record)), in registers.  Each
-// entry keeps the float32 a* of the hit (weights are formed at commit time)
-// and its list position; what the sink needs of the plane (its normal) is
-// read back at commit time by list position, from the staged batch when the
-// hit came from it.  Four registers per entry keep insertions and pops short.
+// Order key of a hit: the float32 depth's bits above the record index.  Hit
+// depths are positive (t > z_near > 0), where the bits of a float order like
+// the float, so one unsigned 64-bit comparison orders (t, record) as
+// key_less does; depth bounds compare as bits(bound) << 32.
+__device__ inline uint64_t hit_key(float t, int r) {
+  return ((uint64_t)__float_as_uint(t) << 32) | (uint32_t)r;
+}
+__device__ inline float key_depth(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ inline bool key_before(uint64_t k, float bound) {   // depth of k < bound (bound >= 0)
+  return (uint32_t)(k >> 32) < __float_as_uint(bound);
+}
+constexpr uint64_t kNoKey = ~0ull;
+
+// Sorted buffer of pending hits (ascending key), in registers.  Each entry
+// keeps the float32 a* of the hit (weights are formed at commit time) and its
+// list position; what the sink needs of the plane (its normal) is read back
+// at commit time by list position, from the staged batch when the hit came
+// from it.
 template <int P>
 struct Pending {
-  float t[P];
-  int r[P];
+  uint64_t k[P];
   float a[P];
   int pos[P];
   int n;
-  float ot; int orr;   // key of the opaque pending hit, +inf if none
-  float tt; int tr;    // key of the last pending hit
+  uint64_t ok;   // key of the opaque pending hit, kNoKey if none
+  uint64_t lk;   // key of the last pending hit, 0 if none
 
   __device__ void reset() {
     n = 0;
-    ot = INFINITY; orr = 0x7fffffff;
-    tt = -INFINITY; tr = -1;
+    ok = kNoKey;
+    lk = 0;
   }
 
   // Keep the `cap` nearest hits (cap = hits still allowed by M, or fewer).
   // false: the buffer is full and the hit may still be among the nearest cap.
-  __device__ bool insert(float nt, int nr, float na, bool opq, int npos, int cap) {
-    if (key_less(ot, orr, nt, nr)) return true;              // behind an opaque hit
+  __device__ bool insert(uint64_t nk, float na, bool opq, int npos, int cap) {
+    if (ok < nk) return true;                   // behind an opaque hit
     if (n >= cap) {
-      if (n == 0 || !key_less(nt, nr, tt, tr)) return true;  // not among the nearest cap
-      n -= 1;                                                // the old last entry drops out
-      ot = INFINITY; orr = 0x7fffffff;                       // an opaque hit is always the last entry
+      if (n == 0 || !(nk < lk)) return true;    // not among the nearest cap
+      n -= 1;                                   // the old last entry drops out
+      ok = kNoKey;                              // an opaque hit is always the last entry
     } else if (n == P) {
       return false;
     }
+    // from the top: entries above the new key move up one place, the new
+    // entry takes the first place whose lower neighbour is not above it
     int at = 0;
+    bool placed = false;
 #pragma unroll
-    for (int k = 0; k < P; ++k)
-      if (k < n && key_less(t[k], r[k], nt, nr)) ++at;
-#pragma unroll
-    for (int k = P - 1; k >= 1; --k)
-      if (k > at && k <= n) {
-        t[k] = t[k - 1]; r[k] = r[k - 1]; a[k] = a[k - 1]; pos[k] = pos[k - 1];
+    for (int i = P - 1; i >= 0; --i) {
+      if (i <= n) {
+        const bool up = i > 0 && nk < k[i - 1];
+        if (up) {
+          k[i] = k[i - 1]; a[i] = a[i - 1]; pos[i] = pos[i - 1];
+        } else if (!placed) {
+          k[i] = nk; a[i] = na; pos[i] = npos;
+          placed = true;
+          at = i;
+        }
       }
-#pragma unroll
-    for (int k = 0; k < P; ++k)
-      if (k == at) {
-        t[k] = nt; r[k] = nr; a[k] = na; pos[k] = npos;
-      }
+    }
     n += 1;
     if (opq) {   // everything behind an opaque hit is hidden
       n = at + 1;
-      ot = nt; orr = nr;
+      ok = nk;
     }
 #pragma unroll
-    for (int k = 0; k < P; ++k)
-      if (k == n - 1) { tt = t[k]; tr = r[k]; }
+    for (int i = 0; i < P; ++i)
+      if (i == n - 1) lk = k[i];
     return true;
   }
 
-  __device__ void pop(float& ft, int& fr, float& fa, int& fpos) {
-    ft = t[0]; fr = r[0]; fa = a[0]; fpos = pos[0];
+  __device__ void pop(uint64_t& fk, float& fa, int& fpos) {
+    fk = k[0]; fa = a[0]; fpos = pos[0];
 #pragma unroll
-    for (int k = 0; k + 1 < P; ++k) {
-      t[k] = t[k + 1]; r[k] = r[k + 1]; a[k] = a[k + 1]; pos[k] = pos[k + 1];
+    for (int i = 0; i + 1 < P; ++i) {
+      k[i] = k[i + 1]; a[i] = a[i + 1]; pos[i] = pos[i + 1];
     }
     n -= 1;
-    if (n == 0) { tt = -INFINITY; tr = -1; ot = INFINITY; orr = 0x7fffffff; }
+    if (n == 0) { lk = 0; ok = kNoKey; }
   }
 };
 
@@ -267,26 +307,27 @@ __device__ inline void cand_normal(const RenderArgs& a, const ItemCtx& c, int sb
 // Pop the nearest pending hit and hand it to the sink with its payload.
 template <int P, class Sink>
 __device__ __forceinline__ void commit_next(const RenderArgs& a, const ItemCtx& c, int sb, Pending<P>& pd,
-                                            Sink& sink, float& lt, int& lr) {
-  float ft, fa; int fr, fp;
-  pd.pop(ft, fr, fa, fp);
+                                            Sink& sink, uint64_t& lk) {
+  uint64_t fk; float fa; int fp;
+  pd.pop(fk, fa, fp);
+  const float ft = key_depth(fk);
   float nrm[3], pl[Sink::NP];
   cand_normal(a, c, sb, fp, nrm);
   sink.payload(ft, nrm, pl);
   sink.commit(ft, fa, fp, pl);
-  lt = ft; lr = fr;
+  lk = fk;
 }
 
 // Commit the pending hits nearer than `bound` (no later candidate can precede them).
 template <int P, class Sink>
 __device__ __forceinline__ void drain(const RenderArgs& a, const ItemCtx& c, int sb, Pending<P>& pd, Sink& sink,
-                                      int M, float bound, bool& done, float& lt, int& lr) {
-  bool want = !done && pd.n > 0 && pd.t[0] < bound;
+                                      int M, float bound, bool& done, uint64_t& lk) {
+  bool want = !done && pd.n > 0 && key_before(pd.k[0], bound);
   if (ballot(want)) {
     while (want) {
-      commit_next(a, c, sb, pd, sink, lt, lr);
+      commit_next(a, c, sb, pd, sink, lk);
       if (sink.finished(M)) { done = true; break; }
-      want = pd.n > 0 && pd.t[0] < bound;
+      want = pd.n > 0 && key_before(pd.k[0], bound);
     }
   }
 }
@@ -302,8 +343,7 @@ __device__ __forceinline__ bool walk(const RenderArgs& a, const ItemCtx& c, Sink
   pd.reset();
   bool slow = (a.flags & 1) && c.inimg;
   bool done = !c.inimg || slow || sink.finished(a.M);
-  float lt = -INFINITY;
-  int lr = -1;
+  uint64_t lk = 0;   // key of the last committed hit
   StageLds& S = *c.stage;
   bool stop = ballot(!done) == 0;
   for (int base = c.b; base < c.e && !stop; base += kBatch) {
@@ -335,20 +375,20 @@ __device__ __forceinline__ bool walk(const RenderArgs& a, const ItemCtx& c, Sink
           float pl[Sink::NP];
           sink.payload(t32, nrm, pl);
           sink.commit(t32, a32, base + j - c.b, pl);
-          lt = t32; lr = ri;
+          lk = hit_key(t32, ri);
           if (sink.finished(a.M)) done = true;
         }
       }
       const bool ins = hit && !now;
       if (ballot(ins)) {
         if (ins) {
-          if (!pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, a.M - sink.count)) {
+          if (!pd.insert(hit_key(t32, ri), a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, a.M - sink.count)) {
             slow = true;
             done = true;
           }
         }
       }
-      drain(a, c, base, pd, sink, a.M, tlb_next, done, lt, lr);
+      drain(a, c, base, pd, sink, a.M, tlb_next, done, lk);
       if (ballot(!done) == 0) {
         stop = true;
         break;
@@ -356,7 +396,7 @@ __device__ __forceinline__ bool walk(const RenderArgs& a, const ItemCtx& c, Sink
     }
     // pending hits below the bound of everything after this batch
     if (!stop) {
-      drain(a, c, base, pd, sink, a.M, tlb_after, done, lt, lr);
+      drain(a, c, base, pd, sink, a.M, tlb_after, done, lk);
       stop = ballot(!done) == 0;
     }
     __syncthreads();
@@ -383,7 +423,7 @@ __device__ __forceinline__ bool walk(const RenderArgs& a, const ItemCtx& c, Sink
         const int j = __ffsll((unsigned long long)ovm) - 1;
         ovm &= ovm - 1;
         const float tj = S.tlb[j];
-        const bool sat = (pd.n >= cap || pd.ot != INFINITY) && pd.tt < tj;
+        const bool sat = (pd.n >= cap || pd.ok != kNoKey) && pd.n > 0 && key_before(pd.lk, tj);
         const bool need = act && !sat;
         if (ballot(need) == 0) {
           stop2 = true;
@@ -399,14 +439,15 @@ __device__ __forceinline__ bool walk(const RenderArgs& a, const ItemCtx& c, Sink
         if (need && g.ok) {
           const float t32 = (float)g.t;
           const float a32 = (float)g.a;
-          if (key_less(lt, lr, t32, ri)) pd.insert(t32, ri, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, cap);
+          const uint64_t nk = hit_key(t32, ri);
+          if (lk < nk) pd.insert(nk, a32, a.mode == 0 && a32 >= 0.f, base + j - c.b, cap);
         }
       }
       __syncthreads();
     }
     if (act) {
-      const bool exhausted = pd.n < cap && pd.ot == INFINITY;
-      while (pd.n > 0 && !sink.finished(a.M)) commit_next(a, c, sb, pd, sink, lt, lr);
+      const bool exhausted = pd.n < cap && pd.ok == kNoKey;
+      while (pd.n > 0 && !sink.finished(a.M)) commit_next(a, c, sb, pd, sink, lk);
       if (exhausted) slow = false;
     }
   }
@@ -449,42 +490,45 @@ struct FwdSink {
 // The render loss of this 8x8 block's pixels (the loss kernel's arithmetic)
 // and the block's partial sums, stored where the loss kernel stores them: at
 // the job's first item plus the block's index in tile order.
-__device__ void block_loss(const RenderArgs& a, int item, const ItemCtx& c, bool pix_on, float D, float N0,
-                           float N1, float N2) {
-  const ItemDesc d = a.items[item];
-  const ps_slot& sl = a.slots[find_slot_by_pix(a.slots, a.S, d.pix_off)];
+__device__ void block_loss(const RenderArgs& a, const ItemCtx& c, const ps_slot& sl, const LossTargets& tg,
+                           bool pix_on, float D, float N0, float N1, float N2) {
   double l[4] = {0, 0, 0, 0};
   if (pix_on) {
     const float N[3] = {N0, N1, N2};
-    loss_pixel(a.loss, sl, c.px, c.py, D, N, l);
+    loss_apply(a.loss, tg, D, N, l);
   }
   for (int q = 0; q < 4; ++q) l[q] = wave_sum_double(l[q]);
   if (threadIdx.x == 0) {
     const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
-    const int tile = (d.oy / sl.tile_h) * sl.tiles_x + d.ox / sl.tile_w;
-    double* o = a.loss_part + 4 * ((size_t)sl.item_begin + (size_t)tile * sub_per + d.sub);
+    const int tile = (c.oy / sl.tile_h) * sl.tiles_x + c.ox / sl.tile_w;
+    double* o = a.loss_part + 4 * ((size_t)sl.item_begin + (size_t)tile * sub_per + c.sub);
     o[0] = l[0]; o[1] = l[1]; o[2] = l[2]; o[3] = l[3];
   }
 }
 
 template <int P, bool GAUSS>
-__global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
-  __shared__ StageLds stage;
-  if (a.counters[C_OVERFLOW]) return;
+__device__ __forceinline__ void fwd_item(const RenderArgs& a, int item, StageLds& stage) {
   const bool diag = a.flags & kFlagDiag;
   const uint64_t t_start = diag ? wall_clock64() : 0;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
   long long* dg = a.diag + (size_t)item * D_NUM;
   if (diag && threadIdx.x < D_BWD_SETUP) dg[threadIdx.x] = 0;
   ItemCtx c;
   const int st = item_setup(a, item, c);
+  // the loss targets of the pixel are read now; their latency overlaps the walk
+  ps_slot sl;
+  LossTargets tg;
+  if (a.loss_part) {
+    sl = a.slots[c.slot];
+    tg = loss_targets(a.loss, sl, c.inimg ? c.px : 0, c.inimg ? c.py : 0);
+  }
   if (st != 0) {
     // no render here; the loss still needs the block's partials (zero) and,
     // for a camera out of range, zero gradients
-    if (a.loss_part) block_loss(a, item, c, st == 2 && c.inimg, 0.f, 0.f, 0.f, 0.f);
+    if (a.loss_part) block_loss(a, c, sl, tg, st == 2 && c.inimg, 0.f, 0.f, 0.f, 0.f);
     return;
   }
   c.stage = &stage;
+  item_priority(c.e - c.b);
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
   const double delta = fringe_margin((double)lam, a.flog, a.mode);
@@ -510,7 +554,62 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
     a.normal[nb + c.HW] = s.N1;
     a.normal[nb + 2 * c.HW] = s.N2;
   }
-  if (a.loss_part) block_loss(a, item, c, c.inimg, s.D, s.N0, s.N1, s.N2);
+  if (a.loss_part) block_loss(a, c, sl, tg, c.inimg, s.D, s.N0, s.N1, s.N2);
+}
+
+// Persistent launches (a batch with more 8x8 items than the chip holds
+// resident): the grid is the resident capacity and every workgroup claims
+// work from an atomic queue until none remains.  The unit of a claim is a
+// group of four consecutive items (the 8x8 blocks of one 16x16 tile read the
+// same list), so a claim costs one atomic per four items.  Groups keep the
+// longest-first order and are dealt to eight streams in turn, stream x for
+// the workgroups the dispatcher places on XCD x (b mod 8), which keeps a
+// tile's list in one L2 as xcd_item does.  Each stream's counter has a
+// 128-byte line of its own: the atomics of one stream do not wait behind
+// those of the others.  A workgroup whose stream is empty moves to streams
+// that a plain read shows are not (no atomic on an empty stream).  A small
+// kernel after the launch clears the counters.
+constexpr int kQueueStride = 16;   // u64 words between stream counters (128 bytes)
+
+__device__ inline int claim_group(unsigned long long* cnt, int n_groups, int& stream) {
+  for (int tries = 0; tries < 8; ++tries) {
+    const int x = (stream + tries) & 7;
+    // groups of stream x: x, x + 8, ...; its counter counts claims
+    const int per = n_groups > x ? (n_groups - x + 7) >> 3 : 0;
+    if (__hip_atomic_load(&cnt[x * kQueueStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+        (unsigned long long)per)
+      continue;
+    unsigned long long l = 0;
+    if (threadIdx.x == 0) l = atomicAdd(&cnt[x * kQueueStride], 1ull);
+    l = __shfl(l, 0, 64);
+    if (l < (unsigned long long)per) {
+      stream = x;
+      return x + 8 * (int)l;
+    }
+  }
+  return -1;
+}
+
+__global__ void queue_reset_kernel(unsigned long long* cnt) {
+  if (threadIdx.x < 8) cnt[threadIdx.x * kQueueStride] = 0ull;
+}
+
+template <int P, bool GAUSS, bool PERSIST>
+__global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
+  __shared__ StageLds stage;
+  if (a.counters[C_OVERFLOW]) return;
+  if (!PERSIST) {
+    fwd_item<P, GAUSS>(a, xcd_item(blockIdx.x, gridDim.x), stage);
+    return;
+  }
+  const int n_groups = (a.n_items + 3) >> 2;
+  int stream = blockIdx.x & 7;
+  for (int g = claim_group(a.queue, n_groups, stream); g >= 0; g = claim_group(a.queue, n_groups, stream)) {
+    for (int item = 4 * g; item < min(4 * g + 4, a.n_items); ++item) {
+      fwd_item<P, GAUSS>(a, item, stage);
+      __syncthreads();
+    }
+  }
 }
 
 // ------------------------------------------------------------------ backward
@@ -523,7 +622,7 @@ struct BwdLds {
   float cg[kChunk][64];   // c_j, then dL/dw_j after the back-to-front walk
   int16_t hpos[kMaxM][64];  // list positions of the committed hits, in commit order
   int gpos[64];           // a group of candidates of the gradient pass: list positions, ascending
-  uint32_t vis[kBigSort / 32];  // list positions visited by the first gradient pass
+  uint32_t vis[kBigSort / 32];  // list positions visited by the first gradient pass (lists up to kBigSort)
 };
 
 // Sum 16 per-lane values over the wave by recursive halving: each exchange
@@ -564,13 +663,15 @@ __device__ __forceinline__ float wave_sum16(float (&v)[16]) {
   return r;
 }
 
+static_assert(3 * kChunk < kMaxM && 4 * kChunk >= kMaxM, "chunk starts: at most four chunks of a list of M hits");
+
 struct BwdSink {
   static constexpr int NP = 1;   // payload: c = gD t + gN . n of the hit
   static constexpr bool BWD = true;
   float T;
   int count;
   int c0;
-  float Ttail, Stail;
+  float Tb1, Tb2, Tb3;   // transmittance in front of hits 8, 16, 24 (chunk starts)
   float gD, gN0, gN1, gN2;
   float lam5;
   int mode;
@@ -592,10 +693,10 @@ struct BwdSink {
       L->a[j][lane] = as;
       L->T[j][lane] = T;
       L->cg[j][lane] = cv;
-    } else if (j >= kChunk) {
-      Stail = fmaf(Ttail * w, cv, Stail);
-      Ttail = Ttail * omw;
     }
+    if (count == kChunk) Tb1 = T;
+    if (count == 2 * kChunk) Tb2 = T;
+    if (count == 3 * kChunk) Tb3 = T;
     T = T * omw;
     ++count;
   }
@@ -604,11 +705,13 @@ struct BwdSink {
 // Commit again, in the same order, the hits that the first pass's walk
 // committed (their list positions are in L.hpos): the same evaluation of the
 // same records gives the same bits, without walking the list again.
-__device__ inline void replay(const RenderArgs& a, const ItemCtx& c, BwdSink& s, int hits, bool one_batch,
-                              double delta) {
-  const int jmax = wave_max_int(hits);
+// Only the hits [j0, min(j1, hits)) are committed; s starts at hit j0 (its
+// count and the transmittance in front of that hit).
+__device__ inline void replay(const RenderArgs& a, const ItemCtx& c, BwdSink& s, int j0, int j1, int hits,
+                              bool one_batch, double delta) {
+  const int jmax = min(j1, wave_max_int(hits));
   const int lane = threadIdx.x;
-  for (int j = 0; j < jmax; ++j) {
+  for (int j = j0; j < jmax; ++j) {
     if (j < hits) {
       const int pos = s.L->hpos[j][lane];
       RecHead rec;
@@ -679,10 +782,7 @@ __device__ inline void zero_row(const RenderArgs& a, uint32_t em, int sub) {
 // its block, exactly once in the first pass (the gradient of a candidate the
 // block hits, zeros otherwise); further passes add to it.
 template <int P, bool GAUSS>
-__global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
-  __shared__ BwdLds L;
-  __shared__ StageLds stage;
-  if (a.counters[C_OVERFLOW]) return;
+__device__ __forceinline__ void bwd_item(const RenderArgs& a, int item, BwdLds& L, StageLds& stage) {
   const bool diag = a.flags & kFlagDiag;
   uint64_t tk = diag ? wall_clock64() : 0;
   unsigned long long ph[4] = {0, 0, 0, 0}, ncand = 0, ngrp = 0;
@@ -693,7 +793,6 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
       tk = now;
     }
   };
-  const int item = xcd_item(blockIdx.x, gridDim.x);
   long long* dg = a.diag + (size_t)item * D_NUM;
   if (diag && threadIdx.x >= D_BWD_SETUP && threadIdx.x <= D_BWD_TICKS) dg[threadIdx.x] = 0;
   ItemCtx c;
@@ -705,6 +804,14 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   if (st == 1) {   // block outside the image (partial tile): zero rows
     for (int i = lane; i < n; i += 64) zero_row(a, a.emit[c.b + i], c.sub);
     return;
+  }
+  item_priority(n);
+  // a list longer than the visit bitmask covers: clear all of its rows first,
+  // then every pass adds
+  const bool big = n > kBigSort;
+  if (big) {
+    for (int i = lane; i < n; i += 64) zero_row(a, a.emit[c.b + i], c.sub);
+    __threadfence_block();
   }
   for (int i = lane; i < kBigSort / 32; i += 64) L.vis[i] = 0u;
   const float lam = a.lambda[0];
@@ -721,35 +828,43 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   // a list of at most one batch stays staged in LDS after the walk
   const bool one_batch = n <= kBatch;
   mark(0);
-  int passes = 1;
-  int hits = 0;   // hits committed by the first pass's walk
-  for (int pass = 0; pass < passes; ++pass) {
-    BwdSink s{1.f, 0, pass * kChunk, 1.f, 0.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
+  // The walk commits every hit once, keeping the first chunk of kChunk hits
+  // per lane in LDS, every hit's list position and the transmittance at each
+  // chunk start.  Chunks are then processed last to first: a chunk after the
+  // first is committed again from its list positions (its transmittance
+  // restored, the same bits as the walk), the back-to-front recurrence
+  // carries the composite of everything behind it, and its candidates get
+  // their gradients.  Each hit is evaluated once after the walk.
+  int hits = 0;   // hits committed by the walk
+  BwdSink s{1.f, 0, 0, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
+  {
     long long evals = 0, steps = 0;
-    if (pass == 0 && a.lst_pos) {
+    if (a.lst_pos) {
       // no walk: stage the first batch here (record heads, emit indices),
       // which the one-batch paths below read from LDS
       if (n > 0) stage_batch<true>(a, c, c.b);
       hits = c.inimg ? a.count[c.pix] : 0;
       load_lists(a, c, s, hits, one_batch, delta);
-    } else if (pass == 0) {
+    } else {
       walk<P, GAUSS>(a, c, s, lam5, delta, evals, steps);
       hits = s.count;
-    } else {
-      replay(a, c, s, hits, one_batch, delta);
     }
-    if (pass == 0) {
-      const int jmax = wave_max_int(s.count);
-      passes = (jmax + kChunk - 1) / kChunk;
-      if (passes > 1 && lane == 0)
-        atomicAdd((unsigned long long*)&a.counters[C_BWD_PASSES], (unsigned long long)(passes - 1));
-    } else {
-      __threadfence_block();   // rows written by other lanes are read back below
+  }
+  const int passes = max(1, (wave_max_int(hits) + kChunk - 1) / kChunk);
+  if (passes > 1 && lane == 0)
+    atomicAdd((unsigned long long*)&a.counters[C_BWD_PASSES], (unsigned long long)(passes - 1));
+  float S = 0.f;   // composite of the hits behind the current chunk
+  for (int pass = 0; pass < passes; ++pass) {
+    const int chunk = passes - 1 - pass;
+    if (passes > 1) {
+      if (pass > 0) __threadfence_block();   // rows written by other lanes are read back below
+      const float T0 = chunk == 0 ? 1.f : chunk == 1 ? s.Tb1 : chunk == 2 ? s.Tb2 : s.Tb3;
+      BwdSink r{T0, chunk * kChunk, chunk * kChunk, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
+      replay(a, c, r, chunk * kChunk, (chunk + 1) * kChunk, hits, one_batch, delta);
     }
     mark(1);
     // back-to-front walk over this chunk
-    const int nE = max(0, min(kChunk, s.count - pass * kChunk));
-    float S = s.Stail;
+    const int nE = max(0, min(kChunk, hits - chunk * kChunk));
     for (int k = nE - 1; k >= 0; --k) {
       const float T = L.T[k][lane], cv = L.cg[k][lane];
       float omw;
@@ -787,7 +902,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
         if (p == 0x7fffffff) break;
         if (lane == 0) {
           L.gpos[grp] = p;
-          if (pass == 0) L.vis[p >> 5] |= 1u << (p & 31);
+          if (pass == 0 && !big) L.vis[p >> 5] |= 1u << (p & 31);
         }
         ++grp;
         if (np == p) {
@@ -873,7 +988,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
         const int q = lane >> 2;
         if ((lane & 3) == 0 && q < 13) {
           float* row = a.partial + ((size_t)stage.em[j] * a.max_sub + c.sub) * 16;
-          if (pass == 0)
+          if (pass == 0 && !big)
             row[q] = tot;
           else
             row[q] += tot;
@@ -881,7 +996,7 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
       }
       __syncthreads();
     }
-    if (pass == 0) {
+    if (pass == 0 && !big) {
       // rows of the list entries this block does not hit
       for (int i = lane; i < n; i += 64)
         if (!((L.vis[i >> 5] >> (i & 31)) & 1u))
@@ -894,6 +1009,25 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
     dg[D_BWD_CAND] = (long long)ncand;
     dg[D_BWD_GROUPS] = (long long)ngrp;
     dg[D_BWD_TICKS] = (long long)(ph[0] + ph[1] + ph[2] + ph[3]);
+  }
+}
+
+template <int P, bool GAUSS, bool PERSIST>
+__global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
+  __shared__ BwdLds L;
+  __shared__ StageLds stage;
+  if (a.counters[C_OVERFLOW]) return;
+  if (!PERSIST) {
+    bwd_item<P, GAUSS>(a, xcd_item(blockIdx.x, gridDim.x), L, stage);
+    return;
+  }
+  const int n_groups = (a.n_items + 3) >> 2;
+  int stream = blockIdx.x & 7;
+  for (int g = claim_group(a.queue, n_groups, stream); g >= 0; g = claim_group(a.queue, n_groups, stream)) {
+    for (int item = 4 * g; item < min(4 * g + 4, a.n_items); ++item) {
+      bwd_item<P, GAUSS>(a, item, L, stage);
+      __syncthreads();
+    }
   }
 }
 
@@ -1040,27 +1174,83 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
   a.diag = (long long*)(base + L->region[R_DIAG]);
   a.partial = (float*)(base + L->region[R_PARTIAL]);
   a.max_sub = L->max_sub;
+  a.queue = (unsigned long long*)(base + L->region[R_QUEUE]);
   return PS_OK;
 }
 
 }  // namespace
 
+// Workgroups of a render kernel resident on the device at once (cached per
+// kernel and device).  A launch with more 8x8 items than that runs
+// persistent: the grid is this many workgroups and they claim items from
+// the work queue; a smaller launch keeps one workgroup per item (no claim).
+static int resident_grid(const void* kernel, hipStream_t st, int* out) {
+  struct Entry { const void* k; int dev; int n; };
+  static Entry cache[64];
+  static int n_cache = 0;
+  static std::mutex mu;
+  int dev = 0;
+  if (st) {
+    hipDevice_t d;
+    PS_HIP_CHECK(hipStreamGetDevice(st, &d));
+    dev = (int)d;
+  } else {
+    PS_HIP_CHECK(hipGetDevice(&dev));
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < n_cache; ++i)
+    if (cache[i].k == kernel && cache[i].dev == dev) {
+      *out = cache[i].n;
+      return PS_OK;
+    }
+  int per_cu = 0, cus = 0;
+  PS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0));
+  PS_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int n = per_cu > 0 && cus > 0 ? per_cu * cus : 1;
+  if (n_cache < 64) cache[n_cache++] = Entry{kernel, dev, n};
+  *out = n;
+  return PS_OK;
+}
+
+// One workgroup per item, or persistent when the items are more than four
+// times what the GPU holds resident at once (ps_params.flags bit 8 keeps one
+// workgroup per item).
+template <class K1, class KP>
+static int launch_items(K1 k1, KP kp, RenderArgs& a, unsigned long long* queue, hipStream_t st) {
+  int cap1 = 0, cap = 0;
+  int rc = resident_grid(reinterpret_cast<const void*>(k1), st, &cap1);
+  if (rc) return rc;
+  rc = resident_grid(reinterpret_cast<const void*>(kp), st, &cap);
+  if (rc) return rc;
+  if (a.n_items <= 4 * cap1 || (a.flags & kFlagNoPersist)) {
+    a.queue = nullptr;
+    hipLaunchKernelGGL(k1, dim3(a.n_items), dim3(64), 0, st, a);
+    return PS_OK;
+  }
+  a.queue = queue;
+  hipLaunchKernelGGL(kp, dim3(cap), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, queue);
+  return PS_OK;
+}
+
 template <bool GAUSS>
-static void launch_fwd_g(RenderArgs& a, hipStream_t st) {
+static int launch_fwd_g(RenderArgs& a, hipStream_t st) {
+  unsigned long long* q = a.queue;
   switch (pending_of(a.flags)) {
-    case 4: hipLaunchKernelGGL((render_fwd_kernel<4, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
-    case 8: hipLaunchKernelGGL((render_fwd_kernel<8, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
-    case 12: hipLaunchKernelGGL((render_fwd_kernel<12, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((render_fwd_kernel<6, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    case 4: return launch_items(render_fwd_kernel<4, GAUSS, false>, render_fwd_kernel<4, GAUSS, true>, a, q, st);
+    case 8: return launch_items(render_fwd_kernel<8, GAUSS, false>, render_fwd_kernel<8, GAUSS, true>, a, q, st);
+    case 12: return launch_items(render_fwd_kernel<12, GAUSS, false>, render_fwd_kernel<12, GAUSS, true>, a, q, st);
+    default: return launch_items(render_fwd_kernel<6, GAUSS, false>, render_fwd_kernel<6, GAUSS, true>, a, q, st);
   }
 }
 template <bool GAUSS>
-static void launch_bwd_g(RenderArgs& a, hipStream_t st) {
+static int launch_bwd_g(RenderArgs& a, hipStream_t st) {
+  unsigned long long* q = a.queue + 8 * kQueueStride;
   switch (pending_of(a.flags)) {
-    case 4: hipLaunchKernelGGL((render_bwd_kernel<4, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
-    case 8: hipLaunchKernelGGL((render_bwd_kernel<8, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
-    case 12: hipLaunchKernelGGL((render_bwd_kernel<12, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
-    default: hipLaunchKernelGGL((render_bwd_kernel<6, GAUSS>), dim3(a.n_items), dim3(64), 0, st, a); break;
+    case 4: return launch_items(render_bwd_kernel<4, GAUSS, false>, render_bwd_kernel<4, GAUSS, true>, a, q, st);
+    case 8: return launch_items(render_bwd_kernel<8, GAUSS, false>, render_bwd_kernel<8, GAUSS, true>, a, q, st);
+    case 12: return launch_items(render_bwd_kernel<12, GAUSS, false>, render_bwd_kernel<12, GAUSS, true>, a, q, st);
+    default: return launch_items(render_bwd_kernel<6, GAUSS, false>, render_bwd_kernel<6, GAUSS, true>, a, q, st);
   }
 }
 
@@ -1068,20 +1258,16 @@ static void launch_bwd_g(RenderArgs& a, hipStream_t st) {
 // carry no per-candidate test of the mode.
 static int launch_fwd(RenderArgs& a, void* stream) {
   if (a.n_items == 0) return PS_OK;
-  if (a.mode == 2)
-    launch_fwd_g<true>(a, (hipStream_t)stream);
-  else
-    launch_fwd_g<false>(a, (hipStream_t)stream);
+  const int rc = a.mode == 2 ? launch_fwd_g<true>(a, (hipStream_t)stream) : launch_fwd_g<false>(a, (hipStream_t)stream);
+  if (rc) return rc;
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
 static int launch_bwd(RenderArgs& a, int K, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (a.n_items > 0) {
-    if (a.mode == 2)
-      launch_bwd_g<true>(a, st);
-    else
-      launch_bwd_g<false>(a, st);
+    const int rc = a.mode == 2 ? launch_bwd_g<true>(a, st) : launch_bwd_g<false>(a, st);
+    if (rc) return rc;
   }
   if (K > 0) hipLaunchKernelGGL(bwd_reduce_kernel, dim3(K), dim3(256), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());

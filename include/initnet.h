@@ -24,6 +24,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "planesplat.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -79,6 +81,51 @@ int64_t initnet_backward_ws(int B, int P);
  * 1-based). */
 int initnet_adam(float* master, float* m, float* v, const float* grad, int64_t n, const int32_t* step,
                  float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Geometry of the per-view form (reading: the network sees N depth samples
+ * of one view and proposes P planes in that view's camera frame; the scene
+ * initialisation takes from each initial plane's nearest confident proposal
+ * its supporting plane).
+ *
+ * initnet_view_points: the network's input of V views.  depth [V][H][W]
+ * (device, metres, 0 = no surface); cams: device array of V ps_camera; cand
+ * [V][n_cand] candidate pixel indices (y W + x, drawn by the caller) and eps
+ * [V][n_cand] standard normal draws (drawn by the caller).  Per view the
+ * candidates are taken in order and the first N with depth > 0 are kept; a
+ * kept pixel (i, j) with depth z becomes the camera-frame point z' d_c,
+ * z' = z (1 + sigma eps), d_c = ((i + 1/2 - cx) / fx, (j + 1/2 - cy) / fy, 1)
+ * (float64, each operation rounded on its own, stored as float32).  With
+ * fewer than N valid candidates the kept points repeat in order (zeros if
+ * none).  X [V][N][3] (device), n_valid [V] (device): points kept per view. */
+int initnet_view_points(const float* depth, const ps_camera* cams, int V, int H, int W, const int32_t* cand,
+                        const float* eps, int n_cand, int N, float sigma, float* X, int32_t* n_valid,
+                        void* stream);
+
+/* initnet_proposals_to_world: the proposals of B views (out [B][12P], the
+ * network's camera-frame output) decoded as the set loss decodes them
+ * (center; unit quaternion of (o3 + 1, o4, o5, o6); radii softplus(o) + 0.01;
+ * confidence sigmoid(o11)) and mapped to the world frame with the camera of
+ * each view (cams[view_cam[b]]): center R^T (c - t), rotation R^T R(q) as a
+ * unit quaternion (Shepperd's method).  Outputs [B*P][3], [B*P][4], [B*P][4],
+ * [B*P] (device). */
+int initnet_proposals_to_world(const float* out, int B, int P, const ps_camera* cams, const int32_t* view_cam,
+                               float* center, float* quat, float* radii, float* conf, void* stream);
+
+/* initnet_refine_planes: the learned initialisation of a scene.  For each of
+ * the K initial planes (center [K][3], quat [K][4], radii [K][4]) the
+ * nearest proposal (Q of them, world frame, from initnet_proposals_to_world)
+ * among those with confidence >= conf_min, by the set loss's distance
+ * d = |c_p - c_k|^2 + 0.25 (1 - (n_p . n_k)^2) + 0.25 ((a_p - a_k)^2 + (b_p - b_k)^2)
+ * (float64, each operation rounded on its own; the smallest index on ties).
+ * If d <= d_max the plane takes the proposal's supporting plane: its normal
+ * becomes n_p turned to the initial normal's side, its center moves onto
+ * that plane along the normal, its frame turns by the smallest rotation that
+ * takes the old normal to the new one; radii are kept.  Otherwise the plane
+ * is unchanged.  out_center [K][3], out_quat [K][4], match [K] (the
+ * proposal index, or -1): device. */
+int initnet_refine_planes(const float* center, const float* quat, const float* radii, int K, const float* p_center,
+                          const float* p_quat, const float* p_radii, const float* p_conf, int Q, double conf_min,
+                          double d_max, float* out_center, float* out_quat, int32_t* match, void* stream);
 
 #ifdef __cplusplus
 }

@@ -100,6 +100,11 @@ _EXPORTS = {
     "ps_check_finite": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int64), _P]),
     "plane_render_fwd_noalloc": (C.c_int, [_P, _P, _P, C.c_int, _P, C.c_int, C.c_int, C.c_int, C.c_int, _P,
                                            C.POINTER(PsParams), _P, _P, _P, _P]),
+    "initnet_view_points": (C.c_int, [_P, _P, C.c_int, C.c_int, C.c_int, _P, _P, C.c_int, C.c_int, C.c_float, _P,
+                                      _P, _P]),
+    "initnet_proposals_to_world": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P]),
+    "initnet_refine_planes": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P, _P, C.c_int, C.c_double, C.c_double, _P,
+                                        _P, _P, _P]),
     "ps_last_error": (C.c_char_p, []),
 }
 

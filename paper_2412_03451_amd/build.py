@@ -42,11 +42,13 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-# Per-file additions.  The scene initialisation and the plane merge turn
-# floats into integers (voxel indices, the pair relation) and must round
-# every float64 operation on its own, as the definition does: no contraction
-# into fused multiply-adds in those files.
-FILE_FLAGS = {"scene_init.hip": ["-ffp-contract=off"], "merge.hip": ["-ffp-contract=off"]}
+# Per-file additions.  The scene initialisation, the plane merge and the
+# learned initializer's refinement turn floats into integers (voxel indices,
+# the pair relation, the nearest proposal) and must round every float64
+# operation on its own, as the definition does: no contraction into fused
+# multiply-adds in those files.
+FILE_FLAGS = {"scene_init.hip": ["-ffp-contract=off"], "merge.hip": ["-ffp-contract=off"],
+              "viewinit.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str, hipcc: str, verbose: bool) -> str:

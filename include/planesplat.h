@@ -85,10 +85,12 @@ typedef struct ps_params {
                           bit 7: plane_render_fwd adds 256 to the hit count
                           (its `count` output) of every pixel that took the
                           exact fallback ordering path;
+                          bit 9: the forward's launch may be persistent too
+                          (by default only the backward's is: measured);
                           bit 8: the render calls launch one workgroup per 8x8
                           block even when the blocks are more than four times
                           what the GPU holds resident (by default such a
-                          launch is persistent:
+                          backward launch is persistent:
                           resident workgroups claim blocks from an atomic work
                           queue, longest lists first; same results) */
 } ps_params;

@@ -151,6 +151,7 @@ enum Counter {
 static_assert(C_BT_MAX + 1 == PS_N_COUNTERS, "counter count");
 constexpr int kFlagDiag = 64;   // params.flags bit 6: forward walk statistics
 constexpr int kFlagNoPersist = 256;   // params.flags bit 8: one workgroup per item even for large batches
+constexpr int kFlagPersistFwd = 512;  // params.flags bit 9: the forward persistent too
 constexpr int kFlagPathDiag = 128;   // params.flags bit 7: mark fallback-path pixels in the hit counts
 
 constexpr int kMaxM = 30;

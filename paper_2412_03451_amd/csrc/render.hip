@@ -1214,15 +1214,19 @@ static int resident_grid(const void* kernel, hipStream_t st, int* out) {
 
 // One workgroup per item, or persistent when the items are more than four
 // times what the GPU holds resident at once (ps_params.flags bit 8 keeps one
-// workgroup per item).
+// workgroup per item).  The forward is persistent only with flags bit 9: its
+// persistent form needs 150 VGPRs against 123 (three waves per SIMD instead
+// of four), and on the 64-room batch it took 1.02 ms against 0.70 ms one
+// workgroup per item; the backward (LDS-bound at eight workgroups per
+// compute unit either way) gains 3 % from it.
 template <class K1, class KP>
-static int launch_items(K1 k1, KP kp, RenderArgs& a, unsigned long long* queue, hipStream_t st) {
+static int launch_items(K1 k1, KP kp, RenderArgs& a, unsigned long long* queue, bool persist_ok, hipStream_t st) {
   int cap1 = 0, cap = 0;
   int rc = resident_grid(reinterpret_cast<const void*>(k1), st, &cap1);
   if (rc) return rc;
   rc = resident_grid(reinterpret_cast<const void*>(kp), st, &cap);
   if (rc) return rc;
-  if (a.n_items <= 4 * cap1 || (a.flags & kFlagNoPersist)) {
+  if (!persist_ok || a.n_items <= 4 * cap1 || (a.flags & kFlagNoPersist)) {
     a.queue = nullptr;
     hipLaunchKernelGGL(k1, dim3(a.n_items), dim3(64), 0, st, a);
     return PS_OK;
@@ -1236,21 +1240,24 @@ static int launch_items(K1 k1, KP kp, RenderArgs& a, unsigned long long* queue, 
 template <bool GAUSS>
 static int launch_fwd_g(RenderArgs& a, hipStream_t st) {
   unsigned long long* q = a.queue;
+  const bool pp = a.flags & kFlagPersistFwd;
   switch (pending_of(a.flags)) {
-    case 4: return launch_items(render_fwd_kernel<4, GAUSS, false>, render_fwd_kernel<4, GAUSS, true>, a, q, st);
-    case 8: return launch_items(render_fwd_kernel<8, GAUSS, false>, render_fwd_kernel<8, GAUSS, true>, a, q, st);
-    case 12: return launch_items(render_fwd_kernel<12, GAUSS, false>, render_fwd_kernel<12, GAUSS, true>, a, q, st);
-    default: return launch_items(render_fwd_kernel<6, GAUSS, false>, render_fwd_kernel<6, GAUSS, true>, a, q, st);
+    case 4: return launch_items(render_fwd_kernel<4, GAUSS, false>, render_fwd_kernel<4, GAUSS, true>, a, q, pp, st);
+    case 8: return launch_items(render_fwd_kernel<8, GAUSS, false>, render_fwd_kernel<8, GAUSS, true>, a, q, pp, st);
+    case 12:
+      return launch_items(render_fwd_kernel<12, GAUSS, false>, render_fwd_kernel<12, GAUSS, true>, a, q, pp, st);
+    default: return launch_items(render_fwd_kernel<6, GAUSS, false>, render_fwd_kernel<6, GAUSS, true>, a, q, pp, st);
   }
 }
 template <bool GAUSS>
 static int launch_bwd_g(RenderArgs& a, hipStream_t st) {
   unsigned long long* q = a.queue + 8 * kQueueStride;
   switch (pending_of(a.flags)) {
-    case 4: return launch_items(render_bwd_kernel<4, GAUSS, false>, render_bwd_kernel<4, GAUSS, true>, a, q, st);
-    case 8: return launch_items(render_bwd_kernel<8, GAUSS, false>, render_bwd_kernel<8, GAUSS, true>, a, q, st);
-    case 12: return launch_items(render_bwd_kernel<12, GAUSS, false>, render_bwd_kernel<12, GAUSS, true>, a, q, st);
-    default: return launch_items(render_bwd_kernel<6, GAUSS, false>, render_bwd_kernel<6, GAUSS, true>, a, q, st);
+    case 4: return launch_items(render_bwd_kernel<4, GAUSS, false>, render_bwd_kernel<4, GAUSS, true>, a, q, true, st);
+    case 8: return launch_items(render_bwd_kernel<8, GAUSS, false>, render_bwd_kernel<8, GAUSS, true>, a, q, true, st);
+    case 12:
+      return launch_items(render_bwd_kernel<12, GAUSS, false>, render_bwd_kernel<12, GAUSS, true>, a, q, true, st);
+    default: return launch_items(render_bwd_kernel<6, GAUSS, false>, render_bwd_kernel<6, GAUSS, true>, a, q, true, st);
   }
 }
 

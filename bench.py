@@ -156,6 +156,35 @@ def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
     }
 
 
+def culling_efficiency(init, cams, lam, tile, n_pix: int = 4096, seed: int = 0):
+    """Culling efficiency N_need / N_eval of the forward on view 0 at the
+    start state: N_eval is the forward's own count of evaluated (pixel,
+    plane) pairs over the whole view (its diagnostics), N_need the pairs a
+    ray needs (every kept hit up to and including its first opaque one, from
+    the float64 oracle) on a seeded uniform sample of n_pix pixels, scaled to
+    the view."""
+    import torch
+    import oracle
+    from paper_2412_03451_amd.splat import Job, Renderer
+    cam = cams[0]
+    W, H = cam.width, cam.height
+    rend = Renderer([Job(0, init.K, 0, W, H, tuple(tile))], cams, pair_capacity=1 << 22)
+    T = [torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+         for x in (init.center, init.quat, init.radii)]
+    rend.render_diag(*T, torch.tensor([lam], dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    n_eval = int(rend.counters()["evals"])
+    del rend
+    pix = np.sort(np.random.default_rng(seed).choice(W * H, size=n_pix, replace=False))
+    t0 = time.perf_counter()
+    _, _, aux = oracle.render_pixels(init.center, init.quat, init.radii, cam, float(np.float32(lam)), pix)
+    need = float(aux["need"].double().mean()) * W * H
+    return {"n_need": round(need), "n_eval": n_eval, "frac": round(need / max(1, n_eval), 4),
+            "sample": f"view 0 ({W}x{H}) at iteration 0; N_need from the float64 oracle on {n_pix} seeded "
+                      f"uniform pixels ({time.perf_counter() - t0:.1f} s), scaled to the view; N_eval over every "
+                      f"pixel of the view"}
+
+
 KERNEL_SOURCES = ("paper_2412_03451_amd/csrc/render.hip", "paper_2412_03451_amd/csrc/ps_internal.h")
 TRAFFIC_FILES = {"fwd": "profiles/render_fwd_room640_hbm_traffic.txt",
                  "bwd": "profiles/render_bwd_room640_hbm_traffic.txt"}
@@ -170,9 +199,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(phase: str):
+def traffic_key(args) -> str:
+    """The bench arguments that decide the render launches of the timed steps."""
+    return (f"--steps {args.steps} --start-ite {args.start_ite} --views {args.views} "
+            f"--tile {args.tile[0]} {args.tile[1]} --pending {args.pending}"
+            + (" --force-rounds" if args.force_rounds else ""))
+
+
+def measured_traffic(phase: str, key: str):
     """HBM bytes per launch of the render kernel from the committed counter
-    summary, if it was taken on the current kernel source (else None)."""
+    summary, if it was taken on the current kernel source over the same
+    steps (bench arguments `key`), else None."""
     path = os.path.join(ROOT, TRAFFIC_FILES[phase])
     if not os.path.exists(path):
         return None
@@ -182,7 +219,7 @@ def measured_traffic(phase: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or vals.get("bench_args") != key:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -370,80 +407,98 @@ def memory_bench(args):
 
 
 def scene_fit_bench(args):
-    """Held-out synthetic rooms (K ~ 500 planes, 20 views of 320 x 240,
-    f = 288.5): each is fitted alone from its noisy initialisation for
-    --fit-iters iterations; its depth L1 after that is its target.  Then all
-    rooms are fitted together in one batched fit from the learned
-    initialisation until every room reaches its target.  Wall-times exclude
-    the depth-L1 checks (taken every 50 iterations); the batched side includes
-    the initialisation's inference.  The initializer is trained first on
-    rooms fitted by the plain method (time reported, not counted)."""
+    """The second half of the metric: scene-fit wall-time at equal depth L1,
+    the batched fit from the learned initialisation against plain fits.
+
+    Rooms of the single-room configuration (K ~ 2000 planes, 100 views of
+    640x480, f = 577).  The initializer (4096 samples per view -> 256
+    proposals) is trained first on --train-rooms rooms fitted by the plain
+    method (time reported, not counted).  Then --rooms held-out rooms: each is
+    fitted alone from its noisy initialisation for --fit-iters iterations
+    (the plain method; its depth L1 after them is the room's target), and all
+    of them together in one batched fit from the learned initialisation until
+    each reaches its target.  Wall-times exclude the depth-L1 checks; the
+    batched side includes the initialisation (network inference, proposal
+    matching, and the fallback check)."""
     import torch
     import synth
-    from paper_2412_03451_amd import learned_init as li
+    from paper_2412_03451_amd import view_init as vi
     from paper_2412_03451_amd.fit import BatchFit, FitConfig, Scene
     from paper_2412_03451_amd.initnet import InitNet
 
-    W, H, F, K, V = 320, 240, 288.5, 500, 20
+    W, H, F, K, V = 640, 480, 577.0, 2000, 100
 
     def room(seed):
         gt, info = synth.room_planes(seed=seed, target_K=K)
         cams = synth.room_trajectory(seed, V, info, width=W, height=H, f=F)
-        return {"gt": gt, "init": synth.room_init_planes(gt, seed=seed + 7919), "cams": cams}
+        rm = {"gt": gt, "init": synth.room_init_planes(gt, seed=seed + 7919), "cams": cams}
+        rm["tD"], rm["tN"] = vi.render_targets((gt.center, gt.quat, gt.radii), cams)
+        return rm
 
+    # training data: rooms fitted by the plain method, one view per sample
     t0 = time.perf_counter()
-    train_rooms = [room(1000 + i) for i in range(args.train_rooms)]
-    fitted = []
-    for s in range(0, len(train_rooms), 16):
-        fitted += li.fit_rooms(train_rooms[s:s + 16], 1500)
-    data = li.training_planes(train_rooms, fitted)
-    net = InitNet(1, seed=0)
-    li.train_planes(net, data, 1500, batch=256, lr=1e-3)
+    data = vi.ViewData()
+    for s in range(0, args.train_rooms, 8):
+        batch = [room(1000 + i) for i in range(s, min(args.train_rooms, s + 8))]
+        fitted = vi.fit_rooms(batch, args.train_fit_iters)
+        for j, (rm, fp) in enumerate(zip(batch, fitted)):
+            data.add_room(rm, fp, seed=1000 + s + j)
+        del batch
+        torch.cuda.empty_cache()
+    data_s = time.perf_counter() - t0
+    log(f"training data: {len(data.X)} views of {args.train_rooms} rooms in {data_s:.1f} s")
+    t0 = time.perf_counter()
+    net = InitNet(vi.N_PROPOSALS, seed=0)
+    hist = vi.train(net, data, args.train_steps, batch=32, lr=1e-3, log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    log(f"initializer trained on {data.X.shape[0]} planes of {len(train_rooms)} rooms in {train_s:.1f} s")
+    del data
+    torch.cuda.empty_cache()
 
     rooms = [room(5000 + i) for i in range(args.rooms)]
-    for rm in rooms:
-        rm["tD"], rm["tN"] = li.render_targets((rm["gt"].center, rm["gt"].quat, rm["gt"].radii), rm["cams"])
     # plain: one fit per room
     plain_s, targets = 0.0, []
     for i, rm in enumerate(rooms):
         init = (rm["init"].center, rm["init"].quat, rm["init"].radii)
-        fit = BatchFit([Scene(*init, rm["cams"], rm["tD"], rm["tN"])], cfg=FitConfig(check_every=250))
+        fit = BatchFit([Scene(*init, rm["cams"], rm["tD"], rm["tN"])], cfg=FitConfig(check_every=500))
         fit.size_capacity()
+        start = fit.state()
         fit.run(1, graph=True)       # capture outside the timed region
-        fit.restore([torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda") for x in init]
-                    + [torch.zeros_like(fit.m), torch.zeros_like(fit.v), torch.zeros_like(fit.ite)])
+        fit.restore(start)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         fit.run(args.fit_iters, graph=True)
         torch.cuda.synchronize()
         plain_s += time.perf_counter() - t1
         targets.append(fit.depth_l1(0, lam=300.0))
+        del fit
     log(f"plain: {len(rooms)} fits of {args.fit_iters} iterations in {plain_s:.2f} s")
     # batched + learned initialisation
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    scenes, used = [], 0
-    for rm in rooms:
+    scenes, used, infos = [], 0, []
+    for i, rm in enumerate(rooms):
         init = (rm["init"].center, rm["init"].quat, rm["init"].radii)
-        planes, info = li.learned_init(net, init, rm["cams"], rm["tD"])
+        planes, info = vi.learned_init(net, init, rm["cams"], rm["tD"], seed=5000 + i)
         used += info["used"] == "learned"
+        infos.append(info)
         scenes.append(Scene(*planes, rm["cams"], rm["tD"], rm["tN"]))
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t1
-    fit = BatchFit(scenes, cfg=FitConfig(check_every=50))
+    fit = BatchFit(scenes, cfg=FitConfig(check_every=100))
     fit.size_capacity()
+    start = fit.state()
+    fit.run(1, graph=True)
+    fit.restore(start)
     done_at = [None] * len(rooms)
     batched_s, its = 0.0, 0
     while its < args.fit_iters * 2 and any(d is None for d in done_at):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        fit.run(50, graph=True)
+        fit.run(100, graph=True)
         torch.cuda.synchronize()
         batched_s += time.perf_counter() - t2
-        its += 50
+        its += 100
         for i in range(len(rooms)):
             if done_at[i] is None and fit.depth_l1(i, lam=300.0) <= targets[i]:
                 done_at[i] = its
@@ -453,15 +508,20 @@ def scene_fit_bench(args):
         "metric": "scene-fit wall-time at equal depth L1, batched+init vs plain",
         "value": round(plain_s / total, 3), "unit": "x (plain seconds / batched+init seconds)",
         "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "f32 (f64 ray-plane geometry)",
-        "config": {"workload": f"{len(rooms)} held-out rooms, K~{K}, {V} views of {W}x{H}, plain fits of "
-                               f"{args.fit_iters} iterations set each room's depth-L1 target",
-                   "rooms": len(rooms)},
+        "config": {"workload": f"{len(rooms)} held-out rooms of the single-room configuration (K~{K}, {V} views of "
+                               f"{W}x{H}); plain fits of {args.fit_iters} iterations set each room's depth-L1 target; "
+                               f"initializer: {vi.N_POINTS} samples per view -> {vi.N_PROPOSALS} proposals, trained on "
+                               f"{args.train_rooms} rooms fitted by the plain method", "rooms": len(rooms)},
         "plain_seconds": round(plain_s, 3), "batched_init_seconds": round(total, 3),
         "learned_init_seconds": round(init_s, 3), "batched_fit_seconds": round(batched_s, 3),
         "rooms_reaching_target": reached, "batched_iterations": its,
         "iterations_to_target": done_at, "learned_init_used": used,
-        "target_depth_l1_mean": round(float(np.mean(targets)), 5),
-        "initializer_training_seconds": round(train_s, 1), "initializer_training_planes": int(data.X.shape[0]),
+        "depth_l1_targets": [round(x, 5) for x in targets],
+        "depth_l1_init_plain_mean": round(float(np.mean([x["depth_l1_plain_init"] for x in infos])), 4),
+        "depth_l1_init_learned_mean": round(float(np.mean([x["depth_l1_learned_init"] for x in infos])), 4),
+        "planes_refined_mean": round(float(np.mean([x["planes_refined"] for x in infos])), 1),
+        "initializer": {"training_data_seconds": round(data_s, 1), "training_seconds": round(train_s, 1),
+                        "set_loss": hist},
     }
 
 
@@ -689,7 +749,10 @@ def main():
                     help="batched: 16x16 tiles for every room")
     ap.add_argument("--per-item-launch", action="store_true",
                     help="batched: one workgroup per 8x8 block instead of the persistent work-queue launch")
-    ap.add_argument("--train-rooms", type=int, default=64, help="scene-fit: rooms fitted to train the initializer")
+    ap.add_argument("--train-rooms", type=int, default=32, help="scene-fit: rooms fitted to train the initializer")
+    ap.add_argument("--train-fit-iters", type=int, default=1000,
+                    help="scene-fit: plain-fit iterations of the training rooms")
+    ap.add_argument("--train-steps", type=int, default=2000, help="scene-fit: initializer training steps")
     ap.add_argument("--fit-iters", type=int, default=2000,
                     help="scene-fit: iterations of the plain fits; init-ablation: iterations of each fit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -793,7 +856,7 @@ def main():
     pix = V * W * H
     value = pix * K / (ms_step * 1e-3) / 1e6
     dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
-    roof, hits, evals = render_roofline(phase_ms, cnt, measured_traffic(dom), measured_peaks())
+    roof, hits, evals = render_roofline(phase_ms, cnt, measured_traffic(dom, traffic_key(args)), measured_peaks())
     n_items = max(1, int(fit.rend.L.n_items))
     out = {
         "metric": "fwd+bwd Mpixel*planes/s",
@@ -836,6 +899,9 @@ def main():
         log("cpu baseline (float64 oracle on a pixel sample)")
         import oracle
         out["cpu_baseline"] = cpu_baseline(init, cams, oracle.lambda_at(args.start_ite), args.cpu_seconds)
+        if args.start_ite == 0:
+            log("culling efficiency (float64 oracle on a pixel sample of view 0)")
+            out["culling"] = culling_efficiency(init, cams, oracle.lambda_at(0), args.tile)
     print(json.dumps(out), flush=True)
 
 

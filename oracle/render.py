@@ -219,7 +219,13 @@ def _composite(q, prm: OracleParams):
         cov = cov + Tw
         T = T * o_s[:, j]                                 # Eq. 13, (1 - w_j)
     ids = torch.where(ks, sel, torch.full_like(sel, -1))
-    return D, N, dict(count=ks.sum(1), coverage=cov.detach(), ids=ids, T=T.detach())
+    # the hits a ray needs, without the cap of M: every kept hit up to and
+    # including the first opaque one (all kept hits if none is opaque)
+    kept_sorted = keep.gather(1, order)
+    opq = kept_sorted & (w.gather(1, order) >= 1)
+    first = torch.where(opq.any(1), opq.int().argmax(1) + 1, kept_sorted.sum(1))
+    need = torch.minimum(first, kept_sorted.sum(1))
+    return D, N, dict(count=ks.sum(1), coverage=cov.detach(), ids=ids, T=T.detach(), need=need)
 
 
 def render_pixels(center, quat, radii, cam, lam, pix, prm: OracleParams = OracleParams(),
@@ -294,7 +300,8 @@ def render_tiled(center, quat, radii, cam, lam, prm: OracleParams = OracleParams
     N = torch.zeros(H * W, 3, dtype=F64)
     Msel = min(prm.M, center.shape[0])
     aux = dict(count=torch.zeros(H * W, dtype=torch.int64), coverage=torch.zeros(H * W, dtype=F64),
-               ids=torch.full((H * W, Msel), -1, dtype=torch.int64), T=torch.ones(H * W, dtype=F64))
+               ids=torch.full((H * W, Msel), -1, dtype=torch.int64), T=torch.ones(H * W, dtype=F64),
+               need=torch.zeros(H * W, dtype=torch.int64))
     order = torch.argsort(ncand, descending=True, stable=True)
     i = 0
     while i < order.numel():
@@ -327,6 +334,7 @@ def render_tiled(center, quat, radii, cam, lam, prm: OracleParams = OracleParams
         aux["count"][pix] = a["count"]
         aux["coverage"][pix] = a["coverage"]
         aux["T"][pix] = a["T"]
+        aux["need"][pix] = a["need"]
         ids = a["ids"]
         mapped = torch.where(ids >= 0, idx.gather(1, ids.clamp_min(0)), ids)
         aux["ids"][pix, :mapped.shape[1]] = mapped

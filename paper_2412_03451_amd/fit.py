@@ -430,27 +430,32 @@ class BatchFit:
         D, N = r.render(self.c, self.q, self.r, lt)
         return D.view(H, W), N.view(3, H, W)
 
-    def depth_l1(self, scene: int = 0, views=None, lam: float | None = None) -> float:
+    def depth_l1(self, scene: int = 0, views=None, lam: float | None = None, chunk: int = 20) -> float:
         """Mean |D - D^| over the pixels of the given views of a scene (all by
-        default), every view rendered in one batch."""
+        default), rendered `chunk` views at a time.  The evaluation renderers
+        are kept per (scene, views) and start from at most 2^20 pairs,
+        growing only if a chunk needs more."""
         W, H = self.size[scene]
         V = self.v_off[scene + 1] - self.v_off[scene]
         views = list(range(V)) if views is None else list(views)
         a, b = int(self.k_off[scene]), int(self.k_off[scene + 1])
         tile = tuple(self.scenes[scene].tile or self.cfg.tile)
-        key = (scene, tuple(views))
         cache = getattr(self, "_eval", {})
-        if key not in cache:
-            cache[key] = Renderer([Job(a, b, self.v_off[scene] + v, W, H, tile) for v in views], self.rend.cams,
-                                  device=self.device, pair_capacity=self.rend.L.pair_capacity * len(views),
-                                  params=self.params)
-            self._eval = cache
-        r = cache[key]
+        self._eval = cache
         lt = torch.tensor([lam if lam is not None else float(self.lam.item())], device=self.device)
-        D, _ = r.render(self.c, self.q, self.r, lt)
-        offs = [int(self.tgt_off[self.v_off[scene] + v].item()) for v in views]
-        Dt = torch.cat([self.tgt_depth[o:o + W * H] for o in offs])
-        return float((D - Dt).abs().mean().item())
+        total = torch.zeros((), dtype=torch.float64, device=self.device)
+        for s0 in range(0, len(views), chunk):
+            part = views[s0:s0 + chunk]
+            key = (scene, tuple(part))
+            if key not in cache:
+                cache[key] = Renderer([Job(a, b, self.v_off[scene] + v, W, H, tile) for v in part], self.rend.cams,
+                                      device=self.device, pair_capacity=min(self.rend.L.pair_capacity, 1 << 20),
+                                      params=self.params)
+            D, _ = cache[key].render(self.c, self.q, self.r, lt)
+            offs = [int(self.tgt_off[self.v_off[scene] + v].item()) for v in part]
+            Dt = torch.cat([self.tgt_depth[o:o + W * H] for o in offs])
+            total += (D - Dt).abs().double().sum()
+        return float(total.item()) / (len(views) * W * H)
 
 
 class SceneFit(BatchFit):

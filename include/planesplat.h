@@ -153,7 +153,9 @@ int ps_set_cameras(const ps_layout* L, void* ws, const int32_t* view_of_slot, vo
  * so depth, normal, g_depth, g_normal and loss hold the same bits as the two
  * calls give (the loss kernel's read of the maps is saved).  Arguments as in
  * the two calls; tgt_off may be null (targets laid out like the jobs, as for
- * loss_depth_normal), else n_tgt offsets as n_cams of loss_depth_normal_cam. */
+ * loss_depth_normal), else n_tgt offsets as n_cams of loss_depth_normal_cam.
+ * loss may be NULL: the per-block partial sums then stay in the workspace
+ * and plane_render_bwd_adam forms the sums. */
 int plane_render_fwd_loss(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, const float* lambda,
                           const ps_params* prm, float* depth, float* normal, const float* tgt_depth,
                           const float* tgt_normal, const uint8_t* mask, const int64_t* tgt_off, int n_tgt,
@@ -289,7 +291,9 @@ int ps_fit_schedule(const ps_layout* L, void* ws, int32_t* ite, const int32_t* t
  *   center [K][3], quat [K][4], radii [K][4]: device, K >= layout.n_planes
  *   (K = 0, every job empty: the arrays may be null and nothing is projected);
  *   cams: device array of n_cams ps_camera; lambda: device float scalar;
- *   prm: host struct.  Result lives in the workspace. */
+ *   prm: host struct.  Result lives in the workspace.  The same launch
+ *   clears the per-record and per-tile counts that tile_bin accumulates, so
+ *   every tile_bin follows a plane_project on the same workspace. */
 int plane_project(const ps_layout* L, void* ws, const float* center, const float* quat,
                   const float* radii, int K, const ps_camera* cams, int n_cams,
                   const float* lambda, const ps_params* prm, void* stream);
@@ -305,8 +309,10 @@ int plane_project(const ps_layout* L, void* ws, const float* center, const float
  * non-null the call synchronises the stream, stores the number of pairs and
  * returns PS_ERR_CAPACITY when it exceeds layout.pair_capacity (the binning
  * is then incomplete and the render calls write nothing).  A tile may hold at
- * most 4096 pairs.  Without pairs_needed the overflow is only flagged on the
- * device (ps_read_counters). */
+ * most 32767 pairs (lists longer than 4096 sort in 4096-pair chunks that are
+ * then merged).  Without pairs_needed the overflow is only flagged on the
+ * device (ps_read_counters).  Call after plane_project (which clears the
+ * counts this call accumulates). */
 int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, void* stream);
 
 /* plane_render_fwd (Eq. 4, 6-9, 11-13): depth [n_pixels] and normal
@@ -384,6 +390,28 @@ int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const fl
                      const float* lambda, const ps_params* prm, const float* g_depth,
                      const float* g_normal, float* g_center, float* g_quat, float* g_radii,
                      void* stream);
+
+/* plane_render_bwd_adam: plane_render_bwd followed by adam_step_planes
+ * (the adjoint of Eq. 4-13, then Sec. 3.3's optimiser step) in one call,
+ * with the loss sums of Eq. 14 formed by workgroups added to the backward's
+ * per-plane reduction.  Arguments as in the two calls (center,
+ * quat, radii are updated in place; g_center, g_quat, g_radii receive the
+ * gradients; m, v, step as for adam_step_planes); the results are the bits
+ * of the two calls.  loss: device float [n_slots][4] or NULL; if given, the
+ * loss sums of the last plane_render_fwd_loss called with a NULL loss (its
+ * per-block partials wait in the workspace) are formed here, with the bits
+ * that call would have given, and the forward's own reduction launch is
+ * saved.  The update itself stays a kernel of its own: inside the
+ * reduction its latency (two float64 powers, the parameter reads) lengthens
+ * every round of a reduction over many planes.  This is the fitting step's
+ * form when neither the single-radius variant nor splitting statistics sit
+ * between the backward and the update. */
+int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
+                          const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm,
+                          const float* g_depth, const float* g_normal, float* g_center, float* g_quat,
+                          float* g_radii, float* m, float* v, const int32_t* step, float lr_center, float lr_quat,
+                          float lr_radii, float beta1, float beta2, float eps, float r_min, float* loss,
+                          void* stream);
 
 /* adam_step_planes (Sec. 3.3): bias-corrected Adam on the K planes.
  * m, v: device [11*K] laid out as center (3K) | quat (4K) | radii (4K).

@@ -71,6 +71,9 @@ _EXPORTS = {
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
     "plane_render_fwd_loss": (C.c_int, [C.POINTER(PsLayout), _P, _P, C.c_int, _P, C.POINTER(PsParams), _P, _P, _P, _P,
                                         _P, _P, C.c_int, C.c_float, C.c_float, C.c_float, _P, _P, _P, _P]),
+    "plane_render_bwd_adam": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,
+                                        C.POINTER(PsParams), _P, _P, _P, _P, _P, _P, _P, _P, C.c_float,
+                                        C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _P, _P]),
     "plane_render_fwd_lists": (C.c_int, [C.POINTER(PsLayout), _P, _P, C.c_int, _P, C.POINTER(PsParams), _P, _P, _P,
                                          _P, _P, _P, _P]),
     "plane_render_bwd_lists": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,

@@ -27,17 +27,10 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
   if (i < 3 * a.K) { grp = 0; j = i; }
   else if (i < 7 * a.K) { grp = 1; j = i - 3 * a.K; }
   else { grp = 2; j = i - 7 * a.K; }
-  const int t = a.step[0];
-  const double bc1 = 1.0 - pow((double)a.b1, (double)t);
-  const double bc2 = 1.0 - pow((double)a.b2, (double)t);
-  const float g = a.g[grp][j];
-  const float m = a.b1 * a.m[i] + (1.f - a.b1) * g;
-  const float v = a.b2 * a.v[i] + (1.f - a.b2) * g * g;
+  float m = a.m[i], v = a.v[i];
+  float x = ps::adam_update(a.p[grp][j], a.g[grp][j], m, v, a.lr[grp], a.b1, a.b2, a.eps, a.step[0]);
   a.m[i] = m;
   a.v[i] = v;
-  const float mhat = (float)((double)m / bc1);
-  const float vhat = (float)((double)v / bc2);
-  float x = a.p[grp][j] - a.lr[grp] * mhat / (sqrtf(vhat) + a.eps);
   if (grp == 2) x = fmaxf(x, a.r_min);
   a.p[grp][j] = x;
 }

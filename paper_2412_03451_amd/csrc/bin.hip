@@ -26,7 +26,6 @@
 using namespace ps;
 
 int ps_check_ws(const ps_layout* L, const void* ws, const char* who);
-__global__ void ps_fill_i32(int32_t* p, int64_t n, int32_t v);
 
 namespace {
 
@@ -416,11 +415,7 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   a.recs_s = (Rec*)(base + L->region[R_RECS_S]);
   a.items = (ItemDesc*)(base + L->region[R_ITEMS]);
   a.tile_pos = (int*)(base + L->region[R_TILEPOS]);
-  // one fill clears the record counts, their offsets and the tile counts
-  // (adjacent regions; the gaps between them are padding)
-  static_assert(R_REC_OFF == R_REC_CNT + 1 && R_TILE_CNT == R_REC_OFF + 1, "region order");
-  const int64_t nfill = (int64_t)(L->region[R_TILE_CNT] - L->region[R_REC_CNT]) / 4 + a.T + 1;
-  hipLaunchKernelGGL(ps_fill_i32, dim3((unsigned)((nfill + 255) / 256)), dim3(256), 0, st, a.rec_cnt, nfill, 0);
+  // the record and tile counts were cleared by plane_project
   if (a.R > 0)
     hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 3) / 4, std::min(a.CH, kChunkWaves)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, a);

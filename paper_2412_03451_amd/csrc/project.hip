@@ -29,6 +29,8 @@ struct ProjArgs {
   int mode, two_sided;
   Rec* recs;
   BinRec* brecs;
+  int32_t* clear;   // the binning counts (record counts .. tile counts) to zero
+  int64_t n_clear;
 };
 
 __device__ inline void store_culled(Rec* recs, BinRec* brecs, int r, int slot) {
@@ -52,6 +54,9 @@ __device__ inline void affine(const double c[3], const ps_camera& cam, double& c
 
 __global__ __launch_bounds__(64) void project_kernel(ProjArgs a) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  // the counts tile_bin accumulates start from zero (this saves the binning a
+  // clearing launch of its own)
+  if (r < a.n_clear) a.clear[r] = 0;
   if (r >= a.R) return;
   const int s = find_slot_by_rec(a.slots, a.S, r);
   const ps_slot sl = a.slots[s];
@@ -236,9 +241,13 @@ extern "C" int plane_project(const ps_layout* L, void* ws, const float* center, 
   if (!(prm->tau > 0.f && prm->tau < 1.f) || !(prm->z_near > 0.f) || prm->M < 1 || prm->M > kMaxM ||
       (prm->weight_mode < 0 || prm->weight_mode > 2))
     return ps_set_error(PS_ERR_INVALID, "plane_project: bad ps_params");
-  if (L->n_records == 0) return PS_OK;
   char* base = (char*)ws;
   ProjArgs a;
+  // record counts, their offsets and the tile counts of tile_bin: adjacent
+  // regions (the gaps between them are padding), cleared by the same launch
+  static_assert(R_REC_OFF == R_REC_CNT + 1 && R_TILE_CNT == R_REC_OFF + 1, "region order");
+  a.clear = (int32_t*)(base + L->region[R_REC_CNT]);
+  a.n_clear = (int64_t)(L->region[R_TILE_CNT] - L->region[R_REC_CNT]) / 4 + L->n_tiles + 1;
   a.slots = (const ps_slot*)(base + L->region[R_SLOTS]);
   a.S = L->n_slots;
   a.R = L->n_records;
@@ -248,7 +257,8 @@ extern "C" int plane_project(const ps_layout* L, void* ws, const float* center, 
   a.flog = filter_log((double)prm->tau, prm->weight_mode);
   a.recs = (Rec*)(base + L->region[R_REC]);
   a.brecs = (BinRec*)(base + L->region[R_BINREC]);
-  hipLaunchKernelGGL(project_kernel, dim3((a.R + 63) / 64), dim3(64), 0, (hipStream_t)stream, a);
+  const int64_t n = a.R > a.n_clear ? (int64_t)a.R : a.n_clear;
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, (hipStream_t)stream, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }

@@ -415,6 +415,21 @@ struct LossView {
   float* gN;
 };
 
+// One parameter's bias-corrected Adam update (Sec. 3.3), step t (1-based);
+// m and v are updated in place, the new parameter is returned.  Shared by
+// adam_step_planes and the backward that applies Adam itself, so both give
+// the same bits.
+__device__ inline float adam_update(float p, float g, float& m, float& v, float lr, float b1, float b2, float eps,
+                                    int t) {
+  const double bc1 = 1.0 - pow((double)b1, (double)t);
+  const double bc2 = 1.0 - pow((double)b2, (double)t);
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  const float mhat = (float)((double)m / bc1);
+  const float vhat = (float)((double)v / bc2);
+  return p - lr * mhat / (sqrtf(vhat) + eps);
+}
+
 // float64 wave sum (the loss partials), in a fixed order
 __device__ inline double wave_sum_double(double v) {
 #pragma unroll

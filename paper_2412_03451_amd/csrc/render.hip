@@ -82,7 +82,16 @@ struct RenderArgs {
   // line each); the queue region until the launch, null in a launch of one
   // workgroup per item
   unsigned long long* queue;
+  // plane_render_bwd_adam: the loss sums of the last forward with the loss,
+  // formed by workgroups added to the per-plane reduction
+  float* loss_out;
+  const double* loss_in;
 };
+
+// LDS of the render workgroups, at namespace scope so that every access
+// compiles to an LDS instruction (a pointer or reference kept in a struct
+// would be a generic address): the staged candidates of a batch.
+__shared__ StageLds g_stage;
 
 struct ItemCtx {
   int b, e;          // list range in keys[]
@@ -96,7 +105,6 @@ struct ItemCtx {
   float du, dv;      // camera-frame ray (du, dv, 1)
   int64_t pix;       // index of the pixel in the depth array
   int64_t pix_off, HW;
-  StageLds* stage;   // LDS staging buffer of the wave
 };
 
 // 0: block inside the image; 1: block entirely outside (partial tile); 2: bad camera
@@ -192,41 +200,44 @@ struct Pending {
 
   // Keep the `cap` nearest hits (cap = hits still allowed by M, or fewer).
   // false: the buffer is full and the hit may still be among the nearest cap.
+  // Selects only, no per-lane branches: every entry is rewritten from
+  // itself, its lower neighbour or the new hit.
   __device__ bool insert(uint64_t nk, float na, bool opq, int npos, int cap) {
-    if (ok < nk) return true;                   // behind an opaque hit
-    if (n >= cap) {
-      if (n == 0 || !(nk < lk)) return true;    // not among the nearest cap
-      n -= 1;                                   // the old last entry drops out
-      ok = kNoKey;                              // an opaque hit is always the last entry
-    } else if (n == P) {
-      return false;
-    }
-    // from the top: entries above the new key move up one place, the new
-    // entry takes the first place whose lower neighbour is not above it
+    const bool full = n >= cap;
+    // dropped: behind an opaque pending hit, or not among the nearest cap
+    const bool drop = (ok < nk) || (full && (n == 0 || !(nk < lk)));
+    const bool ovf = !drop && !full && n == P;
+    const bool put = !drop && !ovf;
+    // a full buffer gives up its last entry (an opaque hit is always the last)
+    const int m = (put && full) ? n - 1 : n;
+    ok = (put && full) ? kNoKey : ok;
+    // place of the new hit: the number of entries below it (keys are unique)
     int at = 0;
-    bool placed = false;
 #pragma unroll
-    for (int i = P - 1; i >= 0; --i) {
-      if (i <= n) {
-        const bool up = i > 0 && nk < k[i - 1];
-        if (up) {
-          k[i] = k[i - 1]; a[i] = a[i - 1]; pos[i] = pos[i - 1];
-        } else if (!placed) {
-          k[i] = nk; a[i] = na; pos[i] = npos;
-          placed = true;
-          at = i;
-        }
-      }
-    }
-    n += 1;
-    if (opq) {   // everything behind an opaque hit is hidden
-      n = at + 1;
-      ok = nk;
+    for (int i = 0; i < P; ++i) at += (i < m && k[i] < nk) ? 1 : 0;
+    // entries at..m-1 move up one place (from the top, so each reads its
+    // lower neighbour before that one moves)
+#pragma unroll
+    for (int i = P - 1; i > 0; --i) {
+      const bool up = put && i > at && i <= m;
+      k[i] = up ? k[i - 1] : k[i];
+      a[i] = up ? a[i - 1] : a[i];
+      pos[i] = up ? pos[i - 1] : pos[i];
     }
 #pragma unroll
-    for (int i = 0; i < P; ++i)
-      if (i == n - 1) lk = k[i];
-    return true;
+    for (int i = 0; i < P; ++i) {
+      const bool here = put && i == at;
+      k[i] = here ? nk : k[i];
+      a[i] = here ? na : a[i];
+      pos[i] = here ? npos : pos[i];
+    }
+    n = put ? m + 1 : n;
+    // everything behind an opaque hit is hidden
+    n = (put && opq) ? at + 1 : n;
+    ok = (put && opq) ? nk : ok;
+#pragma unroll
+    for (int i = 0; i < P; ++i) lk = (put && i == n - 1) ? k[i] : lk;
+    return !ovf;
   }
 
   __device__ void pop(uint64_t& fk, float& fa, int& fpos) {
@@ -247,7 +258,7 @@ struct Pending {
 // the emit index.  Returns the mask of overlapping candidates.
 template <bool BWD>
 __device__ inline uint64_t stage_batch(const RenderArgs& a, const ItemCtx& c, int base) {
-  StageLds& S = *c.stage;
+  StageLds& S = g_stage;
   const int lane = threadIdx.x;
   const int i = base + lane;
   bool ov = false;
@@ -293,14 +304,23 @@ __device__ inline void staged(const StageLds& S, int j, RecHead& rec, float n[3]
 
 // Normal of the candidate at list position pos (relative to the item's list):
 // from the staged batch starting at list index sb when it is there, else
-// from the record copy in memory (a hit kept pending across batches).
+// from the record copy in memory (a hit kept pending across batches).  A
+// list of at most one batch is staged whole (sb = c.b): LDS only.
 __device__ inline void cand_normal(const RenderArgs& a, const ItemCtx& c, int sb, int pos, float n[3]) {
-  const int j = c.b + pos - sb;
   float4 h;
-  if (j >= 0 && j < kBatch)
-    h = c.stage->head[6][j];
-  else
-    h = reinterpret_cast<const float4*>(&a.recs_s[c.b + pos])[6];
+  if (c.e - c.b <= kBatch) {
+    h = g_stage.head[6][pos];
+  } else {
+    const int j = c.b + pos - sb;
+    const bool in = j >= 0 && j < kBatch;
+    h = g_stage.head[6][in ? j : 0];
+    if (!in) {
+      // a volatile read: kept apart from the LDS reads above (merged, both
+      // would become generic-address loads)
+      const volatile float* g = reinterpret_cast<const volatile float*>(&a.recs_s[c.b + pos]) + 24;
+      h.x = g[0]; h.y = g[1]; h.z = g[2];
+    }
+  }
   n[0] = h.x; n[1] = h.y; n[2] = h.z;
 }
 
@@ -344,7 +364,7 @@ __device__ __forceinline__ bool walk(const RenderArgs& a, const ItemCtx& c, Sink
   bool slow = (a.flags & 1) && c.inimg;
   bool done = !c.inimg || slow || sink.finished(a.M);
   uint64_t lk = 0;   // key of the last committed hit
-  StageLds& S = *c.stage;
+  StageLds& S = g_stage;
   bool stop = ballot(!done) == 0;
   for (int base = c.b; base < c.e && !stop; base += kBatch) {
     uint64_t ovm = stage_batch<Sink::BWD>(a, c, base);
@@ -507,7 +527,7 @@ __device__ void block_loss(const RenderArgs& a, const ItemCtx& c, const ps_slot&
 }
 
 template <int P, bool GAUSS>
-__device__ __forceinline__ void fwd_item(const RenderArgs& a, int item, StageLds& stage) {
+__device__ __forceinline__ void fwd_item(const RenderArgs& a, int item) {
   const bool diag = a.flags & kFlagDiag;
   const uint64_t t_start = diag ? wall_clock64() : 0;
   long long* dg = a.diag + (size_t)item * D_NUM;
@@ -527,7 +547,6 @@ __device__ __forceinline__ void fwd_item(const RenderArgs& a, int item, StageLds
     if (a.loss_part) block_loss(a, c, sl, tg, st == 2 && c.inimg, 0.f, 0.f, 0.f, 0.f);
     return;
   }
-  c.stage = &stage;
   item_priority(c.e - c.b);
   const float lam = a.lambda[0];
   const float lam5 = 5.f * lam;
@@ -596,17 +615,16 @@ __global__ void queue_reset_kernel(unsigned long long* cnt) {
 
 template <int P, bool GAUSS, bool PERSIST>
 __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
-  __shared__ StageLds stage;
   if (a.counters[C_OVERFLOW]) return;
   if (!PERSIST) {
-    fwd_item<P, GAUSS>(a, xcd_item(blockIdx.x, gridDim.x), stage);
+    fwd_item<P, GAUSS>(a, xcd_item(blockIdx.x, gridDim.x));
     return;
   }
   const int n_groups = (a.n_items + 3) >> 2;
   int stream = blockIdx.x & 7;
   for (int g = claim_group(a.queue, n_groups, stream); g >= 0; g = claim_group(a.queue, n_groups, stream)) {
     for (int item = 4 * g; item < min(4 * g + 4, a.n_items); ++item) {
-      fwd_item<P, GAUSS>(a, item, stage);
+      fwd_item<P, GAUSS>(a, item);
       __syncthreads();
     }
   }
@@ -624,6 +642,7 @@ struct BwdLds {
   int gpos[64];           // a group of candidates of the gradient pass: list positions, ascending
   uint32_t vis[kBigSort / 32];  // list positions visited by the first gradient pass (lists up to kBigSort)
 };
+__shared__ BwdLds g_bwd;
 
 // Sum 16 per-lane values over the wave by recursive halving: each exchange
 // step sends half of the values still held (permlane swaps across the wave
@@ -675,7 +694,6 @@ struct BwdSink {
   float gD, gN0, gN1, gN2;
   float lam5;
   int mode;
-  BwdLds* L;
   __device__ bool finished(int M) const { return T == 0.f || count >= M; }
   __device__ void payload(float t, const float n[3], float* pl) const {
     // explicit fma chain: the same bits whichever path commits the hit
@@ -687,12 +705,13 @@ struct BwdSink {
     const float cv = pl[0];
     const int j = count - c0;
     const int lane = threadIdx.x;
-    L->hpos[count][lane] = (int16_t)pos;
+    BwdLds& L = g_bwd;
+    L.hpos[count][lane] = (int16_t)pos;
     if (j >= 0 && j < kChunk) {
-      L->pos[j][lane] = pos;
-      L->a[j][lane] = as;
-      L->T[j][lane] = T;
-      L->cg[j][lane] = cv;
+      L.pos[j][lane] = pos;
+      L.a[j][lane] = as;
+      L.T[j][lane] = T;
+      L.cg[j][lane] = cv;
     }
     if (count == kChunk) Tb1 = T;
     if (count == 2 * kChunk) Tb2 = T;
@@ -713,11 +732,11 @@ __device__ inline void replay(const RenderArgs& a, const ItemCtx& c, BwdSink& s,
   const int lane = threadIdx.x;
   for (int j = j0; j < jmax; ++j) {
     if (j < hits) {
-      const int pos = s.L->hpos[j][lane];
+      const int pos = g_bwd.hpos[j][lane];
       RecHead rec;
       float nrm[3];
       if (one_batch) {
-        staged(*c.stage, pos, rec, nrm);
+        staged(g_stage, pos, rec, nrm);
       } else {
         const float4* src = reinterpret_cast<const float4*>(&a.recs_s[c.b + pos]);
         const float4 h0 = src[0], h1 = src[1], h2 = src[2], h3 = src[3], h4 = src[4], h5 = src[5], h6 = src[6];
@@ -752,7 +771,7 @@ __device__ inline void load_lists(const RenderArgs& a, const ItemCtx& c, BwdSink
       RecHead rec;
       float nrm[3];
       if (one_batch) {
-        staged(*c.stage, pos, rec, nrm);
+        staged(g_stage, pos, rec, nrm);
       } else {
         const float4* src = reinterpret_cast<const float4*>(&a.recs_s[c.b + pos]);
         const float4 h0 = src[0], h1 = src[1], h2 = src[2], h3 = src[3], h4 = src[4], h5 = src[5], h6 = src[6];
@@ -782,7 +801,9 @@ __device__ inline void zero_row(const RenderArgs& a, uint32_t em, int sub) {
 // its block, exactly once in the first pass (the gradient of a candidate the
 // block hits, zeros otherwise); further passes add to it.
 template <int P, bool GAUSS>
-__device__ __forceinline__ void bwd_item(const RenderArgs& a, int item, BwdLds& L, StageLds& stage) {
+__device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
+  BwdLds& L = g_bwd;
+  StageLds& stage = g_stage;
   const bool diag = a.flags & kFlagDiag;
   uint64_t tk = diag ? wall_clock64() : 0;
   unsigned long long ph[4] = {0, 0, 0, 0}, ncand = 0, ngrp = 0;
@@ -798,7 +819,6 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item, BwdLds& 
   ItemCtx c;
   const int st = item_setup(a, item, c);
   if (st == 2) return;
-  c.stage = &stage;
   const int lane = threadIdx.x;
   const int n = c.e - c.b;
   if (st == 1) {   // block outside the image (partial tile): zero rows
@@ -836,7 +856,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item, BwdLds& 
   // carries the composite of everything behind it, and its candidates get
   // their gradients.  Each hit is evaluated once after the walk.
   int hits = 0;   // hits committed by the walk
-  BwdSink s{1.f, 0, 0, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
+  BwdSink s{1.f, 0, 0, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode};
   {
     long long evals = 0, steps = 0;
     if (a.lst_pos) {
@@ -859,7 +879,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item, BwdLds& 
     if (passes > 1) {
       if (pass > 0) __threadfence_block();   // rows written by other lanes are read back below
       const float T0 = chunk == 0 ? 1.f : chunk == 1 ? s.Tb1 : chunk == 2 ? s.Tb2 : s.Tb3;
-      BwdSink r{T0, chunk * kChunk, chunk * kChunk, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode, &L};
+      BwdSink r{T0, chunk * kChunk, chunk * kChunk, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode};
       replay(a, c, r, chunk * kChunk, (chunk + 1) * kChunk, hits, one_batch, delta);
     }
     mark(1);
@@ -1014,18 +1034,16 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item, BwdLds& 
 
 template <int P, bool GAUSS, bool PERSIST>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
-  __shared__ BwdLds L;
-  __shared__ StageLds stage;
   if (a.counters[C_OVERFLOW]) return;
   if (!PERSIST) {
-    bwd_item<P, GAUSS>(a, xcd_item(blockIdx.x, gridDim.x), L, stage);
+    bwd_item<P, GAUSS>(a, xcd_item(blockIdx.x, gridDim.x));
     return;
   }
   const int n_groups = (a.n_items + 3) >> 2;
   int stream = blockIdx.x & 7;
   for (int g = claim_group(a.queue, n_groups, stream); g >= 0; g = claim_group(a.queue, n_groups, stream)) {
     for (int item = 4 * g; item < min(4 * g + 4, a.n_items); ++item) {
-      bwd_item<P, GAUSS>(a, item, L, stage);
+      bwd_item<P, GAUSS>(a, item);
       __syncthreads();
     }
   }
@@ -1043,9 +1061,44 @@ __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
 //   dL/dq = 2 (0, dL/domega) (x) q^ / |q|
 // The in-plane offsets (P_X, P_Y) enter instead of the hit point, so no sum
 // carries the (large) camera distance of the plane.
+// Loss sums of job s from the per-8x8-block partials of the forward that
+// formed the loss, by 256 threads in the order of the loss calls' own
+// reduction (1024 strided partial sums, their wave sums, the 16 wave results
+// in order): each thread plays four of those 1024, so the sums have the same
+// bits.
+__device__ void loss_sums(const RenderArgs& a, int s) {
+  __shared__ double lw[16][4];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int i0 = a.slots[s].item_begin;
+  const int i1 = (s + 1 < a.S) ? a.slots[s + 1].item_begin : a.n_items;
+  for (int vw = tid >> 6; vw < 16; vw += 4) {
+    double acc[4] = {0, 0, 0, 0};
+    for (int i = i0 + vw * 64 + lane; i < i1; i += 1024) {
+      const double4 p = *reinterpret_cast<const double4*>(a.loss_in + 4 * (size_t)i);
+      acc[0] += p.x; acc[1] += p.y; acc[2] += p.z; acc[3] += p.w;
+    }
+    for (int q = 0; q < 4; ++q) acc[q] = wave_sum_double(acc[q]);
+    if (lane == 0)
+      for (int q = 0; q < 4; ++q) lw[vw][q] = acc[q];
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double t = lw[0][tid];
+    for (int w = 1; w < 16; ++w) t += lw[w][tid];
+    a.loss_out[4 * s + tid] = (float)t;
+  }
+}
+
+template <bool LOSS>
 __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
   __shared__ float part[4][16];
-  const int k = blockIdx.x;
+  // with LOSS the first n_slots workgroups form the loss sums, one job each
+  // (placed last, they cost the 64-room batch's reduction 150 us: measured)
+  const int k = LOSS ? (int)blockIdx.x - a.S : (int)blockIdx.x;
+  if (k < 0) {
+    loss_sums(a, k + a.S);
+    return;
+  }
   if (k >= a.K) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double gp[3] = {0, 0, 0}, gw[3] = {0, 0, 0}, gr[4] = {0, 0, 0, 0};
@@ -1276,7 +1329,10 @@ static int launch_bwd(RenderArgs& a, int K, void* stream) {
     const int rc = a.mode == 2 ? launch_bwd_g<true>(a, st) : launch_bwd_g<false>(a, st);
     if (rc) return rc;
   }
-  if (K > 0) hipLaunchKernelGGL(bwd_reduce_kernel, dim3(K), dim3(256), 0, st, a);
+  if (a.loss_out)
+    hipLaunchKernelGGL(bwd_reduce_kernel<true>, dim3(K + a.S), dim3(256), 0, st, a);
+  else if (K > 0)
+    hipLaunchKernelGGL(bwd_reduce_kernel<false>, dim3(K), dim3(256), 0, st, a);
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
@@ -1319,7 +1375,7 @@ extern "C" int plane_render_fwd_loss(const ps_layout* L, void* ws, const ps_came
   RenderArgs a;
   int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, "plane_render_fwd_loss");
   if (rc) return rc;
-  if (!depth || !normal || !tgt_depth || !tgt_normal || !loss || !g_depth || !g_normal || (tgt_off && n_tgt <= 0))
+  if (!depth || !normal || !tgt_depth || !tgt_normal || !g_depth || !g_normal || (tgt_off && n_tgt <= 0))
     return ps_set_error(PS_ERR_INVALID, "plane_render_fwd_loss: bad argument");
   a.depth = depth;
   a.normal = normal;
@@ -1330,7 +1386,8 @@ extern "C" int plane_render_fwd_loss(const ps_layout* L, void* ws, const ps_came
   a.loss_part = (double*)((char*)ws + L->region[R_LOSS]);
   rc = launch_fwd(a, stream);
   if (rc) return rc;
-  return ps_loss_reduce(L, ws, loss, stream);
+  // without loss the per-block partials stay for plane_render_bwd_adam
+  return loss ? ps_loss_reduce(L, ws, loss, stream) : PS_OK;
 }
 
 extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const float* quat,
@@ -1343,6 +1400,29 @@ extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* cente
                     g_radii, a, "plane_render_bwd");
   if (rc) return rc;
   return launch_bwd(a, K, stream);
+}
+
+extern "C" int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
+                                     const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm,
+                                     const float* g_depth, const float* g_normal, float* g_center, float* g_quat,
+                                     float* g_radii, float* m, float* v, const int32_t* step, float lr_center,
+                                     float lr_quat, float lr_radii, float beta1, float beta2, float eps, float r_min,
+                                     float* loss, void* stream) {
+  RenderArgs a;
+  int rc = bwd_args(L, ws, center, quat, radii, K, cams, n_cams, lambda, prm, g_depth, g_normal, g_center, g_quat,
+                    g_radii, a, "plane_render_bwd_adam");
+  if (rc) return rc;
+  if (K > 0 && (!m || !v || !step)) return ps_set_error(PS_ERR_INVALID, "plane_render_bwd_adam: null Adam state");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return ps_set_error(PS_ERR_INVALID, "plane_render_bwd_adam: bad beta / eps");
+  if (loss) {
+    a.loss_out = loss;
+    a.loss_in = (const double*)((char*)ws + L->region[R_LOSS]);
+  }
+  rc = launch_bwd(a, K, stream);
+  if (rc || K == 0) return rc;
+  return adam_step_planes(center, quat, radii, g_center, g_quat, g_radii, m, v, K, step, lr_center, lr_quat, lr_radii,
+                          beta1, beta2, eps, r_min, stream);
 }
 
 extern "C" int plane_render_fwd_lists(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,

@@ -207,10 +207,21 @@ class BatchFit:
         m()
         rend.bin(check_capacity=False)
         m()
-        # forward and render loss in one pass (plane_render_fwd_loss)
+        fused = not cfg.single_radii and not cfg.split_every
+        # forward and render loss in one pass (plane_render_fwd_loss); in the
+        # plain step the loss sums and Adam ride on the backward's launches
+        # (plane_render_bwd_adam)
         D, N, loss, gD, gN = rend.forward_loss(self.tgt_depth, self.tgt_normal, self.tgt_off, mask=self.mask,
-                                               a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2])
+                                               a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2],
+                                               reduce=not fused)
         m()
+        if fused:
+            loss = torch.empty(len(rend.jobs), 4, dtype=torch.float32, device=self.device)
+            rend.backward_adam(self.c, self.q, self.r, self.lam, gD, gN, self.m, self.v, self.step_no, lr=cfg.lr,
+                               betas=cfg.betas, eps=cfg.eps, r_min=cfg.r_min, loss=loss)
+            m()
+            m()
+            return loss
         gc, gq, gr = rend.backward(self.c, self.q, self.r, self.lam, gD, gN)
         if cfg.single_radii:
             tie_radii(gr)

@@ -238,10 +238,13 @@ class Renderer:
                                              _stream()))
         return loss, gD, gN
 
-    def forward_loss(self, tgt_depth, tgt_normal, tgt_off=None, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0):
+    def forward_loss(self, tgt_depth, tgt_normal, tgt_off=None, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0,
+                     reduce: bool = True):
         """Forward that forms the render loss as it composites
         (plane_render_fwd_loss): depth, normal, loss [jobs, 4], g_depth,
-        g_normal, the bits of forward() followed by loss_cam() / loss()."""
+        g_normal, the bits of forward() followed by loss_cam() / loss().
+        With reduce=False loss is None: the per-block partial sums stay in the
+        workspace for backward_adam(loss=...)."""
         P = self.n_pixels
         depth = torch.empty(P, dtype=torch.float32, device=self.device)
         normal = torch.empty(3 * P, dtype=torch.float32, device=self.device)
@@ -254,8 +257,8 @@ class Renderer:
         check(self.lib.plane_render_fwd_loss(C.byref(self.L), _ptr(self.ws), _ptr(self.cams), self.n_cams, _ptr(lam),
                                              C.byref(prm), _ptr(depth), _ptr(normal), _ptr(tgt_depth),
                                              _ptr(tgt_normal), _ptr(mask), _ptr(tgt_off), n_tgt, a_cos, a_nl1, a_d,
-                                             _ptr(loss), _ptr(gD), _ptr(gN), _stream()))
-        return depth, normal, loss, gD, gN
+                                             _ptr(loss if reduce else None), _ptr(gD), _ptr(gN), _stream()))
+        return depth, normal, (loss if reduce else None), gD, gN
 
     def backward(self, center, quat, radii, lam, g_depth, g_normal, diagnostics: bool = False):
         K = int(center.shape[0])
@@ -269,6 +272,24 @@ class Renderer:
                                         _ptr(self.cams), self.n_cams, _ptr(lam), C.byref(prm),
                                         _ptr(g_depth.contiguous()), _ptr(g_normal.contiguous()),
                                         _ptr(gc), _ptr(gq), _ptr(gr), _stream()))
+        return gc, gq, gr
+
+    def backward_adam(self, center, quat, radii, lam, g_depth, g_normal, m, v, step, lr=(1e-3, 1e-3, 1e-3),
+                      betas=(0.9, 0.999), eps=1e-8, r_min=1e-4, loss=None):
+        """backward() followed by adam_step_planes in the same launches
+        (plane_render_bwd_adam): center, quat, radii, m and v are updated in
+        place, the gradients returned; with loss ([jobs, 4] float32 device)
+        also the loss sums of the last forward_loss(reduce=False)."""
+        K = int(center.shape[0])
+        gc = torch.empty(K, 3, dtype=torch.float32, device=self.device)
+        gq = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        gr = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        prm = self.params.c()
+        check(self.lib.plane_render_bwd_adam(C.byref(self.L), _ptr(self.ws), _ptr(center), _ptr(quat), _ptr(radii), K,
+                                             _ptr(self.cams), self.n_cams, _ptr(lam), C.byref(prm),
+                                             _ptr(g_depth.contiguous()), _ptr(g_normal.contiguous()), _ptr(gc),
+                                             _ptr(gq), _ptr(gr), _ptr(m), _ptr(v), _ptr(step), lr[0], lr[1], lr[2],
+                                             betas[0], betas[1], eps, r_min, _ptr(loss), _stream()))
         return gc, gq, gr
 
     def counters(self):

@@ -231,48 +231,63 @@ MI355X_BF16_DENSE_TFLOPS = 2500.0
 
 
 def initnet_bench(args):
-    """The learned initializer's network on a batch of 4096 planes x 128
-    depth samples (P = 1): forward (fused point layers on MFMA + head) and
-    backward, timed with events over --steps repetitions.  Algorithmic MFMA
-    work of the forward: 2 x 128 x 256 x 256 x 2 flops per 128 points."""
+    """The learned initializer's training step in its per-view form: a batch
+    of 32 views, 4096 back-projected depth samples each, 256 proposals per
+    view (width 256, bfloat16 MFMA, float32 accumulation), ~30 target planes
+    per view.  Forward (fused point layers on MFMA + head), set loss,
+    backward and Adam timed with events over --steps repetitions.
+    Algorithmic MFMA work of the forward: 2 x 256 x 256 x 2 flops per point
+    (layers 2 and 3)."""
     import torch
     from paper_2412_03451_amd.initnet import InitNet
-    B, N = 4096, 128
+    B, N, P, T = 32, 4096, 256, 30
     rng = np.random.default_rng(0)
-    X = torch.tensor(np.stack([rng.uniform(-0.5, 0.5, (B, N)), rng.uniform(-0.5, 0.5, (B, N)),
-                               rng.normal(scale=0.05, size=(B, N))], -1).astype(np.float32), device="cuda")
-    net = InitNet(1, seed=0)
-    d_out = torch.tensor(rng.normal(size=(B, 12)).astype(np.float32), device="cuda")
+    # points of a view: a box room seen from inside (camera frame, z forward)
+    X = np.stack([rng.uniform(-2, 2, (B, N)), rng.uniform(-1.5, 1.5, (B, N)), rng.uniform(0.5, 5.0, (B, N))], -1)
+    X = torch.tensor(X.astype(np.float32), device="cuda")
+    q = rng.normal(size=(B * T, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    tgt = np.concatenate([rng.uniform(-2, 2, (B * T, 3)), q, rng.uniform(0.05, 1.0, (B * T, 4))], 1)
+    tgt = torch.tensor(tgt.astype(np.float32), device="cuda")
+    off = torch.tensor(np.arange(B + 1, dtype=np.int32) * T, device="cuda")
+    net = InitNet(P, seed=0)
     for _ in range(3):
         g, arg, out = net.forward(X)
-        net.backward(X, g, arg, d_out)
+        loss, d_out = net.set_loss(out, tgt, off)
+        net.adam_step(net.backward(X, g, arg, d_out))
     st = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    names = ("fwd", "set_loss", "bwd", "adam")
+    acc = {n: 0.0 for n in names}
     torch.cuda.synchronize()
-    ev[0].record(st)
+    t0 = time.perf_counter()
     for _ in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(st)
         g, arg, out = net.forward(X)
-    ev[1].record(st)
-    for _ in range(args.steps):
-        net.backward(X, g, arg, d_out)
-    ev[2].record(st)
-    torch.cuda.synchronize()
-    fwd_ms = ev[0].elapsed_time(ev[1]) / args.steps
-    bwd_ms = ev[1].elapsed_time(ev[2]) / args.steps
-    fwd_flops = (B * N // 128) * 2 * 128 * 256 * 256 * 2
-    # backward MFMA work: dW2 (256 x B*256 x 256) and dh1 (B*256 x 256 x 256), plus the recomputed layer 2
-    bwd_flops = 3 * (B * 256) * 256 * 256 * 2
-    ach = fwd_flops / (fwd_ms * 1e-3) / 1e12
+        ev[1].record(st)
+        loss, d_out = net.set_loss(out, tgt, off)
+        ev[2].record(st)
+        grad = net.backward(X, g, arg, d_out)
+        ev[3].record(st)
+        net.adam_step(grad)
+        ev[4].record(st)
+        torch.cuda.synchronize()
+        for i, n in enumerate(names):
+            acc[n] += ev[i].elapsed_time(ev[i + 1])
+    wall = (time.perf_counter() - t0) / args.steps * 1e3
+    ms = {n: acc[n] / args.steps for n in names}
+    fwd_flops = B * N * 2 * 256 * 256 * 2
+    ach = fwd_flops / (ms["fwd"] * 1e-3) / 1e12
+    step_ms = sum(ms.values())
     return {
-        "metric": "learned-initializer network throughput", "value": round(B * N / (fwd_ms * 1e-3) / 1e6, 1),
-        "unit": "Mpoints/s (forward)", "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
+        "metric": "learned-initializer training step", "value": round(B / (step_ms * 1e-3), 1),
+        "unit": "views/s", "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
         "dtype": "bf16 (f32 accumulate)", "data": "synthetic",
-        "config": {"workload": f"{B} planes x {N} depth samples, width 256, P=1"},
-        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+        "config": {"workload": f"{B} views x {N} depth samples, width 256, {P} proposals per view, {T} targets per view"},
+        "ms": {n: round(x, 4) for n, x in ms.items()}, "step_ms": round(step_ms, 4), "wall_ms_per_step": round(wall, 4),
         "roofline": {"kernel": "initnet fwd_kernel + head_kernel", "bound": "mfma", "achieved": round(ach, 2),
                      "peak": MI355X_BF16_DENSE_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(ach / MI355X_BF16_DENSE_TFLOPS, 4)},
-        "backward_tflops": round(bwd_flops / (bwd_ms * 1e-3) / 1e12, 2),
     }
 
 

@@ -231,7 +231,10 @@ struct HeadArgs {
 };
 
 // Maximum over the tiles (the earlier tile wins ties: smaller point index),
-// then out = g Wh + bh.  One workgroup per view.
+// then out = g Wh + bh.  One workgroup per (view, block of 256 outputs):
+// each recomputes its view's maximum (32 KB of tile maxima at 4096 points)
+// and the first block of the view stores it; a thread forms one output,
+// the 256 terms in order.
 __global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
   __shared__ float gs[C];
   const int b = blockIdx.x, c = threadIdx.x;
@@ -245,17 +248,19 @@ __global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
       bi = a.pi[o];
     }
   }
-  a.g[b * C + c] = best;
-  a.arg[b * C + c] = bi;
+  if (blockIdx.y == 0) {
+    a.g[b * C + c] = best;
+    a.arg[b * C + c] = bi;
+  }
   gs[c] = best;
   __syncthreads();
-  const uint16_t* Wh = a.packed + a.po.Wh;
-  const float* bh = a.master + a.o.bh;
-  for (int j = c; j < a.P12; j += 256) {
-    float acc = bh[j];
-    for (int k = 0; k < C; ++k) acc = fmaf(gs[k], bf2f(Wh[(size_t)k * a.P12 + j]), acc);
-    a.out[(size_t)b * a.P12 + j] = acc;
-  }
+  const int j = blockIdx.y * 256 + c;
+  if (j >= a.P12) return;
+  const uint16_t* Wh = a.packed + a.po.Wh + j;
+  float acc = a.master[a.o.bh + j];
+#pragma unroll 8
+  for (int k = 0; k < C; ++k) acc = fmaf(gs[k], bf2f(Wh[(size_t)k * a.P12]), acc);
+  a.out[(size_t)b * a.P12 + j] = acc;
 }
 
 // ---------------------------------------------------------------- set loss
@@ -418,6 +423,7 @@ struct BwdArgs {
   const float* master;
   const uint16_t* packed;
   int B, N, P12, R;
+  int nzh;            // blocks of 256 head outputs (parts of dL/dg)
   Offs o;
   POffs po;
   const float* X;
@@ -426,7 +432,7 @@ struct BwdArgs {
   const float* d_out;
   float* grad;
   // workspace
-  float* dg;          // [B][C]
+  float* dg;          // [B][nzh][C]  parts of dL/dg
   uint16_t* h1T;      // [C][R]
   uint16_t* h1r;      // [R][C]
   uint16_t* dp2;      // [R][C]  dL/dpre2, bfloat16
@@ -436,36 +442,37 @@ struct BwdArgs {
   float* dp3;         // [R]
   float* dh1;         // [R][C]
   float* pw2;         // [parts][C][C] split-K partials of dW2
-  float* colp;        // [R / 256][5][C]
+  float* colp;        // [R / kColChunk][5][C]
 };
 
-// dg[b][c] = sum_j Wh[c][j] d_out[b][j]
+// dg[b][c] = sum_j Wh[c][j] d_out[b][j], in parts: workgroup (b, z) sums
+// the head outputs j of block z (256 of them, in order) into
+// dgp[b][z][c]; rows_kernel adds the parts in order.
 __global__ __launch_bounds__(256) void head_dg_kernel(BwdArgs a) {
-  const int b = blockIdx.x, c = threadIdx.x;
+  const int b = blockIdx.x, z = blockIdx.y, c = threadIdx.x;
   const uint16_t* Wht = a.packed + a.po.Wht;
   const float* d = a.d_out + (size_t)b * a.P12;
+  const int j1 = min(a.P12, 256 * z + 256);
   float acc = 0.f;
-  for (int j = 0; j < a.P12; ++j) acc = fmaf(bf2f(Wht[(size_t)j * C + c]), d[j], acc);
-  a.dg[b * C + c] = acc;
+#pragma unroll 8
+  for (int j = 256 * z; j < j1; ++j) acc = fmaf(bf2f(Wht[(size_t)j * C + c]), d[j], acc);
+  a.dg[((size_t)b * a.nzh + z) * C + c] = acc;
 }
 
 // dWh[c][j] = sum_b g[b][c] d_out[b][j] (c < C) and dbh[j] = sum_b d_out[b][j]
-// (c = C): one wave per output, lanes over the views, fixed-order reduction.
+// (c = C): one thread per output, the views in order.
 __global__ __launch_bounds__(256) void head_dw_kernel(BwdArgs a) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int n_out = (C + 1) * a.P12;
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n_out = (int64_t)(C + 1) * a.P12;
   if (w >= n_out) return;
-  const int c = w / a.P12, j = w % a.P12;
+  const int c = (int)(w / a.P12), j = (int)(w % a.P12);
   float acc = 0.f;
-  for (int b = lane; b < a.B; b += 64) {
+  for (int b = 0; b < a.B; ++b) {
     const float d = a.d_out[(size_t)b * a.P12 + j];
     acc = c < C ? fmaf(a.g[b * C + c], d, acc) : acc + d;
   }
-  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (lane == 0) {
-    if (c < C) a.grad[a.o.Wh + (size_t)c * a.P12 + j] = acc;
-    else a.grad[a.o.bh + j] = acc;
-  }
+  if (c < C) a.grad[a.o.Wh + (size_t)c * a.P12 + j] = acc;
+  else a.grad[a.o.bh + j] = acc;
 }
 
 // Rows r = b * C + c (the point attaining channel c of view b): recompute h1,
@@ -524,7 +531,9 @@ __global__ __launch_bounds__(512) void rows_kernel(BwdArgs a) {
     s += __shfl_xor(s, 2, 64);
     if (part == 0) {
       const float pre3 = s + a.master[a.o.b3 + ch];
-      const float d = pre3 > 0.f ? a.dg[(r / C) * C + ch] : 0.f;
+      float dgr = 0.f;   // dL/dg of (view, channel): its parts in order
+      for (int z = 0; z < a.nzh; ++z) dgr += a.dg[((size_t)(r / C) * a.nzh + z) * C + ch];
+      const float d = pre3 > 0.f ? dgr : 0.f;
       d3[m] = d;
       a.dp3[r] = d;
     }
@@ -590,7 +599,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         Cz[(size_t)(m0 + 32 * i + acc_row(v, l)) * g.ldc + n0 + 32 * j + acc_col(l)] = acc[i][j][v];
 }
 
-constexpr int kColChunk = 1024;   // rows per column-sum chunk
+constexpr int kColChunk = 64;   // rows per column-sum chunk (enough chunks to fill the chip)
 
 // Column sums over a chunk of rows (thread = column): dW1 (3), db1, db2.
 __global__ __launch_bounds__(256) void colpart_kernel(BwdArgs a) {
@@ -702,11 +711,11 @@ inline int wgrad_parts(int64_t R) {
 struct BwdWs {
   int64_t dg, h1T, h1r, dp2, dp2T, dp2f, h2r, dp3, dh1, pw2, colp, n;
 };
-inline BwdWs bwd_ws(int B) {
+inline BwdWs bwd_ws(int B, int P) {
   const int64_t R = (int64_t)B * C;
   BwdWs w;
   int64_t o = 0;
-  w.dg = o; o += ws_align(R);
+  w.dg = o; o += ws_align(R * ((IN_OUT * P + 255) / 256));
   w.h1T = o; o += ws_align(R * C / 2);
   w.h1r = o; o += ws_align(R * C / 2);
   w.dp2 = o; o += ws_align(R * C / 2);
@@ -731,7 +740,7 @@ extern "C" int64_t initnet_forward_ws(int B, int N) {
 }
 extern "C" int64_t initnet_backward_ws(int B, int P) {
   if (B < 2 || B % 2 || P < 1 || P > IN_PMAX) return 0;
-  return bwd_ws(B).n;
+  return bwd_ws(B, P).n;
 }
 
 static int check_p(int P, const char* who) {
@@ -771,7 +780,7 @@ extern "C" int initnet_forward(const float* master, const uint16_t* packed, int 
   HeadArgs h;
   h.master = master; h.packed = packed; h.B = B; h.P12 = IN_OUT * P; h.ntile = a.ntile;
   h.o = a.o; h.po = a.po; h.pv = a.pv; h.pi = a.pi; h.g = g; h.arg = arg; h.out = out;
-  hipLaunchKernelGGL(head_kernel, dim3(B), dim3(256), 0, st, h);
+  hipLaunchKernelGGL(head_kernel, dim3(B, (h.P12 + 255) / 256), dim3(256), 0, st, h);
   IN_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
@@ -796,9 +805,10 @@ extern "C" int initnet_backward(const float* master, const uint16_t* packed, int
   if (B < 2 || B % 2 || N < 1) return ps_set_error(PS_ERR_INVALID, "initnet_backward: B=%d must be even and >= 2", B);
   if (((uintptr_t)ws) & 255) return ps_set_error(PS_ERR_INVALID, "initnet_backward: workspace not 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
-  const BwdWs w = bwd_ws(B);
+  const BwdWs w = bwd_ws(B, P);
   BwdArgs a;
   a.master = master; a.packed = packed; a.B = B; a.N = N; a.P12 = IN_OUT * P; a.R = B * C;
+  a.nzh = (a.P12 + 255) / 256;
   a.o = param_offs(P); a.po = packed_offs(P);
   a.X = X; a.g = g; a.arg = arg; a.d_out = d_out; a.grad = grad;
   a.dg = ws + w.dg;
@@ -813,8 +823,8 @@ extern "C" int initnet_backward(const float* master, const uint16_t* packed, int
   a.pw2 = ws + w.pw2;
   a.colp = ws + w.colp;
   const int R = a.R;
-  hipLaunchKernelGGL(head_dg_kernel, dim3(B), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(head_dw_kernel, dim3(((C + 1) * a.P12 + 3) / 4), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(head_dg_kernel, dim3(B, a.nzh), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(head_dw_kernel, dim3((unsigned)(((int64_t)(C + 1) * a.P12 + 255) / 256)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(rows_kernel, dim3(R / TM), dim3(512), 0, st, a);
   // dW2 partials: [k1][k2] = sum_r h1T[k1][r] dp2T[k2][r], split over row chunks
   const int nz = wgrad_parts(R);

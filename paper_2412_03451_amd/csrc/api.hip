@@ -100,6 +100,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
       4 * (T + 1),                     // R_TILEPOS
       4 * (R * (size_t)max_chunks + 1),  // R_CHUNK_CNT
       8 * 2 * 8 * 16,                  // R_QUEUE
+      4 * (size_t)ps::scan_words(T, R),  // R_SCAN
   };
   size_t off = 0;
   for (int i = 0; i < PS_NUM_REGIONS; ++i) {
@@ -143,6 +144,9 @@ extern "C" int ps_workspace_init(const ps_layout* L, const ps_slot* slots, void*
   const int64_t nq = 2 * 2 * 8 * 16;  // work-queue counters as int32 words
   hipLaunchKernelGGL(ps_fill_i32, dim3((nq + 255) / 256), dim3(256), 0, st,
                      (int32_t*)(base + L->region[ps::R_QUEUE]), nq, 0);
+  const int64_t ns = ps::scan_words(L->n_tiles, L->n_records);
+  hipLaunchKernelGGL(ps_fill_i32, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st,
+                     (int32_t*)(base + L->region[ps::R_SCAN]), ns, 0);
   const int64_t nd = 2 * (int64_t)ps::D_NUM * (L->n_items + 1);  // statistics as int32 words
   hipLaunchKernelGGL(ps_fill_i32, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st,
                      (int32_t*)(base + L->region[ps::R_DIAG]), nd, 0);

@@ -3,9 +3,13 @@
 //   count  (one wave per record): tiles of the record's footprint that pass
 //          a separating-axis test against the projected grown rectangle and
 //          have a hit in front of the camera; per-tile counts by atomics.
-//   scan   (one 1024-thread workgroup): exclusive prefix sums of the per-tile
-//          and per-record counts with wave64 shuffles plus one LDS pass per
-//          4096-element block; capacity and per-tile limits are checked here.
+//   scan   (1024-thread workgroups, one per 4096 tiles and 4096 records):
+//          exclusive prefix sums of the chunk's tile and record counts with
+//          wave64 shuffles plus one LDS pass, and the chunk's list-length
+//          histogram; the last workgroup to finish scans the chunk totals
+//          (the chunk bases, which the later passes add to the chunk-local
+//          offsets), turns the histogram into the render items' bucket
+//          starts, and checks capacity and per-tile limits.
 //   emit   (one wave per record): key = (depth bound bits << 32 | record),
 //          value = emit index (record-major), scattered into tile segments.
 //   sort   (one workgroup per tile): bitonic sort of the tile's keys in LDS;
@@ -51,6 +55,13 @@ struct BinArgs {
   Rec* recs_s;        // record copies in sorted order
   ItemDesc* items;
   int* tile_pos;      // first render item of each tile
+  int G;              // scan chunks
+  int* tbase;         // [G] tile-offset base of each chunk
+  int* rbase;         // [G] record-offset base of each chunk
+  int* chist;         // [G][kBuckets] render items of each chunk per list-length bucket, then the
+                      // chunk's first item position in each bucket
+  int* btot;          // [kBuckets] render items per bucket
+  int* misc;          // [0] workgroups done, [1] big tiles, [2] largest tile list (zero between calls)
 };
 
 template <bool KEY>
@@ -127,33 +138,124 @@ __global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
   if (lane == 0 && total) atomicAdd(&a.rec_cnt[r], total);
 }
 
+// Exclusive scan of in[0, n) by one 1024-thread workgroup (n <= 4096):
+// chunk-local offsets; returns the total and the maximum.
+__device__ inline int chunk_scan(const int* __restrict__ in, int* __restrict__ out, int n, int* lds, int& mx) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int v[4];
+  int local = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int idx = tid * 4 + j;
+    v[j] = idx < n ? in[idx] : 0;
+    mx = max(mx, v[j]);
+    local += v[j];
+  }
+  int incl = local;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) lds[wid] = incl;
+  __syncthreads();
+  if (wid == 0) {
+    const int x = lane < 16 ? lds[lane] : 0;
+    int xi = x;
+    for (int o = 1; o < 16; o <<= 1) {
+      const int y = __shfl_up(xi, o, 64);
+      if (lane >= o) xi += y;
+    }
+    if (lane < 16) lds[16 + lane] = xi - x;
+    if (lane == 15) lds[32] = xi;
+  }
+  __syncthreads();
+  int run = lds[16 + wid] + (incl - local);
+  for (int j = 0; j < 4; ++j) {
+    const int idx = tid * 4 + j;
+    if (idx < n) out[idx] = run;
+    run += v[j];
+  }
+  const int total = lds[32];
+  __syncthreads();
+  return total;
+}
+
 __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   __shared__ int lds[40];
   __shared__ int hist[kBuckets];
+  __shared__ int last;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int t0 = g * kScanChunk, r0 = g * kScanChunk;
+  const int nt = max(0, min(kScanChunk, a.T - t0)), nr = max(0, min(kScanChunk, a.R - r0));
+  for (int k = tid; k < kBuckets; k += blockDim.x) hist[k] = 0;
   int mx_t = 0, mx_r = 0;
-  const long long total = block_scan(a.tile_cnt, a.tile_off, a.T, lds, mx_t);
-  block_scan(a.rec_cnt, a.rec_off, a.R, lds, mx_r);
-  // Items per list-length bucket, then the first position of each bucket
-  // with the longest lists first.  The loops run over the jobs' tile ranges
-  // (a job's tiles are contiguous), so no tile searches for its job.
-  __shared__ int nbig;
-  for (int k = threadIdx.x; k < kBuckets; k += blockDim.x) hist[k] = 0;
-  if (threadIdx.x == 0) nbig = 0;
-  __syncthreads();
-  for (int s = 0; s < a.S; ++s) {
-    const ps_slot& sl = a.slots[s];
-    const int tb = sl.tile_begin, nt = sl.tiles_x * sl.tiles_y;
+  const int tot_t = chunk_scan(a.tile_cnt + t0, a.tile_off + t0, nt, lds, mx_t);
+  const int tot_r = chunk_scan(a.rec_cnt + r0, a.rec_off + r0, nr, lds, mx_r);
+  // the chunk's render items per list-length bucket: each tile's items take
+  // consecutive positions in its bucket after those of the chunk's earlier
+  // claims (tile_pos holds the position inside the chunk's share of the
+  // bucket; the order of tiles inside a bucket does not matter: items are
+  // independent); bin_emit's scatter cursors
+  for (int t = t0 + tid; t < t0 + nt; t += blockDim.x) {
+    const ps_slot& sl = a.slots[find_slot_by_tile(a.slots, a.S, t)];
     const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
-    for (int t = tb + threadIdx.x; t < tb + nt; t += blockDim.x) {
-      const int c = a.tile_cnt[t];
-      atomicAdd(&hist[length_bucket(c)], sub_per);
-      a.tile_cur[t] = 0;   // scatter cursors of bin_emit
-      if (c > kSmallSort && c <= kMaxList) a.bigtiles[atomicAdd(&nbig, 1)] = t;
+    const int c = a.tile_cnt[t];
+    a.tile_pos[t] = atomicAdd(&hist[length_bucket(c)], sub_per);
+    a.tile_cur[t] = 0;
+    if (c > kSmallSort && c <= kMaxList) a.bigtiles[atomicAdd(&a.misc[1], 1)] = t;
+  }
+  for (int w = 64; w > 1; w >>= 1) mx_t = max(mx_t, __shfl_xor(mx_t, w >> 1, 64));
+  __syncthreads();
+  for (int k = tid; k < kBuckets; k += blockDim.x) a.chist[(size_t)g * kBuckets + k] = hist[k];
+  if ((tid & 63) == 0 && mx_t) atomicMax(&a.misc[2], mx_t);
+  if (tid == 0) {
+    a.tbase[g] = tot_t;
+    a.rbase[g] = tot_r;
+  }
+  // the last workgroup to finish combines the chunks (a single workgroup is
+  // the last: no device-scope fence, which writes back the L2 of the XCD)
+  if (gridDim.x > 1) {
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(&a.misc[0], 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+  } else {
+    __syncthreads();
+  }
+  long long total = 0;
+  if (tid == 0) {   // chunk bases (a few hundred chunks at most: in order on one thread)
+    long long tb = 0, rb = 0;
+    for (int k = 0; k < a.G; ++k) {
+      const int ct = __hip_atomic_load(&a.tbase[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int cr = __hip_atomic_load(&a.rbase[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.tbase[k] = (int)tb;
+      a.rbase[k] = (int)rb;
+      tb += ct;
+      rb += cr;
     }
+    lds[34] = (int)(tb >> 31);   // pairs beyond int range: flagged as overflow below
+    lds[35] = (int)(tb & 0x7fffffff);
+    // the totals after the last entries (the offsets before them stay chunk-local)
+    a.tile_off[a.T] = (int)tb;
+    a.rec_off[a.R] = (int)rb;
+  }
+  // items per bucket over the chunks; each chunk's counts become its start
+  // inside the bucket (chunks in order)
+  for (int k = tid; k < kBuckets; k += blockDim.x) {
+    int run = 0;
+    for (int c = 0; c < a.G; ++c) {
+      int* h = &a.chist[(size_t)c * kBuckets + k];
+      const int v = __hip_atomic_load(h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *h = run;
+      run += v;
+    }
+    hist[k] = run;
   }
   __syncthreads();
-  if (threadIdx.x < 64) {   // exclusive scan over buckets, longest first: 16 buckets per lane
-    const int lane = threadIdx.x;
+  total = ((long long)lds[34] << 31) | lds[35];
+  if (tid < 64) {   // exclusive scan over buckets, longest first: 16 buckets per lane
+    const int lane = tid;
     int loc = 0;
     for (int i = 0; i < 16; ++i) loc += hist[kBuckets - 1 - (16 * lane + i)];
     int incl = loc;
@@ -165,26 +267,20 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
     for (int i = 0; i < 16; ++i) {
       const int k = kBuckets - 1 - (16 * lane + i);
       const int h = hist[k];
-      hist[k] = run;
+      a.btot[k] = run;   // first item position of the bucket
       run += h;
     }
   }
-  __syncthreads();
-  // each tile's items take consecutive positions in their bucket (the order
-  // of tiles inside a bucket does not matter: items are independent)
-  for (int s = 0; s < a.S; ++s) {
-    const ps_slot& sl = a.slots[s];
-    const int tb = sl.tile_begin, nt = sl.tiles_x * sl.tiles_y;
-    const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
-    for (int t = tb + threadIdx.x; t < tb + nt; t += blockDim.x)
-      a.tile_pos[t] = atomicAdd(&hist[length_bucket(a.tile_cnt[t])], sub_per);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
+    const int mx = __hip_atomic_load(&a.misc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int nbig = __hip_atomic_load(&a.misc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a.misc[0] = 0;
+    a.misc[1] = 0;
+    a.misc[2] = 0;
     a.counters[C_PAIRS] = total;
-    a.counters[C_MAXTILE] = mx_t;
+    a.counters[C_MAXTILE] = mx;
     a.counters[C_NBIG] = nbig;
-    a.counters[C_OVERFLOW] = (total > a.capacity || mx_t > kMaxList) ? 1 : 0;
+    a.counters[C_OVERFLOW] = (total > a.capacity || mx > kMaxList) ? 1 : 0;
     if (a.counters[C_OVERFLOW]) a.counters[C_STICKY] = 1;
     a.counters[C_SLOW] = 0;
     a.counters[C_BWD_PASSES] = 0;
@@ -209,7 +305,7 @@ __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
   const Rec& rec = a.recs[r];
   const ps_slot& sl = a.slots[br.slot];
   const int* cc = a.chunk_cnt + (size_t)r * a.CH;
-  int j = a.rec_off[r];
+  int j = a.rec_off[r] + a.rbase[r / kScanChunk];
   int done = 0;   // groups counted into j
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int ch = blockIdx.y; ch * 64 < n; ch += gridDim.y) {
@@ -226,7 +322,7 @@ __global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
     const uint64_t m = ballot(pass);
     if (pass) {
       const int gt = sl.tile_begin + ty * sl.tiles_x + tx;
-      const int slot = a.tile_off[gt] + atomicAdd(&a.tile_cur[gt], 1);
+      const int slot = a.tile_off[gt] + a.tbase[gt / kScanChunk] + atomicAdd(&a.tile_cur[gt], 1);
       a.keys_u[slot] = ((uint64_t)__float_as_uint(kt) << 32) | (uint32_t)r;
       a.emit_u[slot] = (uint32_t)(j + __popcll(m & below));
     }
@@ -276,18 +372,27 @@ __device__ void lds_bitonic(uint64_t* k, uint32_t* v, int n, const uint64_t* __r
 __global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
   __shared__ uint64_t k[kSmallSort];
   __shared__ uint32_t v[kSmallSort];
+  __shared__ int pos0;
   const int t = blockIdx.x;
   const int n = a.tile_cnt[t];
-  const int off = a.tile_off[t];
+  const int off = a.tile_off[t] + a.tbase[t / kScanChunk];   // chunk-local offset + chunk base
+  const int s = find_slot_by_tile(a.slots, a.S, t);
+  const ps_slot& sl = a.slots[s];
+  const int sub_w = sl.tile_w >> 3;
+  const int sub_per = sub_w * (sl.tile_h >> 3);
+  // the tile's first render item: its bucket's start + its chunk's start in
+  // the bucket + its place among the chunk's tiles of the bucket
+  if (threadIdx.x == 0) {
+    const int k = length_bucket(n);
+    pos0 = a.btot[k] + a.chist[(size_t)(t / kScanChunk) * kBuckets + k] + a.tile_pos[t];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.tile_off[t] = off;   // final offset, for bin_sort_big
   // render items (8x8 blocks) of this tile, placed by list length
   if (threadIdx.x < 16) {
-    const int s = find_slot_by_tile(a.slots, a.S, t);
-    const ps_slot& sl = a.slots[s];
-    const int sub_w = sl.tile_w >> 3;
-    const int sub_per = sub_w * (sl.tile_h >> 3);
     const int sub = threadIdx.x;
     if (sub < sub_per) {
-      const int pos = a.tile_pos[t] + sub;
+      const int pos = pos0 + sub;
       const int lt = t - sl.tile_begin;
       ItemDesc d;
       d.b = off;
@@ -415,10 +520,16 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   a.recs_s = (Rec*)(base + L->region[R_RECS_S]);
   a.items = (ItemDesc*)(base + L->region[R_ITEMS]);
   a.tile_pos = (int*)(base + L->region[R_TILEPOS]);
+  a.G = scan_chunks(a.T, a.R);
+  a.tbase = (int*)(base + L->region[R_SCAN]);
+  a.rbase = a.tbase + a.G;
+  a.chist = a.rbase + a.G;
+  a.btot = a.chist + (size_t)a.G * kBuckets;
+  a.misc = a.btot + kBuckets;
   // the record and tile counts were cleared by plane_project
   if (a.R > 0)
     hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 3) / 4, std::min(a.CH, kChunkWaves)), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(bin_scan_kernel, dim3(a.G), dim3(1024), 0, st, a);
   if (a.R > 0)
     hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + 3) / 4, std::min(a.CH, kChunkWaves)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(bin_sort_small_kernel, dim3(a.T), dim3(256), 0, st, a);

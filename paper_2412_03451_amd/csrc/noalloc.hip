@@ -53,11 +53,13 @@ int scratch_address(int dev, void** out) {
 
 // The slot table and the counters of the workspace (what ps_workspace_init
 // writes), from kernel arguments: no host-to-device copy.
-__global__ void noalloc_init_kernel(ps_slot slot, ps_slot* slots, long long* counters, unsigned long long* queue) {
+__global__ void noalloc_init_kernel(ps_slot slot, ps_slot* slots, long long* counters, unsigned long long* queue,
+                                    int32_t* scan, int n_scan) {
   const int t = threadIdx.x;
   if (t == 0) slots[0] = slot;
   if (t < 64) counters[t] = 0;
   for (int i = t; i < 2 * 8 * 16; i += blockDim.x) queue[i] = 0ull;   // persistent-launch work queues
+  for (int i = t; i < n_scan; i += blockDim.x) scan[i] = 0;           // binning-scan histogram and counters
 }
 
 // After the render: the binning overflowed (more pairs than the scratch
@@ -126,8 +128,10 @@ extern "C" int plane_render_fwd_noalloc(const float* center, const float* quat, 
   rc = scratch_address(dev, &ws);
   if (rc) return rc;
   char* base = (char*)ws;
-  hipLaunchKernelGGL(noalloc_init_kernel, dim3(1), dim3(64), 0, st, slot, (ps_slot*)(base + L.region[R_SLOTS]),
-                     (long long*)(base + L.region[R_COUNTERS]), (unsigned long long*)(base + L.region[R_QUEUE]));
+  const int n_scan = (int)scan_words(L.n_tiles, L.n_records);
+  hipLaunchKernelGGL(noalloc_init_kernel, dim3(1), dim3(256), 0, st, slot, (ps_slot*)(base + L.region[R_SLOTS]),
+                     (long long*)(base + L.region[R_COUNTERS]), (unsigned long long*)(base + L.region[R_QUEUE]),
+                     (int32_t*)(base + L.region[R_SCAN]), n_scan);
   PS_HIP_CHECK(hipGetLastError());
   rc = plane_project(&L, ws, center, quat, radii, K, cam, 1, lambda, prm, stream);
   if (rc) return rc;

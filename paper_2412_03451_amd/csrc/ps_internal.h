@@ -81,9 +81,11 @@ enum Region {
   R_REC,         // Rec[R]
   R_BINREC,      // BinRec[R]
   R_REC_CNT,     // int[R + 1]   tiles per record
-  R_REC_OFF,     // int[R + 1]   exclusive scan of R_REC_CNT (emit index base)
+  R_REC_OFF,     // int[R + 1]   exclusive scan of R_REC_CNT (emit index base) within scan chunks
+                 //   (add the chunk's base from R_SCAN); [R] the total
   R_TILE_CNT,    // int[T + 1]   records per tile
-  R_TILE_OFF,    // int[T + 1]   exclusive scan of R_TILE_CNT
+  R_TILE_OFF,    // int[T + 1]   exclusive scan of R_TILE_CNT: within scan chunks until the tile
+                 //   sort writes the full offset back; [T] the total
   R_TILE_CUR,    // int[T]       scatter cursors
   R_KEYS_U,      // uint64[C]    unsorted (depth bound, record) keys
   R_EMIT_U,      // uint32[C]    unsorted emit indices
@@ -99,11 +101,25 @@ enum Region {
   R_TILEPOS,     // int[T]       first render item of each tile (longest lists first)
   R_CHUNK_CNT,   // int[R][max_chunks]  passing tiles per (record, group of 64 tiles of its box)
   R_QUEUE,       // uint64[2][8][16]  work-queue counters of persistent render launches (one line each)
+  R_SCAN,        // int[2 G + (G + 1) kBuckets + 16]  binning scan: chunk bases of tile and record
+                 //   offsets, per-chunk list-length histograms then each chunk's start in every
+                 //   bucket, the totals per bucket, counters (zero between calls); G scan chunks
   R_NUM_USED     // further regions are reserved (size 0)
 };
 // Render items are placed longest tile list first (buckets of list length),
 // so the blocks that take longest start first.
 constexpr int kBuckets = 1024;
+// tiles and records per workgroup of the binning scan
+constexpr int kScanChunk = 4096;
+__host__ __device__ inline int scan_chunks(int64_t T, int64_t R) {
+  const int64_t n = T > R ? T : R;
+  return n > 0 ? (int)((n + kScanChunk - 1) / kScanChunk) : 1;
+}
+// int32 words of R_SCAN
+__host__ __device__ inline int64_t scan_words(int64_t T, int64_t R) {
+  const int64_t G = scan_chunks(T, R);
+  return 2 * G + (G + 1) * kBuckets + 16;
+}
 __host__ __device__ inline int length_bucket(int n) { return n >> 2 < kBuckets - 1 ? n >> 2 : kBuckets - 1; }
 // per-block statistics slots of R_DIAG
 enum DiagSlot {

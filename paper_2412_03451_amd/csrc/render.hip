@@ -43,7 +43,8 @@ struct RenderArgs {
   const uint64_t* keys;
   const uint32_t* emit;
   const int* rec_cnt;
-  const int* rec_off;
+  const int* rec_off;   // chunk-local (binning scan); add rbase[r / kScanChunk]
+  const int* rbase;
   const ps_camera* cams;
   int n_cams;
   const float* lambda;
@@ -1124,7 +1125,7 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
     if (a.recs[r].cull) continue;
     const int nsub = (sl.tile_w >> 3) * (sl.tile_h >> 3);
     const int rows = a.rec_cnt[r] * nsub;
-    const int e0 = a.rec_off[r];
+    const int e0 = a.rec_off[r] + a.rbase[r / kScanChunk];
     float A[13];
 #pragma unroll
     for (int q = 0; q < 13; ++q) A[q] = 0.f;
@@ -1217,6 +1218,7 @@ int fill_args(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams, c
   a.emit = (const uint32_t*)(base + L->region[R_EMIT_S]);
   a.rec_cnt = (const int*)(base + L->region[R_REC_CNT]);
   a.rec_off = (const int*)(base + L->region[R_REC_OFF]);
+  a.rbase = (const int*)(base + L->region[R_SCAN]) + scan_chunks(L->n_tiles, L->n_records);
   a.cams = cams;
   a.n_cams = n_cams;
   a.lambda = lambda;

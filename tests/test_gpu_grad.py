@@ -309,6 +309,8 @@ def test_pending_buffer_size_does_not_change_results(mode):
         outs[P] = (D.clone(), N.clone(), [x.clone() for x in g], slow)
     print({P: o[3] for P, o in outs.items()}, flush=True)
     assert outs["all-fallback"][3] == cam.width * cam.height
+    # a buffer of 4 overflows on some pixels, not all: the mixed walk + fallback path is exercised
+    assert 0 < outs[4][3] < cam.width * cam.height
     for P in (4, 8, 12, "all-fallback"):
         assert torch.equal(outs[P][0], outs[6][0]) and torch.equal(outs[P][1], outs[6][1])
         for a, b in zip(outs[P][2], outs[6][2]):

@@ -18,7 +18,7 @@ and repeats the run, so no iteration is ever applied with a truncated list.
 from __future__ import annotations
 
 import ctypes as C
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import numpy as np
 import torch
@@ -73,6 +73,7 @@ class Scene:
     tgt_normal: torch.Tensor
     tile: tuple | None = None
     mask: torch.Tensor | None = None
+    sched_seed: int | None = None   # seed of the scene's view schedule (None: cfg.seed + its index)
 
 
 class BatchFit:
@@ -118,7 +119,8 @@ class BatchFit:
                 raise ValueError(f"scene {si}: all views must have the same size")
             V = len(sc.cams)
             self.size.append((W, H))
-            table = view_schedule(V, self.cfg.schedule_rows, S, self.cfg.seed + si) + self.v_off[-1]
+            seed = self.cfg.seed + si if sc.sched_seed is None else sc.sched_seed
+            table = view_schedule(V, self.cfg.schedule_rows, S, seed) + self.v_off[-1]
             tables.append(table)
             tile = tuple(sc.tile or self.cfg.tile)
             for j in range(S):
@@ -428,6 +430,36 @@ class BatchFit:
     def planes(self, scene: int = 0):
         a, b = int(self.k_off[scene]), int(self.k_off[scene + 1])
         return self.c[a:b], self.q[a:b], self.r[a:b]
+
+    def subset(self, keep) -> "BatchFit":
+        """A batch of the scenes `keep` (indices into this batch) that carries
+        on from the current state: planes, Adam moments, the iteration
+        counter and each scene's view schedule, so every kept scene follows
+        the trajectory it had in this batch (a batch gives each scene the
+        bits it gets alone).  Scenes that have reached their goal leave the
+        batch this way.  Splitting statistics are not carried."""
+        keep = list(keep)
+        scenes = []
+        for i in keep:
+            c, q, r = self.planes(i)
+            sc = self.scenes[i]
+            scenes.append(replace(sc, center=c, quat=q, radii=r,
+                                  sched_seed=self.cfg.seed + i if sc.sched_seed is None else sc.sched_seed))
+        nf = BatchFit(scenes, cfg=self.cfg, params=self.params, pair_capacity=self.rend.L.pair_capacity,
+                      size_capacity=False, device=self.device)
+        for j, i in enumerate(keep):
+            a0, a1 = int(self.k_off[i]), int(self.k_off[i + 1])
+            b0 = int(nf.k_off[j])
+            n = a1 - a0
+            # moments laid out center (3K) | quat (4K) | radii (4K)
+            for o_old, o_new, w in ((0, 0, 3), (3 * self.K, 3 * nf.K, 4), (7 * self.K, 7 * nf.K, 4)):
+                nf.m[o_new + w * b0:o_new + w * (b0 + n)] = self.m[o_old + w * a0:o_old + w * a1]
+                nf.v[o_new + w * b0:o_new + w * (b0 + n)] = self.v[o_old + w * a0:o_old + w * a1]
+        nf.ite.copy_(self.ite)
+        nf.step_no.copy_(self.step_no)
+        nf.lam.copy_(self.lam)
+        nf.size_capacity()
+        return nf
 
     def render_view(self, view: int, scene: int = 0, lam: float | None = None):
         """Depth [H, W] and normal [3, H, W] of one view of a scene at the

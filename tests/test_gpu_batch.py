@@ -187,3 +187,27 @@ def test_full_size_batch_sampled_pixels():
         grads, abss = oracle.per_pixel_abs_grad(*args, chunk=25, pix=samples[i])
         conds = oracle.weight_path_magnitude(*args, chunk=25, pix=samples[i])
         _check_grads([g[a:b] for g in gpu], grads, abss, f"batch room {i}", conds=conds)
+
+
+def test_subset_carries_each_scene_on():
+    """Scenes leaving a batch (BatchFit.subset): the scenes kept follow the
+    trajectory they had, the bits of a fit that never dropped a scene."""
+    from dataclasses import replace
+    from paper_2412_03451_amd.fit import BatchFit, FitConfig
+    scenes = _room_scenes()
+    cfg = FitConfig(check_every=10)
+    full = BatchFit(scenes, cfg=cfg)
+    full.run(30, graph=True)
+    part = BatchFit(scenes, cfg=cfg)
+    part.run(10, graph=True)
+    keep = [1]
+    part = part.subset(keep)
+    part.run(20, graph=True)
+    for j, i in enumerate(keep):
+        for a, b in zip(part.planes(j), full.planes(i)):
+            assert torch.equal(a, b), (i, j)
+    # a scene alone with the schedule seed it had in the batch: the same bits as well
+    alone = BatchFit([replace(scenes[1], sched_seed=cfg.seed + 1)], cfg=cfg)
+    alone.run(30, graph=True)
+    for a, b in zip(alone.planes(0), full.planes(1)):
+        assert torch.equal(a, b)

@@ -185,7 +185,8 @@ def culling_efficiency(init, cams, lam, tile, n_pix: int = 4096, seed: int = 0):
                       f"pixel of the view"}
 
 
-KERNEL_SOURCES = ("paper_2412_03451_amd/csrc/render.hip", "paper_2412_03451_amd/csrc/ps_internal.h")
+KERNEL_SOURCES = ("paper_2412_03451_amd/csrc/render.hip", "paper_2412_03451_amd/csrc/ps_internal.h",
+                  "paper_2412_03451_amd/csrc/adam.hip")
 TRAFFIC_FILES = {"fwd": "profiles/render_fwd_room640_hbm_traffic.txt",
                  "bwd": "profiles/render_bwd_room640_hbm_traffic.txt"}
 

@@ -4,8 +4,11 @@ timing graph-replayed fitting steps on the scene itself.
 
 The results are cached in a JSON file (PLANESPLAT_TUNE_CACHE, else
 ~/.cache/planesplat/tune.json): key "WxH/K<bucket>" -> {"tile": [w, h],
-"pending": p, "ms": step time, "tried": {...}}.  Tuning only reads the scene;
-the fits it times are thrown away.
+"pending": p, "ms": step time, "tried": {...}}.  Each configuration's time
+is the median of three timed runs, and the first tile shape and buffer size
+(16x16, 6) stay unless another is more than TILE_MARGIN faster, so timing
+noise does not change the choice from run to run.  Tuning only reads the
+scene; the fits it times are thrown away.
 """
 
 from __future__ import annotations
@@ -22,6 +25,7 @@ from .splat import SplatParams
 
 TILES = ((16, 16), (32, 8), (8, 8))
 PENDING = (6, 8, 4)
+TILE_MARGIN = 0.03   # a configuration other than the first replaces it only when this much faster
 _PENDING_BITS = {6: 0, 4: 1, 8: 2, 12: 3}
 
 
@@ -73,15 +77,18 @@ class Autotuner:
         st = torch.cuda.current_stream()
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(st)
-        for _ in range(steps):
-            fit.graph.replay()
-        b.record(st)
-        torch.cuda.synchronize()
+        times = []
+        for _ in range(3):   # the median of three runs: one slow run does not decide
+            torch.cuda.synchronize()
+            a.record(st)
+            for _ in range(steps):
+                fit.graph.replay()
+            b.record(st)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b) / steps)
         if fit.overflowed():
             return float("inf")
-        return a.elapsed_time(b) / steps
+        return sorted(times)[1]
 
     def tune(self, scene: Scene, cfg: FitConfig | None = None, steps: int = 20, warmup: int = 5,
              tiles=TILES, pendings=PENDING, force: bool = False):
@@ -97,10 +104,19 @@ class Autotuner:
         # tiles first at the default buffer size, then buffer sizes at the best tile
         for t in tiles:
             tried[f"{t[0]}x{t[1]}/p{pendings[0]}"] = self.time_config(scene, t, pendings[0], cfg, steps, warmup)
+        # another tile than the first (the default) only if it is clearly faster:
+        # timing noise does not flip the choice from one run to the next
+        t0 = tried[f"{tiles[0][0]}x{tiles[0][1]}/p{pendings[0]}"]
         best_t = min(tiles, key=lambda t: tried[f"{t[0]}x{t[1]}/p{pendings[0]}"])
+        if tried[f"{best_t[0]}x{best_t[1]}/p{pendings[0]}"] > t0 / (1.0 + TILE_MARGIN):
+            best_t = tiles[0]
         for p in pendings[1:]:
             tried[f"{best_t[0]}x{best_t[1]}/p{p}"] = self.time_config(scene, best_t, p, cfg, steps, warmup)
-        best = min(tried, key=tried.get)
+        best = f"{best_t[0]}x{best_t[1]}/p{pendings[0]}"
+        for p in pendings[1:]:
+            k = f"{best_t[0]}x{best_t[1]}/p{p}"
+            if tried[k] < tried[best] / (1.0 + TILE_MARGIN):
+                best = k
         tile_s, p_s = best.split("/p")
         tile = tuple(int(x) for x in tile_s.split("x"))
         self.table[key] = {"tile": list(tile), "pending": int(p_s), "ms": tried[best], "tried": tried}

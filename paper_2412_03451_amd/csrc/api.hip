@@ -101,6 +101,7 @@ extern "C" int ps_layout_init(ps_slot* slots, int n_slots, int64_t pair_capacity
       4 * (R * (size_t)max_chunks + 1),  // R_CHUNK_CNT
       8 * 2 * 8 * 16,                  // R_QUEUE
       4 * (size_t)ps::scan_words(T, R),  // R_SCAN
+      4 * (T + 1),                     // R_TILESLOT
   };
   size_t off = 0;
   for (int i = 0; i < PS_NUM_REGIONS; ++i) {

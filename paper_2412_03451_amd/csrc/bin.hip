@@ -1,22 +1,26 @@
 // tile_bin: (tile, plane) pairs keyed by a per-tile depth lower bound.
 //
-//   count  (one wave per record): tiles of the record's footprint that pass
-//          a separating-axis test against the projected grown rectangle and
-//          have a hit in front of the camera; per-tile counts by atomics.
+//   count  (one wave per (record, group of 64 tiles of its tile box)): tiles
+//          of the record's footprint that pass a separating-axis test
+//          against the projected grown rectangle and have a hit in front of
+//          the camera; per-tile counts by atomics.
 //   scan   (1024-thread workgroups, one per 4096 tiles and 4096 records):
 //          exclusive prefix sums of the chunk's tile and record counts with
-//          wave64 shuffles plus one LDS pass, and the chunk's list-length
-//          histogram; the last workgroup to finish scans the chunk totals
-//          (the chunk bases, which the later passes add to the chunk-local
-//          offsets), turns the histogram into the render items' bucket
-//          starts, and checks capacity and per-tile limits.
-//   emit   (one wave per record): key = (depth bound bits << 32 | record),
+//          wave64 shuffles plus one LDS pass, the chunk's list-length
+//          histogram and each tile's job slot; the last workgroup to finish
+//          scans the chunk totals (the chunk bases, which the later passes
+//          add to the chunk-local offsets), turns the histograms into the
+//          render items' bucket starts, and checks capacity and per-tile
+//          limits.
+//   emit   (the units of count): key = (depth bound bits << 32 | record),
 //          value = emit index (record-major), scattered into tile segments.
-//   sort   (one workgroup per tile): bitonic sort of the tile's keys in LDS;
-//          keys are unique, so the order is deterministic.  The sort also
-//          writes the records in list order (one contiguous, coalesced run
-//          per tile for the render loops) and the descriptors of the tile's
-//          8x8 render items.
+//   sort   (one wave per tile): bitonic sort of the tile's keys, across the
+//          lanes for lists of at most 64 entries, in LDS up to kSmallSort;
+//          longer lists in a second kernel (1024-thread workgroups, LDS
+//          sorts of 4096 entries and merges).  Keys are unique, so the order
+//          is deterministic.  The sort also writes the records in list order
+//          (one contiguous, coalesced run per tile for the render loops) and
+//          the descriptors of the tile's 8x8 render items.
 //
 // The depth bound of a record over a tile is the larger of (a) the minimum
 // camera z of its grown, near-clipped rectangle and (b) the minimum over the
@@ -62,6 +66,7 @@ struct BinArgs {
                       // chunk's first item position in each bucket
   int* btot;          // [kBuckets] render items per bucket
   int* misc;          // [0] workgroups done, [1] big tiles, [2] largest tile list (zero between calls)
+  int* tile_slot;     // [T] job slot of each tile
 };
 
 template <bool KEY>
@@ -99,30 +104,64 @@ __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot
   return true;
 }
 
-// One wave per record: the 64 lanes test the record's candidate tiles in
-// row-major order, 64 at a time (a plane near the camera can cover every
-// tile of the image, so one thread per record would serialise it).
-// Waves over (record, group of 64 tiles of its tile box): grid (R / 4, G),
-// wave (r, y) takes the groups y, y + G, ... of record r, so records with big
-// boxes (planes close to the camera, wide fringes at small lambda) spread
-// over up to G waves instead of one long loop.  Each group's count goes to
-// chunk_cnt for the emit pass; rec_cnt (cleared with the tile counts)
-// accumulates the record's total.
-constexpr int kChunkWaves = 8;
+// Work units of the count and emit passes: (record, group of 64 tiles of its
+// tile box, row-major); the 64 lanes of a wave test one group.  The
+// workgroups (x, y), y < gridDim.y, take the kRecPerWG records from
+// kRecPerWG x on and share their units round-robin over their
+// kRecPerWG gridDim.y waves, so a record
+// with a large box (a plane near the camera, a wide fringe at small lambda)
+// spreads over many waves, and records without tiles cost no waves of their
+// own.  The host sets gridDim.y from the record count: few records (one
+// scene, where the visible ones with large boxes are neighbours in record
+// order) get up to eight times the waves; many (a batch of scenes, most
+// records outside their job's view) get one wave per record.
+constexpr int kRecPerWG = 8;
+inline int unit_split(int R) { return std::max(1, std::min(8, 16384 / std::max(R, 1))); }
 
-__global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+// Units of the workgroup's records: ub[i] = first unit of record i, ub[8] the
+// total; us[i] = the record's job slot (so a unit's loads do not wait on each
+// other).
+__device__ inline void unit_bases(const BinArgs& a, int* ub, int* us) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * kRecPerWG + w;
+  if (lane == 0) {
+    int ng = 0, sl = 0;
+    if (r < a.R) {
+      const BinRec& br = a.brecs[r];
+      if (br.nedge != 0) ng = ((br.tx1 - br.tx0 + 1) * (br.ty1 - br.ty0 + 1) + 63) >> 6;
+      sl = br.slot;
+    }
+    ub[1 + w] = ng;
+    us[w] = sl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ub[0] = 0;
+    for (int i = 1; i <= kRecPerWG; ++i) ub[i] += ub[i - 1];
+  }
+  __syncthreads();
+}
+
+// Record (index in the workgroup) of unit u.
+__device__ inline int unit_record(const int* ub, int u) {
+  int i = 0;
+  while (u >= ub[i + 1]) ++i;
+  return i;
+}
+
+__global__ __launch_bounds__(64 * kRecPerWG) void bin_count_kernel(BinArgs a) {
+  __shared__ int ub[kRecPerWG + 1], us[kRecPerWG];
+  unit_bases(a, ub, us);
   const int lane = threadIdx.x & 63;
-  if (r >= a.R) return;
-  const BinRec& br = a.brecs[r];
-  if (br.nedge == 0) return;
-  const int nx = br.tx1 - br.tx0 + 1;
-  const int n = nx * (br.ty1 - br.ty0 + 1);
-  if ((int)blockIdx.y * 64 >= n) return;
-  const Rec& rec = a.recs[r];
-  const ps_slot& sl = a.slots[br.slot];
-  int total = 0;
-  for (int ch = blockIdx.y; ch * 64 < n; ch += gridDim.y) {
+  for (int u = (int)blockIdx.y * kRecPerWG + (threadIdx.x >> 6); u < ub[kRecPerWG]; u += kRecPerWG * gridDim.y) {
+    // wave-uniform: the record's fields come in through scalar loads
+    const int i = __builtin_amdgcn_readfirstlane(unit_record(ub, u));
+    const int r = blockIdx.x * kRecPerWG + i, ch = u - __builtin_amdgcn_readfirstlane(ub[i]);
+    const BinRec& br = a.brecs[r];
+    const Rec& rec = a.recs[r];
+    const ps_slot& sl = a.slots[__builtin_amdgcn_readfirstlane(us[i])];
+    const int nx = br.tx1 - br.tx0 + 1;
+    const int n = nx * (br.ty1 - br.ty0 + 1);
     const int idx = ch * 64 + lane;
     bool pass = false;
     if (idx < n) {
@@ -132,10 +171,11 @@ __global__ __launch_bounds__(256) void bin_count_kernel(BinArgs a) {
       if (pass) atomicAdd(&a.tile_cnt[sl.tile_begin + ty * sl.tiles_x + tx], 1);
     }
     const int cnt = __popcll(ballot(pass));
-    if (lane == 0) a.chunk_cnt[(size_t)r * a.CH + ch] = cnt;
-    total += cnt;
+    if (lane == 0) {
+      a.chunk_cnt[(size_t)r * a.CH + ch] = cnt;
+      if (cnt) atomicAdd(&a.rec_cnt[r], cnt);
+    }
   }
-  if (lane == 0 && total) atomicAdd(&a.rec_cnt[r], total);
 }
 
 // Exclusive scan of in[0, n) by one 1024-thread workgroup (n <= 4096):
@@ -179,14 +219,56 @@ __device__ inline int chunk_scan(const int* __restrict__ in, int* __restrict__ o
   return total;
 }
 
+// Exclusive scan in place of x[0, n), int32 values that other workgroups
+// wrote (read with device-scope loads), by one 1024-thread workgroup, 1024
+// values at a time; returns the total.  lsum: 17 int64 of LDS.
+__device__ inline long long block_scan_inplace(int* x, int n, long long* lsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  long long carry = 0;
+  for (int b0 = 0; b0 < n; b0 += 1024) {
+    const int i = b0 + tid;
+    const long long v = i < n ? __hip_atomic_load(&x[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    long long incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) lsum[wid] = incl;
+    __syncthreads();
+    if (tid == 0) {
+      long long run = 0;
+      for (int w = 0; w < 16; ++w) {
+        const long long t = lsum[w];
+        lsum[w] = run;
+        run += t;
+      }
+      lsum[16] = run;
+    }
+    __syncthreads();
+    if (i < n) x[i] = (int)(carry + lsum[wid] + incl - v);
+    carry += lsum[16];
+    __syncthreads();
+  }
+  return carry;
+}
+
+// Job slots are cached in LDS for the tile-to-slot search when there are at
+// most this many
+constexpr int kSlotCache = 1024;
+
 __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   __shared__ int lds[40];
   __shared__ int hist[kBuckets];
+  __shared__ int stb[kSlotCache];   // tile_begin of each slot
+  __shared__ long long lsum[17];
   __shared__ int last;
   const int g = blockIdx.x, tid = threadIdx.x;
   const int t0 = g * kScanChunk, r0 = g * kScanChunk;
   const int nt = max(0, min(kScanChunk, a.T - t0)), nr = max(0, min(kScanChunk, a.R - r0));
+  const bool cached = a.S <= kSlotCache;
   for (int k = tid; k < kBuckets; k += blockDim.x) hist[k] = 0;
+  if (cached)
+    for (int s = tid; s < a.S; s += blockDim.x) stb[s] = a.slots[s].tile_begin;
   int mx_t = 0, mx_r = 0;
   const int tot_t = chunk_scan(a.tile_cnt + t0, a.tile_off + t0, nt, lds, mx_t);
   const int tot_r = chunk_scan(a.rec_cnt + r0, a.rec_off + r0, nr, lds, mx_r);
@@ -196,9 +278,21 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   // bucket; the order of tiles inside a bucket does not matter: items are
   // independent); bin_emit's scatter cursors
   for (int t = t0 + tid; t < t0 + nt; t += blockDim.x) {
-    const ps_slot& sl = a.slots[find_slot_by_tile(a.slots, a.S, t)];
+    int si;
+    if (cached) {   // last slot whose first tile is <= t
+      int lo = 0, hi = a.S - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (stb[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      si = lo;
+    } else {
+      si = find_slot_by_tile(a.slots, a.S, t);
+    }
+    const ps_slot& sl = a.slots[si];
     const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
     const int c = a.tile_cnt[t];
+    a.tile_slot[t] = si;
     a.tile_pos[t] = atomicAdd(&hist[length_bucket(c)], sub_per);
     a.tile_cur[t] = 0;
     if (c > kSmallSort && c <= kMaxList) a.bigtiles[atomicAdd(&a.misc[1], 1)] = t;
@@ -223,37 +317,43 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   } else {
     __syncthreads();
   }
-  long long total = 0;
-  if (tid == 0) {   // chunk bases (a few hundred chunks at most: in order on one thread)
-    long long tb = 0, rb = 0;
-    for (int k = 0; k < a.G; ++k) {
-      const int ct = __hip_atomic_load(&a.tbase[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int cr = __hip_atomic_load(&a.rbase[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      a.tbase[k] = (int)tb;
-      a.rbase[k] = (int)rb;
-      tb += ct;
-      rb += cr;
+  // chunk bases: exclusive scans of the chunk totals (one chunk: its own)
+  const long long tb = a.G == 1 ? tot_t : block_scan_inplace(a.tbase, a.G, lsum);
+  const long long rb = a.G == 1 ? tot_r : block_scan_inplace(a.rbase, a.G, lsum);
+  if (tid == 0) {
+    if (a.G == 1) {
+      a.tbase[0] = 0;
+      a.rbase[0] = 0;
     }
-    lds[34] = (int)(tb >> 31);   // pairs beyond int range: flagged as overflow below
-    lds[35] = (int)(tb & 0x7fffffff);
     // the totals after the last entries (the offsets before them stay chunk-local)
     a.tile_off[a.T] = (int)tb;
     a.rec_off[a.R] = (int)rb;
   }
   // items per bucket over the chunks; each chunk's counts become its start
-  // inside the bucket (chunks in order)
-  for (int k = tid; k < kBuckets; k += blockDim.x) {
+  // inside the bucket (chunks in order; 16 loads in flight per thread).  One
+  // chunk: its histogram is still in LDS and starts every bucket at 0.
+  if (a.G == 1)
+    for (int k = tid; k < kBuckets; k += blockDim.x) a.chist[k] = 0;
+  for (int k = tid; k < kBuckets && a.G > 1; k += blockDim.x) {
     int run = 0;
-    for (int c = 0; c < a.G; ++c) {
-      int* h = &a.chist[(size_t)c * kBuckets + k];
-      const int v = __hip_atomic_load(h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      *h = run;
-      run += v;
+    for (int c0 = 0; c0 < a.G; c0 += 16) {
+      int v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        v[j] = c0 + j < a.G ? __hip_atomic_load(&a.chist[(size_t)(c0 + j) * kBuckets + k], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : 0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (c0 + j < a.G) {
+          a.chist[(size_t)(c0 + j) * kBuckets + k] = run;
+          run += v[j];
+        }
     }
     hist[k] = run;
   }
   __syncthreads();
-  total = ((long long)lds[34] << 31) | lds[35];
+  const long long total = tb;   // pairs (beyond int range: flagged as overflow below)
   if (tid < 64) {   // exclusive scan over buckets, longest first: 16 buckets per lane
     const int lane = tid;
     int loc = 0;
@@ -289,27 +389,29 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   }
 }
 
-// Waves over (record, group of 64 tiles) as in bin_count_kernel: the j-th
-// passing tile of record r, in tile-box order, gets emit index rec_off[r] + j
-// (counts of the earlier groups, then a ballot prefix count).
-__global__ __launch_bounds__(256) void bin_emit_kernel(BinArgs a) {
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (r >= a.R) return;
+// Work units as in bin_count_kernel: the j-th passing tile of record r, in
+// tile-box order, gets emit index rec_off[r] + j (the counts of the earlier
+// groups, summed across the lanes, then a ballot prefix count).
+__global__ __launch_bounds__(64 * kRecPerWG) void bin_emit_kernel(BinArgs a) {
+  __shared__ int ub[kRecPerWG + 1], us[kRecPerWG];
   if (a.counters[C_OVERFLOW]) return;
-  const BinRec& br = a.brecs[r];
-  if (br.nedge == 0) return;
-  const int nx = br.tx1 - br.tx0 + 1;
-  const int n = nx * (br.ty1 - br.ty0 + 1);
-  if ((int)blockIdx.y * 64 >= n) return;
-  const Rec& rec = a.recs[r];
-  const ps_slot& sl = a.slots[br.slot];
-  const int* cc = a.chunk_cnt + (size_t)r * a.CH;
-  int j = a.rec_off[r] + a.rbase[r / kScanChunk];
-  int done = 0;   // groups counted into j
+  unit_bases(a, ub, us);
+  const int lane = threadIdx.x & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int ch = blockIdx.y; ch * 64 < n; ch += gridDim.y) {
-    for (; done < ch; ++done) j += cc[done];
+  for (int u = (int)blockIdx.y * kRecPerWG + (threadIdx.x >> 6); u < ub[kRecPerWG]; u += kRecPerWG * gridDim.y) {
+    // wave-uniform: the record's fields come in through scalar loads
+    const int i = __builtin_amdgcn_readfirstlane(unit_record(ub, u));
+    const int r = blockIdx.x * kRecPerWG + i, ch = u - __builtin_amdgcn_readfirstlane(ub[i]);
+    const BinRec& br = a.brecs[r];
+    const Rec& rec = a.recs[r];
+    const ps_slot& sl = a.slots[__builtin_amdgcn_readfirstlane(us[i])];
+    const int nx = br.tx1 - br.tx0 + 1;
+    const int n = nx * (br.ty1 - br.ty0 + 1);
+    const int* cc = a.chunk_cnt + (size_t)r * a.CH;
+    int before = 0;   // passing tiles of the groups before ch
+    for (int c = lane; c < ch; c += 64) before += cc[c];
+    for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
+    const int j = a.rec_off[r] + a.rbase[r / kScanChunk] + before;
     const int idx = ch * 64 + lane;
     bool pass = false;
     float kt = 0.f;
@@ -369,49 +471,88 @@ __device__ void lds_bitonic(uint64_t* k, uint32_t* v, int n, const uint64_t* __r
   }
 }
 
-__global__ __launch_bounds__(256) void bin_sort_small_kernel(BinArgs a) {
+// One wave per tile.  The tile's render items, then its sort: a list of at
+// most 64 entries in registers (a bitonic network across the lanes, one key
+// per lane), up to kSmallSort in LDS; longer lists are left to
+// bin_sort_big_kernel.  The list's keys are fetched before the item
+// bookkeeping, so their latency overlaps it.
+__global__ __launch_bounds__(64) void bin_sort_small_kernel(BinArgs a) {
   __shared__ uint64_t k[kSmallSort];
   __shared__ uint32_t v[kSmallSort];
-  __shared__ int pos0;
-  const int t = blockIdx.x;
+  const int t = blockIdx.x, lane = threadIdx.x;
   const int n = a.tile_cnt[t];
   const int off = a.tile_off[t] + a.tbase[t / kScanChunk];   // chunk-local offset + chunk base
-  const int s = find_slot_by_tile(a.slots, a.S, t);
+  const bool reg = n <= 64;
+  uint64_t key = ~0ull;
+  uint32_t val = 0u;
+  if (reg && lane < n) {
+    key = a.keys_u[off + lane];
+    val = a.emit_u[off + lane];
+  }
+  const int s = a.tile_slot[t];
   const ps_slot& sl = a.slots[s];
   const int sub_w = sl.tile_w >> 3;
   const int sub_per = sub_w * (sl.tile_h >> 3);
   // the tile's first render item: its bucket's start + its chunk's start in
   // the bucket + its place among the chunk's tiles of the bucket
-  if (threadIdx.x == 0) {
-    const int k = length_bucket(n);
-    pos0 = a.btot[k] + a.chist[(size_t)(t / kScanChunk) * kBuckets + k] + a.tile_pos[t];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) a.tile_off[t] = off;   // final offset, for bin_sort_big
+  const int kb = length_bucket(n);
+  const int pos0 = a.btot[kb] + a.chist[(size_t)(t / kScanChunk) * kBuckets + kb] + a.tile_pos[t];
+  if (lane == 0) a.tile_off[t] = off;   // final offset, for bin_sort_big
   // render items (8x8 blocks) of this tile, placed by list length
-  if (threadIdx.x < 16) {
-    const int sub = threadIdx.x;
-    if (sub < sub_per) {
-      const int pos = pos0 + sub;
-      const int lt = t - sl.tile_begin;
-      ItemDesc d;
-      d.b = off;
-      d.e = off + n;
-      d.ox = (int16_t)((lt % sl.tiles_x) * sl.tile_w + (sub % sub_w) * 8);
-      d.oy = (int16_t)((lt / sl.tiles_x) * sl.tile_h + (sub / sub_w) * 8);
-      d.width = (int16_t)sl.width;
-      d.height = (int16_t)sl.height;
-      d.cam = sl.cam;
-      d.sub = (int16_t)sub;
-      d.slot = (int16_t)s;
-      d.pix_off = sl.pix_off;
-      a.items[pos] = d;
-    }
+  if (lane < sub_per) {
+    const int sub = lane;
+    const int lt = t - sl.tile_begin;
+    ItemDesc d;
+    d.b = off;
+    d.e = off + n;
+    d.ox = (int16_t)((lt % sl.tiles_x) * sl.tile_w + (sub % sub_w) * 8);
+    d.oy = (int16_t)((lt / sl.tiles_x) * sl.tile_h + (sub / sub_w) * 8);
+    d.width = (int16_t)sl.width;
+    d.height = (int16_t)sl.height;
+    d.cam = sl.cam;
+    d.sub = (int16_t)sub;
+    d.slot = (int16_t)s;
+    d.pix_off = sl.pix_off;
+    a.items[pos0 + sub] = d;
   }
   if (a.counters[C_OVERFLOW]) return;
   if (n == 0 || n > kSmallSort) return;
-  lds_bitonic<kSmallSort, 256>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off,
-                               a.recs, a.recs_s + off);
+  if (!reg) {
+    lds_bitonic<kSmallSort, 64>(k, v, n, a.keys_u + off, a.emit_u + off, a.keys_s + off, a.emit_s + off,
+                                a.recs, a.recs_s + off);
+    return;
+  }
+  // bitonic network over the n2 >= n lanes (unused lanes hold the largest
+  // key and stay at the end); keys are unique
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
+      const uint64_t ok = ((uint64_t)(uint32_t)__shfl_xor((int)khi, stride, 64) << 32) |
+                          (uint32_t)__shfl_xor((int)klo, stride, 64);
+      const uint32_t ov = (uint32_t)__shfl_xor((int)val, stride, 64);
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      const bool take = lower == up ? ok < key : ok > key;   // keep the smaller in the lower lane when ascending
+      if (take) {
+        key = ok;
+        val = ov;
+      }
+    }
+  }
+  if (lane < n) {
+    a.keys_s[off + lane] = key;
+    a.emit_s[off + lane] = val;
+  }
+  // record copies in list order, eight lanes per 128-byte record
+  const int rec_lo = (int)(uint32_t)key;
+  for (int i0 = 0; i0 < 8 * n; i0 += 64) {   // every lane takes part in the exchange
+    const int i = i0 + lane, e = i >> 3, q = i & 7;
+    const int ri = __shfl(rec_lo, e & 63, 64);
+    if (i < 8 * n)
+      reinterpret_cast<float4*>(&a.recs_s[off + e])[q] = reinterpret_cast<const float4*>(&a.recs[ri])[q];
+  }
 }
 
 // One merge pass over a tile list made of sorted runs of length L: the runs
@@ -526,14 +667,17 @@ extern "C" int tile_bin(const ps_layout* L, void* ws, int64_t* pairs_needed, voi
   a.chist = a.rbase + a.G;
   a.btot = a.chist + (size_t)a.G * kBuckets;
   a.misc = a.btot + kBuckets;
+  a.tile_slot = (int*)(base + L->region[R_TILESLOT]);
   // the record and tile counts were cleared by plane_project
   if (a.R > 0)
-    hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + 3) / 4, std::min(a.CH, kChunkWaves)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bin_count_kernel, dim3((a.R + kRecPerWG - 1) / kRecPerWG, unit_split(a.R)),
+                       dim3(64 * kRecPerWG), 0, st, a);
   hipLaunchKernelGGL(bin_scan_kernel, dim3(a.G), dim3(1024), 0, st, a);
   if (a.R > 0)
-    hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + 3) / 4, std::min(a.CH, kChunkWaves)), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(bin_sort_small_kernel, dim3(a.T), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(bin_sort_big_kernel, dim3(32), dim3(1024), 12 * kBigSort, st, a);
+    hipLaunchKernelGGL(bin_emit_kernel, dim3((a.R + kRecPerWG - 1) / kRecPerWG, unit_split(a.R)),
+                       dim3(64 * kRecPerWG), 0, st, a);
+  hipLaunchKernelGGL(bin_sort_small_kernel, dim3(a.T), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(bin_sort_big_kernel, dim3(64), dim3(1024), 12 * kBigSort, st, a);
   PS_HIP_CHECK(hipGetLastError());
   if (pairs_needed) {
     long long c[2];

@@ -104,6 +104,7 @@ enum Region {
   R_SCAN,        // int[2 G + (G + 1) kBuckets + 16]  binning scan: chunk bases of tile and record
                  //   offsets, per-chunk list-length histograms then each chunk's start in every
                  //   bucket, the totals per bucket, counters (zero between calls); G scan chunks
+  R_TILESLOT,    // int[T + 1]   job slot of each tile (binning scan, for the tile sort)
   R_NUM_USED     // further regions are reserved (size 0)
 };
 // Render items are placed longest tile list first (buckets of list length),
@@ -168,10 +169,12 @@ static_assert(C_BT_MAX + 1 == PS_N_COUNTERS, "counter count");
 constexpr int kFlagDiag = 64;   // params.flags bit 6: forward walk statistics
 constexpr int kFlagNoPersist = 256;   // params.flags bit 8: one workgroup per item even for large batches
 constexpr int kFlagPersistFwd = 512;  // params.flags bit 9: the forward persistent too
+constexpr int kFlagReduceWave = 1024; // params.flags bit 10: the gradient reduction a wave per plane at any size
+constexpr int kReduceWaveMin = 8192;  // planes from which the gradient reduction takes a wave per plane
 constexpr int kFlagPathDiag = 128;   // params.flags bit 7: mark fallback-path pixels in the hit counts
 
 constexpr int kMaxM = 30;
-constexpr int kSmallSort = 1024;  // tile lists up to this size sort in one small-LDS pass
+constexpr int kSmallSort = 256;   // tile lists up to this size sort in one wave (registers or 3 KB of LDS)
 constexpr int kBigSort = 4096;    // tile lists up to this size sort in one LDS pass (48 KB of LDS);
                                   // longer ones sort in chunks of this size, then merge in memory
 constexpr int kMaxList = 32767;   // longest tile list: list positions are kept as int16

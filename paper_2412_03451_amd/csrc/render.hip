@@ -1090,25 +1090,45 @@ __device__ void loss_sums(const RenderArgs& a, int s) {
   }
 }
 
-template <bool LOSS>
+// Per plane: the sum of each of its records' partial rows in one fixed order
+// whatever the launch shape.  The rows are taken in blocks of 256: row
+// 64 v + l of each block goes to accumulator set v (v < 4) of lane l, each
+// set is summed over the wave (wave_sum16) and the four totals are added as
+// ((s0 + s1) + s2) + s3.  Y = 4: a workgroup per plane, wave v holds set v
+// (few planes: four waves on the rows of a large plane); Y = 1: a wave per
+// plane holds all four sets (many planes: no idle waves, four rows in flight
+// per lane).  Same bits either way.
+template <bool LOSS, int Y>
 __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
   __shared__ float part[4][16];
   // with LOSS the first n_slots workgroups form the loss sums, one job each
   // (placed last, they cost the 64-room batch's reduction 150 us: measured)
-  const int k = LOSS ? (int)blockIdx.x - a.S : (int)blockIdx.x;
-  if (k < 0) {
-    loss_sums(a, k + a.S);
+  const int wg = LOSS ? (int)blockIdx.x - a.S : (int)blockIdx.x;
+  if (wg < 0) {
+    loss_sums(a, wg + a.S);
     return;
   }
+  constexpr int NV = 4 / Y;   // accumulator sets per wave
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int k = Y == 4 ? wg : 4 * wg + w;
+  const int vs0 = Y == 4 ? w : 0;   // this wave's first set
   if (k >= a.K) return;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // the plane's parameters, fetched up front: the chain rule at the end
+  // needs them, and their latency hides behind the lookups below
+  float pc[3], pq[4];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pc[i] = a.center[3 * k + i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) pq[i] = a.quat[4 * k + i];
   double gp[3] = {0, 0, 0}, gw[3] = {0, 0, 0}, gr[4] = {0, 0, 0, 0};
   double qn[4] = {0, 0, 0, 0}, qnorm = 0;
   const bool ok = !a.counters[C_OVERFLOW];
-  // the slots holding plane k, in slot order: with sorted plane ranges they
-  // are a run starting at the first slot whose range ends after k
+  // the slots holding plane k, in slot order, 64 slots per lookup (one slot
+  // per lane, whose fields the wave then reads from that lane); with sorted
+  // plane ranges they are a run starting at the first slot whose range ends
+  // after k.  (With Y = 4 every wave of the workgroup finds the same slots.)
   int s0 = 0;
-  if (a.slots_sorted) {
+  if (a.slots_sorted && a.S > 64) {
     int lo = 0, hi = a.S;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -1116,58 +1136,104 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
     }
     s0 = lo;
   }
-  for (int s = s0; s < a.S && ok; ++s) {
-    const ps_slot sl = a.slots[s];
-    if (a.slots_sorted && sl.plane_begin > k) break;
-    if (k < sl.plane_begin || k >= sl.plane_end) continue;
-    if (sl.cam < 0 || sl.cam >= a.n_cams) continue;
-    const int r = sl.rec_begin + (k - sl.plane_begin);
-    if (a.recs[r].cull) continue;
-    const int nsub = (sl.tile_w >> 3) * (sl.tile_h >> 3);
-    const int rows = a.rec_cnt[r] * nsub;
-    const int e0 = a.rec_off[r] + a.rbase[r / kScanChunk];
-    float A[13];
-#pragma unroll
-    for (int q = 0; q < 13; ++q) A[q] = 0.f;
-    for (int idx = tid; idx < rows; idx += 256) {
-      const int e = e0 + idx / nsub, sb = idx % nsub;
-      const float4* row = (const float4*)(a.partial + ((size_t)e * a.max_sub + sb) * 16);
-      const float4 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
-      A[0] += r0.x; A[1] += r0.y; A[2] += r0.z; A[3] += r0.w;
-      A[4] += r1.x; A[5] += r1.y; A[6] += r1.z; A[7] += r1.w;
-      A[8] += r2.x; A[9] += r2.y; A[10] += r2.z; A[11] += r2.w;
-      A[12] += r3.x;
+  for (int sb = s0; sb < a.S && ok; sb += 64) {
+    const int sl_i = sb + lane;
+    bool in = false, past = false;
+    int f_pb = 0, f_cam = 0, f_rb = 0, f_nsub = 0;
+    if (sl_i < a.S) {
+      const ps_slot& q = a.slots[sl_i];
+      f_pb = q.plane_begin;
+      f_cam = q.cam;
+      f_rb = q.rec_begin;
+      f_nsub = (q.tile_w >> 3) * (q.tile_h >> 3);
+      in = k >= f_pb && k < q.plane_end && f_cam >= 0 && f_cam < a.n_cams;
+      past = f_pb > k;
     }
-    {
-      float V[16];
+    uint64_t m = ballot(in);
+    const bool stop = a.slots_sorted && ballot(past) != 0;
+    while (m) {
+      const int j = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int cam_i = __builtin_amdgcn_readlane(f_cam, j);
+      const int r = __builtin_amdgcn_readlane(f_rb, j) + (k - __builtin_amdgcn_readlane(f_pb, j));
+      const int nsub = __builtin_amdgcn_readlane(f_nsub, j);
+      const ps_camera cam = a.cams[cam_i];
+      if (a.recs[r].cull) continue;
+      const int rows = a.rec_cnt[r] * nsub;
+      const int e0 = a.rec_off[r] + a.rbase[r / kScanChunk];
+      float A[NV][16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) V[q] = q < 13 ? A[q] : 0.f;
-      const float tot = wave_sum16(V);   // lane 4 q holds the wave's sum of A[q]
-      if ((lane & 3) == 0) part[wid][lane >> 2] = tot;
-      __syncthreads();
-      // the four waves' sums in a fixed order
+      for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int q = 0; q < 13; ++q) A[q] = ((part[0][q] + part[1][q]) + part[2][q]) + part[3][q];
-      __syncthreads();
+        for (int q = 0; q < 16; ++q) A[v][q] = 0.f;
+      constexpr int NL = NV < 2 ? NV : 2;   // sets loaded together (rows in flight per lane)
+      for (int i0 = 0; i0 < rows; i0 += 256) {
+#pragma unroll
+        for (int vp = 0; vp < NV; vp += NL) {
+          float4 x[NL][3];
+          float y[NL];
+#pragma unroll
+          for (int u = 0; u < NL; ++u) {
+            const int idx = i0 + 64 * (vs0 + vp + u) + lane;
+            if (idx < rows) {
+              const int e = e0 + idx / nsub, sbk = idx % nsub;
+              const float* rowp = a.partial + ((size_t)e * a.max_sub + sbk) * 16;
+              const float4* row = (const float4*)rowp;
+              x[u][0] = row[0]; x[u][1] = row[1]; x[u][2] = row[2]; y[u] = rowp[12];
+            } else {
+              x[u][0] = x[u][1] = x[u][2] = make_float4(0.f, 0.f, 0.f, 0.f);
+              y[u] = 0.f;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < NL; ++u) {
+            float* Av = A[vp + u];
+            Av[0] += x[u][0].x; Av[1] += x[u][0].y; Av[2] += x[u][0].z; Av[3] += x[u][0].w;
+            Av[4] += x[u][1].x; Av[5] += x[u][1].y; Av[6] += x[u][1].z; Av[7] += x[u][1].w;
+            Av[8] += x[u][2].x; Av[9] += x[u][2].y; Av[10] += x[u][2].z; Av[11] += x[u][2].w;
+            Av[12] += y[u];
+          }
+        }
+      }
+      float S[13];   // ((s0 + s1) + s2) + s3 of each accumulator
+      if (Y == 4) {
+        const float tot = wave_sum16(A[0]);   // lane 4 q holds the wave's sum of accumulator q
+        if ((lane & 3) == 0) part[w][lane >> 2] = tot;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 13; ++q) S[q] = ((part[0][q] + part[1][q]) + part[2][q]) + part[3][q];
+        __syncthreads();
+      } else {
+        float t[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) t[v] = wave_sum16(A[v]);
+#pragma unroll
+        for (int q = 0; q < 13; ++q) {
+          float s4[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) s4[v] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[v % NV]), 4 * q));
+          S[q] = ((s4[0] + s4[1]) + s4[2]) + s4[3];
+        }
+      }
+      Frame f;
+      if (!plane_frame(pc, pq, 0, cam, f)) continue;
+      for (int q = 0; q < 4; ++q) qn[q] = f.q[q];
+      qnorm = f.qnorm;
+      const double sg = a.two_sided ? (f.h > 0.0 ? -1.0 : 1.0) : 1.0;
+      double gs[3];   // s R^T dL/d(rendered normal)
+      for (int i = 0; i < 3; ++i)
+        gs[i] = sg * ((double)cam.R[i] * S[6] + (double)cam.R[3 + i] * S[7] + (double)cam.R[6 + i] * S[8]);
+      const double nxg[3] = {f.n[1] * gs[2] - f.n[2] * gs[1], f.n[2] * gs[0] - f.n[0] * gs[2],
+                             f.n[0] * gs[1] - f.n[1] * gs[0]};
+      for (int i = 0; i < 3; ++i) {
+        gp[i] += (double)S[2] * f.n[i] - (double)S[0] * f.vx[i] - (double)S[1] * f.vy[i];
+        gw[i] += (double)S[3] * f.n[i] + (double)S[5] * f.vx[i] - (double)S[4] * f.vy[i] + nxg[i];
+      }
+      for (int q = 0; q < 4; ++q) gr[q] += S[9 + q];
     }
-    const ps_camera cam = a.cams[sl.cam];
-    Frame f;
-    if (!plane_frame(a.center, a.quat, k, cam, f)) continue;
-    for (int q = 0; q < 4; ++q) qn[q] = f.q[q];
-    qnorm = f.qnorm;
-    const double sg = a.two_sided ? (f.h > 0.0 ? -1.0 : 1.0) : 1.0;
-    double gs[3];   // s R^T dL/d(rendered normal)
-    for (int i = 0; i < 3; ++i)
-      gs[i] = sg * ((double)cam.R[i] * A[6] + (double)cam.R[3 + i] * A[7] + (double)cam.R[6 + i] * A[8]);
-    const double nxg[3] = {f.n[1] * gs[2] - f.n[2] * gs[1], f.n[2] * gs[0] - f.n[0] * gs[2],
-                           f.n[0] * gs[1] - f.n[1] * gs[0]};
-    for (int i = 0; i < 3; ++i) {
-      gp[i] += (double)A[2] * f.n[i] - (double)A[0] * f.vx[i] - (double)A[1] * f.vy[i];
-      gw[i] += (double)A[3] * f.n[i] + (double)A[5] * f.vx[i] - (double)A[4] * f.vy[i] + nxg[i];
-    }
-    for (int q = 0; q < 4; ++q) gr[q] += A[9 + q];
+    if (stop) break;
   }
-  if (tid == 0) {
+  if (lane == 0 && (Y == 1 || w == 0)) {
     for (int i = 0; i < 3; ++i) a.g_center[3 * k + i] = (float)gp[i];
     for (int q = 0; q < 4; ++q) a.g_radii[4 * k + q] = (float)gr[q];
     // 2 (0, w) (x) q^  =  2 (-(w . v), q0 w + w x v),  v = (q1, q2, q3)
@@ -1331,10 +1397,21 @@ static int launch_bwd(RenderArgs& a, int K, void* stream) {
     const int rc = a.mode == 2 ? launch_bwd_g<true>(a, st) : launch_bwd_g<false>(a, st);
     if (rc) return rc;
   }
-  if (a.loss_out)
-    hipLaunchKernelGGL(bwd_reduce_kernel<true>, dim3(K + a.S), dim3(256), 0, st, a);
-  else if (K > 0)
-    hipLaunchKernelGGL(bwd_reduce_kernel<false>, dim3(K), dim3(256), 0, st, a);
+  // a wave per plane for many planes, a workgroup per plane for few (the
+  // same bits either way); ps_params.flags bit 10 asks for a wave per plane
+  const bool per_wave = K >= kReduceWaveMin || (a.flags & kFlagReduceWave);
+  const int nwg = per_wave ? (K + 3) / 4 : K;
+  if (a.loss_out) {
+    if (per_wave)
+      hipLaunchKernelGGL((bwd_reduce_kernel<true, 1>), dim3(nwg + a.S), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((bwd_reduce_kernel<true, 4>), dim3(nwg + a.S), dim3(256), 0, st, a);
+  } else if (K > 0) {
+    if (per_wave)
+      hipLaunchKernelGGL((bwd_reduce_kernel<false, 1>), dim3(nwg), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((bwd_reduce_kernel<false, 4>), dim3(nwg), dim3(256), 0, st, a);
+  }
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }

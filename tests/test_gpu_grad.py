@@ -140,6 +140,37 @@ def test_backward_multi_view_sums_over_views():
     _check_grads(out, tot[0], tot[1], "two views")
 
 
+def test_reduction_shape_does_not_change_bits():
+    """The per-plane reduction of the partial rows takes a workgroup per plane
+    for few planes and a wave per plane for many (flags bit 10 forces the
+    latter): the same summation order, so the same bits.  Two views (two
+    records per plane) and 8x8 tiles on a 320x240 image, so large planes have
+    more than 256 rows."""
+    from paper_2412_03451_amd.splat import Job, Renderer, SplatParams
+    ps = synth.random_planes(60, seed=9, center_range=0.3, extent_range=(0.4, 0.9), independent_radii=True)
+    cams = [synth.Camera(320, 240, 300.0, 300.0, 160.0, 120.0, np.eye(3, dtype=np.float32),
+                         np.array([0.0, 0.0, 3.0], np.float32)),
+            synth.Camera(320, 240, 280.0, 280.0, 161.0, 119.0, np.eye(3, dtype=np.float32),
+                         np.array([0.2, -0.1, 3.3], np.float32))]
+    rng = np.random.default_rng(3)
+    n = sum(c.width * c.height for c in cams)
+    gD = _dev(rng.normal(size=n).astype(np.float32))
+    gN = _dev(rng.normal(size=3 * n).astype(np.float32))
+    outs = []
+    for flags in (0, 1 << 10):
+        jobs = [Job(0, ps.K, i, c.width, c.height, (8, 8)) for i, c in enumerate(cams)]
+        r = Renderer(jobs, cams, params=SplatParams(flags=flags))
+        c, q, rr = _dev(ps.center), _dev(ps.quat), _dev(ps.radii)
+        lt = torch.tensor([20.0], device="cuda")
+        r.render(c, q, rr, lt)
+        outs.append([x.clone() for x in r.backward(c, q, rr, lt, gD, gN)])
+        rows = r.region(3, torch.int32, r.L.n_records).max().item()   # 8x8 tiles: rows = tiles of a record
+    assert rows > 256
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+        assert float(a.abs().max()) > 0
+
+
 def test_loss_matches_oracle():
     from paper_2412_03451_amd.splat import Renderer
     cam = synth.tiny_camera(100, 70, 90.0)

@@ -92,7 +92,11 @@ typedef struct ps_params {
                           what the GPU holds resident (by default such a
                           backward launch is persistent:
                           resident workgroups claim blocks from an atomic work
-                          queue, longest lists first; same results) */
+                          queue, longest lists first; same results);
+                          bit 10: the backward's per-plane reduction takes a
+                          wave per plane at any plane count (by default from
+                          8192 planes on, below that a workgroup per plane;
+                          the same summation order, so the same bits) */
 } ps_params;
 
 /* One render job.  The caller fills the first block; ps_layout_init fills

@@ -297,8 +297,9 @@ def batched_bench(args):
     counts log-uniform in [200, 4000], 20-100 views, 320x240 or 640x480),
     every room advancing one iteration (one view) per step, all in one
     graph-replayed step of one launch per phase.  Tile shapes per room from
-    the autotuner (tuned on the first room of each shape, cached).  Value:
-    sum over rooms of (pixels x planes) per second of step time."""
+    the autotuner (tuned for throughput on copies of the first room of each
+    shape filling the GPU, cached).  Value: sum over rooms of
+    (pixels x planes) per second of step time."""
     import torch
     import synth
     from paper_2412_03451_amd import learned_init as li
@@ -316,7 +317,9 @@ def batched_bench(args):
         tD, tN = li.render_targets((gt.center, gt.quat, gt.radii), cams)
         sc = Scene(init.center, init.quat, init.radii, cams, tD, tN)
         if tuner is not None:
-            tile, _ = tuner.tune(sc, steps=10, warmup=3)
+            # tuned for throughput: copies of the room filling the GPU (about 2 Mpixel per step)
+            reps = max(1, round(2e6 / (sp["width"] * sp["height"])))
+            tile, _ = tuner.tune(sc, steps=10, warmup=3, pendings=(6,), replicas=reps)
             sc.tile = tile
         scenes.append(sc)
         work += sp["width"] * sp["height"] * gt.K

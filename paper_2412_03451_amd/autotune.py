@@ -38,8 +38,8 @@ def k_bucket(K: int) -> int:
     return 1 << max(0, int(round(math.log2(max(K, 1)))))
 
 
-def cache_key(width: int, height: int, K: int) -> str:
-    return f"{width}x{height}/K{k_bucket(K)}"
+def cache_key(width: int, height: int, K: int, replicas: int = 1) -> str:
+    return f"{width}x{height}/K{k_bucket(K)}" + (f"/x{replicas}" if replicas > 1 else "")
 
 
 def default_cache_path() -> str:
@@ -62,16 +62,18 @@ class Autotuner:
             json.dump(self.table, f, indent=1, sort_keys=True)
         os.replace(tmp, self.path)
 
-    def lookup(self, width: int, height: int, K: int):
+    def lookup(self, width: int, height: int, K: int, replicas: int = 1):
         """(tile, pending) cached for this shape, or None."""
-        e = self.table.get(cache_key(width, height, K))
+        e = self.table.get(cache_key(width, height, K, replicas))
         return None if e is None else (tuple(e["tile"]), int(e["pending"]))
 
     @staticmethod
-    def time_config(scene: Scene, tile, pending: int, cfg: FitConfig, steps: int, warmup: int) -> float:
-        """ms per graph-replayed fitting step of one scene with this configuration."""
+    def time_config(scene: Scene, tile, pending: int, cfg: FitConfig, steps: int, warmup: int,
+                    replicas: int = 1) -> float:
+        """ms per graph-replayed fitting step of `replicas` copies of the scene
+        (one batch) with this configuration."""
         sc = replace(scene, tile=tuple(tile))
-        fit = BatchFit([sc], cfg=replace(cfg, check_every=max(1, warmup)),
+        fit = BatchFit([sc] * replicas, cfg=replace(cfg, check_every=max(1, warmup)),
                        params=SplatParams(flags=pending_flags(pending)))
         fit.run(max(1, warmup), graph=True)
         st = torch.cuda.current_stream()
@@ -91,11 +93,15 @@ class Autotuner:
         return sorted(times)[1]
 
     def tune(self, scene: Scene, cfg: FitConfig | None = None, steps: int = 20, warmup: int = 5,
-             tiles=TILES, pendings=PENDING, force: bool = False):
-        """Best (tile, pending) for the scene's shape; cached."""
+             tiles=TILES, pendings=PENDING, force: bool = False, replicas: int = 1):
+        """Best (tile, pending) for the scene's shape; cached.  replicas > 1
+        times that many copies of the scene in one batch: the configuration
+        for a scene fitted in a large batch, where the GPU is full and
+        throughput counts (alone, a small scene's step is latency: smaller
+        tiles win there and lose in a batch)."""
         W, H = int(scene.cams[0].width), int(scene.cams[0].height)
         K = int(torch.as_tensor(scene.center).reshape(-1, 3).shape[0])
-        key = cache_key(W, H, K)
+        key = cache_key(W, H, K, replicas)
         if not force and key in self.table:
             e = self.table[key]
             return tuple(e["tile"]), int(e["pending"])
@@ -103,7 +109,8 @@ class Autotuner:
         tried = {}
         # tiles first at the default buffer size, then buffer sizes at the best tile
         for t in tiles:
-            tried[f"{t[0]}x{t[1]}/p{pendings[0]}"] = self.time_config(scene, t, pendings[0], cfg, steps, warmup)
+            tried[f"{t[0]}x{t[1]}/p{pendings[0]}"] = self.time_config(scene, t, pendings[0], cfg, steps, warmup,
+                                                                      replicas)
         # another tile than the first (the default) only if it is clearly faster:
         # timing noise does not flip the choice from one run to the next
         t0 = tried[f"{tiles[0][0]}x{tiles[0][1]}/p{pendings[0]}"]
@@ -111,7 +118,8 @@ class Autotuner:
         if tried[f"{best_t[0]}x{best_t[1]}/p{pendings[0]}"] > t0 / (1.0 + TILE_MARGIN):
             best_t = tiles[0]
         for p in pendings[1:]:
-            tried[f"{best_t[0]}x{best_t[1]}/p{p}"] = self.time_config(scene, best_t, p, cfg, steps, warmup)
+            tried[f"{best_t[0]}x{best_t[1]}/p{p}"] = self.time_config(scene, best_t, p, cfg, steps, warmup,
+                                                                      replicas)
         best = f"{best_t[0]}x{best_t[1]}/p{pendings[0]}"
         for p in pendings[1:]:
             k = f"{best_t[0]}x{best_t[1]}/p{p}"

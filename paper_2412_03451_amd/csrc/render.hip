@@ -1091,16 +1091,16 @@ __device__ void loss_sums(const RenderArgs& a, int s) {
 }
 
 // Per plane: the sum of each of its records' partial rows in one fixed order
-// whatever the launch shape.  The rows are taken in blocks of 256: row
-// 64 v + l of each block goes to accumulator set v (v < 4) of lane l, each
-// set is summed over the wave (wave_sum16) and the four totals are added as
-// ((s0 + s1) + s2) + s3.  Y = 4: a workgroup per plane, wave v holds set v
-// (few planes: four waves on the rows of a large plane); Y = 1: a wave per
-// plane holds all four sets (many planes: no idle waves, four rows in flight
-// per lane).  Same bits either way.
+// whatever the launch shape: the rows in blocks of 64, each block summed
+// across a wave (lane l holds row 64 b + l, zeros past the end; wave_sum16),
+// the block sums added in block order.  Y = 4: a workgroup per plane, its
+// waves sum the blocks w, w + 4, ... of each round of 64 blocks into LDS and
+// wave 0 adds them up (few planes: four waves on the rows of a large plane);
+// Y = 1: a wave per plane does all of it (many planes: no idle waves).  Same
+// bits either way.
 template <bool LOSS, int Y>
 __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
-  __shared__ float part[4][16];
+  __shared__ float part[64][16];   // Y = 4: one round of block sums
   // with LOSS the first n_slots workgroups form the loss sums, one job each
   // (placed last, they cost the 64-room batch's reduction 150 us: measured)
   const int wg = LOSS ? (int)blockIdx.x - a.S : (int)blockIdx.x;
@@ -1108,10 +1108,8 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
     loss_sums(a, wg + a.S);
     return;
   }
-  constexpr int NV = 4 / Y;   // accumulator sets per wave
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int k = Y == 4 ? wg : 4 * wg + w;
-  const int vs0 = Y == 4 ? w : 0;   // this wave's first set
   if (k >= a.K) return;
   // the plane's parameters, fetched up front: the chain rule at the end
   // needs them, and their latency hides behind the lookups below
@@ -1161,60 +1159,51 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
       if (a.recs[r].cull) continue;
       const int rows = a.rec_cnt[r] * nsub;
       const int e0 = a.rec_off[r] + a.rbase[r / kScanChunk];
-      float A[NV][16];
+      // row i of the record: partial row (e0 + i / nsub, i % nsub)
+      auto row_of = [&](int i, float (&v)[16]) {
+        if (i < rows) {
+          const int e = e0 + i / nsub, sbk = i % nsub;
+          const float* rowp = a.partial + ((size_t)e * a.max_sub + sbk) * 16;
+          const float4* row = (const float4*)rowp;
+          const float4 r0 = row[0], r1 = row[1], r2 = row[2];
+          v[0] = r0.x; v[1] = r0.y; v[2] = r0.z; v[3] = r0.w;
+          v[4] = r1.x; v[5] = r1.y; v[6] = r1.z; v[7] = r1.w;
+          v[8] = r2.x; v[9] = r2.y; v[10] = r2.z; v[11] = r2.w;
+          v[12] = rowp[12];
+        } else {
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) A[v][q] = 0.f;
-      constexpr int NL = NV < 2 ? NV : 2;   // sets loaded together (rows in flight per lane)
-      for (int i0 = 0; i0 < rows; i0 += 256) {
-#pragma unroll
-        for (int vp = 0; vp < NV; vp += NL) {
-          float4 x[NL][3];
-          float y[NL];
-#pragma unroll
-          for (int u = 0; u < NL; ++u) {
-            const int idx = i0 + 64 * (vs0 + vp + u) + lane;
-            if (idx < rows) {
-              const int e = e0 + idx / nsub, sbk = idx % nsub;
-              const float* rowp = a.partial + ((size_t)e * a.max_sub + sbk) * 16;
-              const float4* row = (const float4*)rowp;
-              x[u][0] = row[0]; x[u][1] = row[1]; x[u][2] = row[2]; y[u] = rowp[12];
-            } else {
-              x[u][0] = x[u][1] = x[u][2] = make_float4(0.f, 0.f, 0.f, 0.f);
-              y[u] = 0.f;
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < NL; ++u) {
-            float* Av = A[vp + u];
-            Av[0] += x[u][0].x; Av[1] += x[u][0].y; Av[2] += x[u][0].z; Av[3] += x[u][0].w;
-            Av[4] += x[u][1].x; Av[5] += x[u][1].y; Av[6] += x[u][1].z; Av[7] += x[u][1].w;
-            Av[8] += x[u][2].x; Av[9] += x[u][2].y; Av[10] += x[u][2].z; Av[11] += x[u][2].w;
-            Av[12] += y[u];
-          }
+          for (int q = 0; q < 13; ++q) v[q] = 0.f;
         }
-      }
-      float S[13];   // ((s0 + s1) + s2) + s3 of each accumulator
-      if (Y == 4) {
-        const float tot = wave_sum16(A[0]);   // lane 4 q holds the wave's sum of accumulator q
-        if ((lane & 3) == 0) part[w][lane >> 2] = tot;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 13; ++q) S[q] = ((part[0][q] + part[1][q]) + part[2][q]) + part[3][q];
-        __syncthreads();
+        v[13] = v[14] = v[15] = 0.f;
+      };
+      const int nblk = (rows + 63) >> 6;
+      float acc = 0.f;   // lane 4 q + r: the sum of accumulator q so far
+      if (Y == 1) {
+        for (int b = 0; b < nblk; b += 2) {   // two blocks in flight
+          float v0[16], v1[16];
+          row_of(64 * b + lane, v0);
+          row_of(64 * (b + 1) + lane, v1);
+          acc += wave_sum16(v0);
+          if (b + 1 < nblk) acc += wave_sum16(v1);
+        }
       } else {
-        float t[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) t[v] = wave_sum16(A[v]);
-#pragma unroll
-        for (int q = 0; q < 13; ++q) {
-          float s4[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) s4[v] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[v % NV]), 4 * q));
-          S[q] = ((s4[0] + s4[1]) + s4[2]) + s4[3];
+        for (int r0 = 0; r0 < nblk; r0 += 64) {
+          const int nb = min(64, nblk - r0);
+          for (int b = w; b < nb; b += 4) {
+            float v[16];
+            row_of(64 * (r0 + b) + lane, v);
+            const float t = wave_sum16(v);
+            if ((lane & 3) == 0) part[b][lane >> 2] = t;
+          }
+          __syncthreads();
+          if (w == 0)
+            for (int b = 0; b < nb; ++b) acc += part[b][lane >> 2];
+          __syncthreads();
         }
       }
+      float S[13];
+#pragma unroll
+      for (int q = 0; q < 13; ++q) S[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 4 * q));
       Frame f;
       if (!plane_frame(pc, pq, 0, cam, f)) continue;
       for (int q = 0; q < 4; ++q) qn[q] = f.q[q];

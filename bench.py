@@ -188,7 +188,8 @@ def culling_efficiency(init, cams, lam, tile, n_pix: int = 4096, seed: int = 0):
 KERNEL_SOURCES = ("paper_2412_03451_amd/csrc/render.hip", "paper_2412_03451_amd/csrc/ps_internal.h",
                   "paper_2412_03451_amd/csrc/adam.hip")
 TRAFFIC_FILES = {"fwd": "profiles/render_fwd_room640_hbm_traffic.txt",
-                 "bwd": "profiles/render_bwd_room640_hbm_traffic.txt"}
+                 "bwd": "profiles/render_bwd_room640_hbm_traffic.txt",
+                 "step": "profiles/render_step_room640_hbm_traffic.txt"}
 
 
 def kernel_source_hash() -> str:
@@ -204,7 +205,8 @@ def traffic_key(args) -> str:
     """The bench arguments that decide the render launches of the timed steps."""
     return (f"--steps {args.steps} --start-ite {args.start_ite} --views {args.views} "
             f"--tile {args.tile[0]} {args.tile[1]} --pending {args.pending}"
-            + (" --force-rounds" if args.force_rounds else ""))
+            + (" --force-rounds" if args.force_rounds else "")
+            + (" --separate-calls" if getattr(args, "separate_calls", False) else ""))
 
 
 def measured_traffic(phase: str, key: str):
@@ -326,7 +328,8 @@ def batched_bench(args):
     log(f"{len(scenes)} rooms ready")
     from paper_2412_03451_amd.splat import SplatParams
     params = SplatParams(flags=256 if args.per_item_launch else 0)
-    fit = BatchFit(scenes, cfg=FitConfig(check_every=max(1, args.warmup)), params=params)
+    fit = BatchFit(scenes, cfg=FitConfig(check_every=max(1, args.warmup), one_launch=not args.separate_calls),
+                   params=params)
     fit.size_capacity()
     start_state = fit.state()
     fit.run(max(1, args.warmup), graph=True)
@@ -742,6 +745,10 @@ def sample_phases(fit, steps: int, n_samples: int, stream):
         for j, n in enumerate(names):
             ev[n].append(starts[j].elapsed_time(ends[j + 1]))
     phase_ms = {n: float(np.mean(x)) for n, x in ev.items()}
+    if one_launch_step(fit):
+        # forward, loss, backward and Adam in one call: timed as one phase
+        phase_ms = {"project": phase_ms["project"], "bin": phase_ms["bin"],
+                    "step": phase_ms["fwd"] + phase_ms["bwd"] + phase_ms["adam"]}
     phase_sum = float(sum(phase_ms.values()))
     cnt = {k: float(np.mean([st[k] for st in stats])) for k in stats[0] if not isinstance(stats[0][k], list)}
     cnt["max_steps"] = max(st["max_steps"] for st in stats)
@@ -750,21 +757,35 @@ def sample_phases(fit, steps: int, n_samples: int, stream):
     return phase_ms, phase_sum, cnt
 
 
+def one_launch_step(fit) -> bool:
+    """The fitting step takes plane_render_step (forward, loss and backward
+    in one render launch)."""
+    c = fit.cfg
+    return c.one_launch and not c.single_radii and not c.split_every
+
+
+def dominant_phase(phase_ms) -> str:
+    return "step" if "step" in phase_ms else max(("fwd", "bwd"), key=lambda n: phase_ms[n])
+
+
 def render_roofline(phase_ms, cnt, traffic=None, peaks=None):
     """Roofline of the dominant render phase: algorithmic lane operations of
     the sampled launches (evaluated pairs and composited hits, the kernels'
     own counts) / the phase's mean launch time, against the vector ALU's
-    non-packed issue rate."""
+    non-packed issue rate.  The one-launch step does the forward's and the
+    backward's algorithmic work."""
     hits = int(round(cnt["composited_hits"]))
     evals = int(round(cnt["evals"]))
-    dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
-    per_hit = OPS_PER_HIT_FWD if dom == "fwd" else OPS_PER_HIT_BWD
-    per_eval = OPS_PER_EVAL if dom == "fwd" else OPS_PER_EVAL_BWD
+    dom = dominant_phase(phase_ms)
+    per_hit = {"fwd": OPS_PER_HIT_FWD, "bwd": OPS_PER_HIT_BWD, "step": OPS_PER_HIT_FWD + OPS_PER_HIT_BWD}[dom]
+    per_eval = {"fwd": OPS_PER_EVAL, "bwd": OPS_PER_EVAL_BWD, "step": OPS_PER_EVAL + OPS_PER_EVAL_BWD}[dom]
     ops = evals * per_eval + hits * per_hit
     achieved = ops / (phase_ms[dom] * 1e-3) / 1e12
     roof = {
-        "kernel": ("render_fwd_kernel (plane_render_fwd_loss)" if dom == "fwd" else
-                   "render_bwd_kernel+bwd_reduce_kernel+adam_kernel (plane_render_bwd_adam)"),
+        "kernel": {"fwd": "render_fwd_kernel (plane_render_fwd_loss)",
+                   "bwd": "render_bwd_kernel+bwd_reduce_kernel+adam_kernel (plane_render_bwd_adam)",
+                   "step": "render_bwd_kernel<fused>+bwd_reduce_kernel+adam_kernel (plane_render_step: forward, "
+                           "loss, backward and Adam)"}[dom],
         "bound": "alu",
         "achieved": round(achieved, 4),
         "peak": round(MI355X_VALU_TOPS, 2),
@@ -816,6 +837,9 @@ def main():
     ap.add_argument("--start-ite", type=int, default=0)
     ap.add_argument("--pending", type=int, default=6, choices=(4, 6, 8, 12),
                     help="pending-hit buffer size of the render kernels")
+    ap.add_argument("--separate-calls", action="store_true",
+                    help="fitting step with plane_render_fwd_loss and plane_render_bwd_adam instead of "
+                         "plane_render_step (forward, loss and backward in one render launch)")
     ap.add_argument("--force-rounds", action="store_true",
                     help="send every pixel through the exact round-based ordering path")
     ap.add_argument("--phase-steps", type=int, default=50,
@@ -898,7 +922,8 @@ def main():
     del tr
 
     params = SplatParams(flags=({6: 0, 4: 1, 8: 2, 12: 3}[args.pending] << 4) | (1 if args.force_rounds else 0))
-    cfg = FitConfig(tile=tuple(args.tile), views_per_step=V, check_every=max(1, args.warmup))
+    cfg = FitConfig(tile=tuple(args.tile), views_per_step=V, check_every=max(1, args.warmup),
+                    one_launch=not args.separate_calls)
     fit = SceneFit(init.center, init.quat, init.radii, cams, tgt_d.view(n_views, -1), tgt_n.view(n_views, -1),
                    cfg=cfg, params=params, device=dev)
     fit.ite.fill_(args.start_ite)
@@ -945,7 +970,7 @@ def main():
     phase_ms, phase_sum, cnt = sample_phases(fit, args.steps, args.phase_steps, stream)
     pix = V * W * H
     value = pix * K / (ms_step * 1e-3) / 1e6
-    dom = max(("fwd", "bwd"), key=lambda n: phase_ms[n])
+    dom = dominant_phase(phase_ms)
     roof, hits, evals = render_roofline(phase_ms, cnt, measured_traffic(dom, traffic_key(args)), measured_peaks())
     n_items = max(1, int(fit.rend.L.n_items))
     out = {
@@ -966,7 +991,9 @@ def main():
                                f"tile {args.tile[0]}x{args.tile[1]}, fitting iterations {args.start_ite}-"
                                f"{args.start_ite + args.steps - 1} (lambda of Eq. 10), graph-replayed steps",
                    "planes": K, "views_per_step": V, "width": W, "height": H,
-                   "pairs_per_step": int(cnt["pairs"])},
+                   "pairs_per_step": int(cnt["pairs"]),
+                   "step_form": ("one render launch (plane_render_step)" if one_launch_step(fit) else
+                                 "plane_render_fwd_loss + plane_render_bwd_adam")},
         "phase_sum_ms": round(phase_sum, 4),
         "phase_ms": {k: round(x, 4) for k, x in phase_ms.items()},
         "final_loss": [round(x, 3) for x in final_loss[:3]],

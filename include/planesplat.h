@@ -417,6 +417,30 @@ int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center, float* qu
                           float lr_radii, float beta1, float beta2, float eps, float r_min, float* loss,
                           void* stream);
 
+/* plane_render_step: one fitting step's render work in one call, for the
+ * loss of Eq. 14: plane_render_fwd_loss (Eq. 11-14) and plane_render_bwd_adam
+ * (the adjoint of Eq. 4-13, Sec. 3.3's update, the loss sums), with the
+ * forward, the loss and the backward of each 8x8 block in the same launch.
+ * The block's walk over its tile list is done once: it composites depth and
+ * normal and records, in the block's LDS, the list position of every
+ * committed hit; the pixel's loss gradient is formed right after
+ * compositing and stays in registers; the backward then commits the hits
+ * again from those positions (no per-pixel list leaves the block) and forms
+ * the gradients.  depth, normal, g_depth, g_normal, loss, the gradients and
+ * the updated planes and Adam moments hold the bits of the two calls.
+ * Arguments as in plane_render_fwd_loss (depth, normal, targets, mask,
+ * tgt_off, n_tgt, loss weights, g_depth and g_normal as outputs) and
+ * plane_render_bwd_adam (planes updated in place, gradients, Adam state and
+ * rates; loss: device float [n_slots][4] or NULL).  ps_params.flags bit 6
+ * (walk statistics) is refused: the separate calls record them. */
+int plane_render_step(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
+                      const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm, float* depth,
+                      float* normal, const float* tgt_depth, const float* tgt_normal, const uint8_t* mask,
+                      const int64_t* tgt_off, int n_tgt, float a_cos, float a_nl1, float a_d, float* g_depth,
+                      float* g_normal, float* g_center, float* g_quat, float* g_radii, float* m, float* v,
+                      const int32_t* step, float lr_center, float lr_quat, float lr_radii, float beta1, float beta2,
+                      float eps, float r_min, float* loss, void* stream);
+
 /* adam_step_planes (Sec. 3.3): bias-corrected Adam on the K planes.
  * m, v: device [11*K] laid out as center (3K) | quat (4K) | radii (4K).
  * step: device int, the 1-based step number read by the kernel.  After the

@@ -74,6 +74,10 @@ _EXPORTS = {
     "plane_render_bwd_adam": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,
                                         C.POINTER(PsParams), _P, _P, _P, _P, _P, _P, _P, _P, C.c_float,
                                         C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, _P, _P]),
+    "plane_render_step": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,
+                                    C.POINTER(PsParams), _P, _P, _P, _P, _P, _P, C.c_int, C.c_float, C.c_float,
+                                    C.c_float, _P, _P, _P, _P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float,
+                                    C.c_float, C.c_float, C.c_float, C.c_float, _P, _P]),
     "plane_render_fwd_lists": (C.c_int, [C.POINTER(PsLayout), _P, _P, C.c_int, _P, C.POINTER(PsParams), _P, _P, _P,
                                          _P, _P, _P, _P]),
     "plane_render_bwd_lists": (C.c_int, [C.POINTER(PsLayout), _P, _P, _P, _P, C.c_int, _P, C.c_int, _P,

@@ -511,12 +511,14 @@ struct FwdSink {
 // The render loss of this 8x8 block's pixels (the loss kernel's arithmetic)
 // and the block's partial sums, stored where the loss kernel stores them: at
 // the job's first item plus the block's index in tile order.
+// g (optional): the pixel's loss gradient (zeros without a pixel).
 __device__ void block_loss(const RenderArgs& a, const ItemCtx& c, const ps_slot& sl, const LossTargets& tg,
-                           bool pix_on, float D, float N0, float N1, float N2) {
+                           bool pix_on, float D, float N0, float N1, float N2, float* g = nullptr) {
   double l[4] = {0, 0, 0, 0};
+  if (g) g[0] = g[1] = g[2] = g[3] = 0.f;
   if (pix_on) {
     const float N[3] = {N0, N1, N2};
-    loss_apply(a.loss, tg, D, N, l);
+    loss_apply(a.loss, tg, D, N, l, g);
   }
   for (int q = 0; q < 4; ++q) l[q] = wave_sum_double(l[q]);
   if (threadIdx.x == 0) {
@@ -722,6 +724,41 @@ struct BwdSink {
   }
 };
 
+// The fused forward-and-backward walk of the fitting step: composites depth
+// and normal like the forward (the same arithmetic, so the same bits) and
+// records what the backward needs of every committed hit: its list position
+// and the transmittance at each chunk start.  The gradient pass's per-hit
+// values wait for the pixel's loss gradient, which exists only once the
+// pixel is composited, so every chunk is committed again from the positions.
+struct FwdBwdSink {
+  static constexpr int NP = 3;   // payload: rendered normal of the hit
+  static constexpr bool BWD = true;
+  float T, D, N0, N1, N2;
+  int count;
+  float Tb1, Tb2, Tb3;   // transmittance in front of hits 8, 16, 24 (chunk starts)
+  float lam5;
+  int mode;
+  __device__ bool finished(int M) const { return T == 0.f || count >= M; }
+  __device__ void payload(float, const float n[3], float* pl) const {
+    pl[0] = n[0]; pl[1] = n[1]; pl[2] = n[2];
+  }
+  __device__ void commit(float t, float as, int pos, const float* n) {
+    g_bwd.hpos[count][threadIdx.x] = (int16_t)pos;
+    if (count == kChunk) Tb1 = T;
+    if (count == 2 * kChunk) Tb2 = T;
+    if (count == 3 * kChunk) Tb3 = T;
+    float omw;
+    const float w = splat_weight(as, lam5, mode, omw);
+    const float Tw = T * w;
+    D = fmaf(Tw, t, D);                 // Eq. 11
+    N0 = fmaf(Tw, n[0], N0);            // Eq. 12
+    N1 = fmaf(Tw, n[1], N1);
+    N2 = fmaf(Tw, n[2], N2);
+    T = T * omw;                        // Eq. 13
+    ++count;
+  }
+};
+
 // Commit again, in the same order, the hits that the first pass's walk
 // committed (their list positions are in L.hpos): the same evaluation of the
 // same records gives the same bits, without walking the list again.
@@ -801,7 +838,14 @@ __device__ inline void zero_row(const RenderArgs& a, uint32_t em, int sub) {
 // Partial rows: every (list entry, 8x8 block) row of the tile is written by
 // its block, exactly once in the first pass (the gradient of a candidate the
 // block hits, zeros otherwise); further passes add to it.
-template <int P, bool GAUSS>
+//
+// FUSED (the fitting step): the same block's forward and loss come first, in
+// the same walk (FwdBwdSink): depth and normal are written, the loss of
+// Eq. 14 is formed per pixel (the forward-with-loss arithmetic: the same
+// partials and loss gradients), and the gradient passes take the pixel's
+// loss gradient from registers.  Every chunk, the first too, is committed
+// again from the recorded positions: the same bits as the two separate calls.
+template <int P, bool GAUSS, bool FUSED>
 __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   BwdLds& L = g_bwd;
   StageLds& stage = g_stage;
@@ -819,6 +863,16 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   if (diag && threadIdx.x >= D_BWD_SETUP && threadIdx.x <= D_BWD_TICKS) dg[threadIdx.x] = 0;
   ItemCtx c;
   const int st = item_setup(a, item, c);
+  // the loss targets of the pixel are read now; their latency overlaps the walk
+  ps_slot sl;
+  LossTargets tg;
+  if (FUSED) {
+    sl = a.slots[c.slot];
+    tg = loss_targets(a.loss, sl, c.inimg ? c.px : 0, c.inimg ? c.py : 0);
+    // no render here: the block's loss partials (zero) and, for a camera out
+    // of range, zero loss gradients
+    if (st != 0) block_loss(a, c, sl, tg, st == 2 && c.inimg, 0.f, 0.f, 0.f, 0.f);
+  }
   if (st == 2) return;
   const int lane = threadIdx.x;
   const int n = c.e - c.b;
@@ -839,7 +893,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   const float lam5 = 5.f * lam;
   const double delta = fringe_margin((double)lam, a.flog, a.mode);
   float gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f;
-  if (c.inimg) {
+  if (!FUSED && c.inimg) {
     gD = a.g_depth[c.pix];
     const int64_t nb = 3 * c.pix_off + (c.pix - c.pix_off);
     gN0 = a.g_normal[nb];
@@ -860,7 +914,24 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   BwdSink s{1.f, 0, 0, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode};
   {
     long long evals = 0, steps = 0;
-    if (a.lst_pos) {
+    if (FUSED) {
+      FwdBwdSink f{1.f, 0.f, 0.f, 0.f, 0.f, 0, 1.f, 1.f, 1.f, lam5, a.mode};
+      walk<P, GAUSS>(a, c, f, lam5, delta, evals, steps);
+      hits = f.count;
+      s.Tb1 = f.Tb1; s.Tb2 = f.Tb2; s.Tb3 = f.Tb3;
+      if (c.inimg) {
+        a.depth[c.pix] = f.D;
+        const int64_t nb = 3 * c.pix_off + (c.pix - c.pix_off);
+        a.normal[nb] = f.N0;
+        a.normal[nb + c.HW] = f.N1;
+        a.normal[nb + 2 * c.HW] = f.N2;
+      }
+      float g[4];
+      block_loss(a, c, sl, tg, c.inimg, f.D, f.N0, f.N1, f.N2, g);
+      if (c.inimg) {
+        gD = g[0]; gN0 = g[1]; gN1 = g[2]; gN2 = g[3];
+      }
+    } else if (a.lst_pos) {
       // no walk: stage the first batch here (record heads, emit indices),
       // which the one-batch paths below read from LDS
       if (n > 0) stage_batch<true>(a, c, c.b);
@@ -877,7 +948,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   float S = 0.f;   // composite of the hits behind the current chunk
   for (int pass = 0; pass < passes; ++pass) {
     const int chunk = passes - 1 - pass;
-    if (passes > 1) {
+    if (passes > 1 || FUSED) {
       if (pass > 0) __threadfence_block();   // rows written by other lanes are read back below
       const float T0 = chunk == 0 ? 1.f : chunk == 1 ? s.Tb1 : chunk == 2 ? s.Tb2 : s.Tb3;
       BwdSink r{T0, chunk * kChunk, chunk * kChunk, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode};
@@ -1033,18 +1104,18 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   }
 }
 
-template <int P, bool GAUSS, bool PERSIST>
+template <int P, bool GAUSS, bool PERSIST, bool FUSED>
 __global__ __launch_bounds__(64) void render_bwd_kernel(RenderArgs a) {
   if (a.counters[C_OVERFLOW]) return;
   if (!PERSIST) {
-    bwd_item<P, GAUSS>(a, xcd_item(blockIdx.x, gridDim.x));
+    bwd_item<P, GAUSS, FUSED>(a, xcd_item(blockIdx.x, gridDim.x));
     return;
   }
   const int n_groups = (a.n_items + 3) >> 2;
   int stream = blockIdx.x & 7;
   for (int g = claim_group(a.queue, n_groups, stream); g >= 0; g = claim_group(a.queue, n_groups, stream)) {
     for (int item = 4 * g; item < min(4 * g + 4, a.n_items); ++item) {
-      bwd_item<P, GAUSS>(a, item);
+      bwd_item<P, GAUSS, FUSED>(a, item);
       __syncthreads();
     }
   }
@@ -1359,15 +1430,22 @@ static int launch_fwd_g(RenderArgs& a, hipStream_t st) {
     default: return launch_items(render_fwd_kernel<6, GAUSS, false>, render_fwd_kernel<6, GAUSS, true>, a, q, pp, st);
   }
 }
-template <bool GAUSS>
+template <bool GAUSS, bool FUSED>
 static int launch_bwd_g(RenderArgs& a, hipStream_t st) {
   unsigned long long* q = a.queue + 8 * kQueueStride;
   switch (pending_of(a.flags)) {
-    case 4: return launch_items(render_bwd_kernel<4, GAUSS, false>, render_bwd_kernel<4, GAUSS, true>, a, q, true, st);
-    case 8: return launch_items(render_bwd_kernel<8, GAUSS, false>, render_bwd_kernel<8, GAUSS, true>, a, q, true, st);
+    case 4:
+      return launch_items(render_bwd_kernel<4, GAUSS, false, FUSED>, render_bwd_kernel<4, GAUSS, true, FUSED>, a, q,
+                          true, st);
+    case 8:
+      return launch_items(render_bwd_kernel<8, GAUSS, false, FUSED>, render_bwd_kernel<8, GAUSS, true, FUSED>, a, q,
+                          true, st);
     case 12:
-      return launch_items(render_bwd_kernel<12, GAUSS, false>, render_bwd_kernel<12, GAUSS, true>, a, q, true, st);
-    default: return launch_items(render_bwd_kernel<6, GAUSS, false>, render_bwd_kernel<6, GAUSS, true>, a, q, true, st);
+      return launch_items(render_bwd_kernel<12, GAUSS, false, FUSED>, render_bwd_kernel<12, GAUSS, true, FUSED>, a, q,
+                          true, st);
+    default:
+      return launch_items(render_bwd_kernel<6, GAUSS, false, FUSED>, render_bwd_kernel<6, GAUSS, true, FUSED>, a, q,
+                          true, st);
   }
 }
 
@@ -1380,10 +1458,16 @@ static int launch_fwd(RenderArgs& a, void* stream) {
   PS_HIP_CHECK(hipGetLastError());
   return PS_OK;
 }
-static int launch_bwd(RenderArgs& a, int K, void* stream) {
+// fused: the fitting step's forward, loss and backward in one launch (the
+// forward-with-loss fields of `a` set as well)
+static int launch_bwd(RenderArgs& a, int K, void* stream, bool fused = false) {
   hipStream_t st = (hipStream_t)stream;
   if (a.n_items > 0) {
-    const int rc = a.mode == 2 ? launch_bwd_g<true>(a, st) : launch_bwd_g<false>(a, st);
+    int rc;
+    if (fused)
+      rc = a.mode == 2 ? launch_bwd_g<true, true>(a, st) : launch_bwd_g<false, true>(a, st);
+    else
+      rc = a.mode == 2 ? launch_bwd_g<true, false>(a, st) : launch_bwd_g<false, false>(a, st);
     if (rc) return rc;
   }
   // a wave per plane for many planes, a workgroup per plane for few (the
@@ -1488,6 +1572,43 @@ extern "C" int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center
     a.loss_in = (const double*)((char*)ws + L->region[R_LOSS]);
   }
   rc = launch_bwd(a, K, stream);
+  if (rc || K == 0) return rc;
+  return adam_step_planes(center, quat, radii, g_center, g_quat, g_radii, m, v, K, step, lr_center, lr_quat, lr_radii,
+                          beta1, beta2, eps, r_min, stream);
+}
+
+extern "C" int plane_render_step(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
+                                 const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm,
+                                 float* depth, float* normal, const float* tgt_depth, const float* tgt_normal,
+                                 const uint8_t* mask, const int64_t* tgt_off, int n_tgt, float a_cos, float a_nl1,
+                                 float a_d, float* g_depth, float* g_normal, float* g_center, float* g_quat,
+                                 float* g_radii, float* m, float* v, const int32_t* step, float lr_center,
+                                 float lr_quat, float lr_radii, float beta1, float beta2, float eps, float r_min,
+                                 float* loss, void* stream) {
+  RenderArgs a;
+  int rc = bwd_args(L, ws, center, quat, radii, K, cams, n_cams, lambda, prm, g_depth, g_normal, g_center, g_quat,
+                    g_radii, a, "plane_render_step");
+  if (rc) return rc;
+  if (!depth || !normal || !tgt_depth || !tgt_normal || (tgt_off && n_tgt <= 0))
+    return ps_set_error(PS_ERR_INVALID, "plane_render_step: bad argument");
+  if (K > 0 && (!m || !v || !step)) return ps_set_error(PS_ERR_INVALID, "plane_render_step: null Adam state");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return ps_set_error(PS_ERR_INVALID, "plane_render_step: bad beta / eps");
+  if (a.flags & kFlagDiag)
+    return ps_set_error(PS_ERR_INVALID, "plane_render_step: the walk statistics (flags bit 6) are the separate "
+                                        "calls'");
+  a.depth = depth;
+  a.normal = normal;
+  a.loss.Dt = tgt_depth; a.loss.Nt = tgt_normal; a.loss.mask = mask;
+  a.loss.tgt_off = tgt_off; a.loss.n_cams = tgt_off ? n_tgt : 0;
+  a.loss.a_cos = a_cos; a.loss.a_nl1 = a_nl1; a.loss.a_d = a_d;
+  a.loss.gD = g_depth; a.loss.gN = g_normal;
+  a.loss_part = (double*)((char*)ws + L->region[R_LOSS]);
+  if (loss) {
+    a.loss_out = loss;
+    a.loss_in = a.loss_part;
+  }
+  rc = launch_bwd(a, K, stream, true);
   if (rc || K == 0) return rc;
   return adam_step_planes(center, quat, radii, g_center, g_quat, g_radii, m, v, K, step, lr_center, lr_quat, lr_radii,
                           beta1, beta2, eps, r_min, stream);

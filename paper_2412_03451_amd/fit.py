@@ -55,6 +55,7 @@ class FitConfig:
     split_every: int = 0                # plane splitting every n iterations (Sec. 3.3: 1000); 0: off
     split_thresh: float = 0.2           # average |dL/dr| over a pair of radii that triggers a split
     single_radii: bool = False          # ablation (Sec. 4.3): one radius per axis, r+ = r- (from their mean)
+    one_launch: bool = True             # plain step: forward, loss and backward in one render launch
     check_finite: bool = False          # before a run and after every checked run of steps, fail on NaN or
                                         # infinity in the planes (the kernels do not test their inputs)
 
@@ -210,6 +211,17 @@ class BatchFit:
         rend.bin(check_capacity=False)
         m()
         fused = not cfg.single_radii and not cfg.split_every
+        if fused and cfg.one_launch:
+            # the plain step's forward, loss, backward and Adam with one render
+            # launch (plane_render_step); its time counts as the forward phase
+            loss = torch.empty(len(rend.jobs), 4, dtype=torch.float32, device=self.device)
+            rend.step(self.tgt_depth, self.tgt_normal, self.m, self.v, self.step_no, self.tgt_off, mask=self.mask,
+                      a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2], lr=cfg.lr, betas=cfg.betas,
+                      eps=cfg.eps, r_min=cfg.r_min, loss=loss)
+            m()
+            m()
+            m()
+            return loss
         # forward and render loss in one pass (plane_render_fwd_loss); in the
         # plain step the loss sums and Adam ride on the backward's launches
         # (plane_render_bwd_adam)

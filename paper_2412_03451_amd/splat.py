@@ -292,6 +292,32 @@ class Renderer:
                                              betas[0], betas[1], eps, r_min, _ptr(loss), _stream()))
         return gc, gq, gr
 
+    def step(self, tgt_depth, tgt_normal, m, v, step, tgt_off=None, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0,
+             lr=(1e-3, 1e-3, 1e-3), betas=(0.9, 0.999), eps=1e-8, r_min=1e-4, loss=None):
+        """forward_loss(reduce=False) then backward_adam(loss=...) in one
+        render launch (plane_render_step), on the planes last projected:
+        planes, m and v updated in place; returns depth, normal, g_depth,
+        g_normal and the gradients, the bits of the two calls."""
+        center, quat, radii, lam = self._inputs
+        K = int(center.shape[0])
+        P = self.n_pixels
+        depth = torch.empty(P, dtype=torch.float32, device=self.device)
+        normal = torch.empty(3 * P, dtype=torch.float32, device=self.device)
+        gD = torch.empty_like(depth)
+        gN = torch.empty_like(normal)
+        gc = torch.empty(K, 3, dtype=torch.float32, device=self.device)
+        gq = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        gr = torch.empty(K, 4, dtype=torch.float32, device=self.device)
+        prm = self.params.c()
+        n_tgt = 0 if tgt_off is None else int(tgt_off.numel())
+        check(self.lib.plane_render_step(C.byref(self.L), _ptr(self.ws), _ptr(center), _ptr(quat), _ptr(radii), K,
+                                         _ptr(self.cams), self.n_cams, _ptr(lam), C.byref(prm), _ptr(depth),
+                                         _ptr(normal), _ptr(tgt_depth), _ptr(tgt_normal), _ptr(mask), _ptr(tgt_off),
+                                         n_tgt, a_cos, a_nl1, a_d, _ptr(gD), _ptr(gN), _ptr(gc), _ptr(gq), _ptr(gr),
+                                         _ptr(m), _ptr(v), _ptr(step), lr[0], lr[1], lr[2], betas[0], betas[1], eps,
+                                         r_min, _ptr(loss), _stream()))
+        return depth, normal, gD, gN, gc, gq, gr
+
     def counters(self):
         out = (C.c_int64 * 20)()
         check(self.lib.ps_read_counters(C.byref(self.L), _ptr(self.ws), out, _stream()))

@@ -1,4 +1,7 @@
-"""The plain fitting step's fused backward (plane_render_bwd_adam: the
+"""The plain fitting step's fused calls against the separate calls they
+replace, bit for bit.  plane_render_step (forward, loss, backward and Adam
+with one render launch) in several weight modes and with deep lists; and the
+fused backward (plane_render_bwd_adam: the
 backward, Adam of Sec. 3.3 and the loss sums of Eq. 14 in one call, the
 sums formed by workgroups of the backward's reduction) against the separate
 calls it replaces (plane_render_fwd_loss with its own loss sums,
@@ -38,10 +41,12 @@ def batch():
     return init, cams, jobs, _dev(np.concatenate(tD)), _dev(np.concatenate([n.reshape(3, -1).ravel() for n in tN]))
 
 
-def _run(batch, fused: bool, steps: int = 4):
+def _run(batch, fused, steps: int = 4, params=None):
+    """fused: False (separate calls), True (plane_render_bwd_adam) or "step"
+    (plane_render_step: forward, loss, backward and Adam in one launch)."""
     from paper_2412_03451_amd.splat import Renderer, adam_step
     init, cams, jobs, tD, tN = batch
-    r = Renderer(jobs, cams)
+    r = Renderer(jobs, cams, params=params)
     c, q, rr = _dev(init.center), _dev(init.quat), _dev(init.radii)
     K = c.shape[0]
     m = torch.zeros(11 * K, device="cuda")
@@ -52,6 +57,12 @@ def _run(batch, fused: bool, steps: int = 4):
         step = torch.tensor([it + 1], dtype=torch.int32, device="cuda")
         r.project(c, q, rr, lam)
         r.bin()
+        if fused == "step":
+            loss = torch.empty(len(jobs), 4, device="cuda")
+            D, N, gD, gN, gc, gq, gr = r.step(tD, tN, m, v, step, loss=loss)
+            torch.cuda.synchronize()
+            out.append([x.detach().cpu().numpy().copy() for x in (loss, gc, gq, gr, c, q, rr, m, v, D, N, gD, gN)])
+            continue
         D, N, loss, gD, gN = r.forward_loss(tD, tN, reduce=not fused)
         if fused:
             loss = torch.empty(len(jobs), 4, device="cuda")
@@ -60,14 +71,15 @@ def _run(batch, fused: bool, steps: int = 4):
             gc, gq, gr = r.backward(c, q, rr, lam, gD, gN)
             adam_step(c, q, rr, gc, gq, gr, m, v, step)
         torch.cuda.synchronize()
-        out.append([x.detach().cpu().numpy().copy() for x in (loss, gc, gq, gr, c, q, rr, m, v, D, N)])
+        out.append([x.detach().cpu().numpy().copy() for x in (loss, gc, gq, gr, c, q, rr, m, v, D, N, gD, gN)])
     return out
 
 
 def test_fused_backward_adam_gives_the_separate_calls_bits(batch):
     a = _run(batch, fused=False)
     b = _run(batch, fused=True)
-    names = ("loss", "g_center", "g_quat", "g_radii", "center", "quat", "radii", "m", "v", "depth", "normal")
+    names = ("loss", "g_center", "g_quat", "g_radii", "center", "quat", "radii", "m", "v", "depth", "normal",
+             "g_depth", "g_normal")
     for it, (sa, sb) in enumerate(zip(a, b)):
         print(f"step {it}: loss {sa[0].sum(0)}", flush=True)
         for n, x, y in zip(names, sa, sb):
@@ -75,3 +87,61 @@ def test_fused_backward_adam_gives_the_separate_calls_bits(batch):
     # the fit actually moved and the gradients are not trivial
     assert np.abs(a[-1][4] - batch[0].center).max() > 0
     assert np.abs(a[0][1]).max() > 0
+
+
+@pytest.mark.parametrize("mode,flags", [(0, 0), (2, 0), (1, 1), (0, 2 << 4)])
+def test_one_launch_step_gives_the_separate_calls_bits(batch, mode, flags):
+    """plane_render_step (each 8x8 block's forward, loss and backward in one
+    launch, the hits committed again from the walk's recorded positions)
+    against plane_render_fwd_loss + plane_render_bwd + adam_step_planes:
+    the same bits for everything, in the default weight mode, the Gaussian
+    (Eq. 5), mode 1 with the exact fallback forced for every pixel, and with
+    an 8-hit pending buffer."""
+    from paper_2412_03451_amd.splat import SplatParams
+    prm = SplatParams(weight_mode=mode, flags=flags)
+    a = _run(batch, fused=False, params=prm)
+    b = _run(batch, fused="step", params=prm)
+    names = ("loss", "g_center", "g_quat", "g_radii", "center", "quat", "radii", "m", "v", "depth", "normal",
+             "g_depth", "g_normal")
+    for it, (sa, sb) in enumerate(zip(a, b)):
+        for n, x, y in zip(names, sa, sb):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (mode, flags, it, n)
+    assert np.abs(a[0][1]).max() > 0
+
+
+def test_one_launch_step_deep_lists():
+    """Deep per-pixel lists (more than one 8-hit chunk per pixel, several
+    staged batches per tile): the one-launch step's gradients are the
+    separate calls' bits."""
+    from paper_2412_03451_amd.splat import Renderer, SplatParams, adam_step
+    ps = synth.random_planes(150, seed=4, center_range=0.3, extent_range=(0.4, 0.9))
+    cam = synth.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, np.eye(3, dtype=np.float32),
+                       np.array([0.0, 0.0, 3.0], np.float32))
+    _, _, aux = oracle.render(ps.center, ps.quat, ps.radii, cam, 8.0, oracle.OracleParams(weight_mode="B"))
+    assert int(aux["count"].max()) > 16   # three chunks of 8 hits for some pixels
+    tgt = synth.random_planes(150, seed=5, center_range=0.3, extent_range=(0.4, 0.9))
+    tD, tN, _ = oracle.render(tgt.center, tgt.quat, tgt.radii, cam, 300.0, oracle.OracleParams(weight_mode="B"))
+    tD = _dev(tD.numpy().astype(np.float32).ravel())
+    tN = _dev(tN.numpy().astype(np.float32).reshape(3, -1).ravel())
+    outs = []
+    for form in ("separate", "step"):
+        r = Renderer.single_scene([cam], ps.K, params=SplatParams(weight_mode=1))
+        c, q, rr = _dev(ps.center), _dev(ps.quat), _dev(ps.radii)
+        m = torch.zeros(11 * ps.K, device="cuda")
+        v = torch.zeros(11 * ps.K, device="cuda")
+        step = torch.tensor([1], dtype=torch.int32, device="cuda")
+        lam = torch.tensor([8.0], device="cuda")
+        r.project(c, q, rr, lam)
+        r.bin()
+        if form == "step":
+            loss = torch.empty(1, 4, device="cuda")
+            D, N, gD, gN, gc, gq, gr = r.step(tD, tN, m, v, step, loss=loss)
+        else:
+            D, N, loss, gD, gN = r.forward_loss(tD, tN)
+            gc, gq, gr = r.backward(c, q, rr, lam, gD, gN)
+            adam_step(c, q, rr, gc, gq, gr, m, v, step)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy().copy() for x in (loss, gc, gq, gr, c, q, rr, D, N)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert np.abs(outs[0][1]).max() > 0

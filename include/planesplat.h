@@ -407,9 +407,9 @@ int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const fl
  * that call would have given, and the forward's own reduction launch is
  * saved.  The update itself stays a kernel of its own: inside the
  * reduction its latency (two float64 powers, the parameter reads) lengthens
- * every round of a reduction over many planes.  This is the fitting step's
- * form when neither the single-radius variant nor splitting statistics sit
- * between the backward and the update. */
+ * every round of a reduction over many planes.  plane_render_step does the
+ * work of plane_render_fwd_loss and this call with one render launch; this
+ * call is the step's form with a separate forward. */
 int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
                           const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm,
                           const float* g_depth, const float* g_normal, float* g_center, float* g_quat,

@@ -727,9 +727,12 @@ struct BwdSink {
 // The fused forward-and-backward walk of the fitting step: composites depth
 // and normal like the forward (the same arithmetic, so the same bits) and
 // records what the backward needs of every committed hit: its list position
-// and the transmittance at each chunk start.  The gradient pass's per-hit
-// values wait for the pixel's loss gradient, which exists only once the
-// pixel is composited, so every chunk is committed again from the positions.
+// and the transmittance at each chunk start; of the first chunk also a*, the
+// transmittance in front of the hit and its depth.  The per-hit values of
+// the gradient pass wait for the pixel's loss gradient, which exists only
+// once the pixel is composited: they are formed from the depth and the
+// plane's normal then (a list of one chunk), or the chunks are committed
+// again from the positions (longer lists).
 struct FwdBwdSink {
   static constexpr int NP = 3;   // payload: rendered normal of the hit
   static constexpr bool BWD = true;
@@ -743,7 +746,15 @@ struct FwdBwdSink {
     pl[0] = n[0]; pl[1] = n[1]; pl[2] = n[2];
   }
   __device__ void commit(float t, float as, int pos, const float* n) {
-    g_bwd.hpos[count][threadIdx.x] = (int16_t)pos;
+    BwdLds& L = g_bwd;
+    const int lane = threadIdx.x;
+    L.hpos[count][lane] = (int16_t)pos;
+    if (count < kChunk) {
+      L.pos[count][lane] = pos;
+      L.a[count][lane] = as;
+      L.T[count][lane] = T;
+      L.cg[count][lane] = t;   // the depth, until the loss gradient exists
+    }
     if (count == kChunk) Tb1 = T;
     if (count == 2 * kChunk) Tb2 = T;
     if (count == 3 * kChunk) Tb3 = T;
@@ -931,6 +942,15 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
       if (c.inimg) {
         gD = g[0]; gN0 = g[1]; gN1 = g[2]; gN2 = g[3];
       }
+      // a block whose pixels hold at most one chunk: its per-hit values c_j
+      // now (BwdSink::payload's arithmetic), no second commit
+      if (wave_max_int(hits) <= kChunk) {
+        for (int j = 0; j < hits; ++j) {
+          float nrm[3];
+          cand_normal(a, c, c.e, L.pos[j][lane], nrm);
+          L.cg[j][lane] = fmaf(gD, L.cg[j][lane], fmaf(gN0, nrm[0], fmaf(gN1, nrm[1], gN2 * nrm[2])));
+        }
+      }
     } else if (a.lst_pos) {
       // no walk: stage the first batch here (record heads, emit indices),
       // which the one-batch paths below read from LDS
@@ -948,7 +968,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   float S = 0.f;   // composite of the hits behind the current chunk
   for (int pass = 0; pass < passes; ++pass) {
     const int chunk = passes - 1 - pass;
-    if (passes > 1 || FUSED) {
+    if (passes > 1) {
       if (pass > 0) __threadfence_block();   // rows written by other lanes are read back below
       const float T0 = chunk == 0 ? 1.f : chunk == 1 ? s.Tb1 : chunk == 2 ? s.Tb2 : s.Tb3;
       BwdSink r{T0, chunk * kChunk, chunk * kChunk, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode};

@@ -178,15 +178,13 @@ __global__ __launch_bounds__(64 * kRecPerWG) void bin_count_kernel(BinArgs a) {
   }
 }
 
-// Exclusive scan of in[0, n) by one 1024-thread workgroup (n <= 4096):
-// chunk-local offsets; returns the total and the maximum.
-__device__ inline int chunk_scan(const int* __restrict__ in, int* __restrict__ out, int n, int* lds, int& mx) {
+// Exclusive scan of a chunk of n <= 4096 values by one 1024-thread
+// workgroup, thread i holding values 4 i .. 4 i + 3 (zeros past n): writes
+// the chunk-local offsets to out and returns the total (and the maximum).
+__device__ inline int chunk_scan(const int (&v)[4], int* __restrict__ out, int n, int* lds, int& mx) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  int v[4];
   int local = 0;
   for (int j = 0; j < 4; ++j) {
-    const int idx = tid * 4 + j;
-    v[j] = idx < n ? in[idx] : 0;
     mx = max(mx, v[j]);
     local += v[j];
   }
@@ -260,25 +258,40 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
   __shared__ int lds[40];
   __shared__ int hist[kBuckets];
   __shared__ int stb[kSlotCache];   // tile_begin of each slot
+  __shared__ int ssub[kSlotCache];  // 8x8 blocks per tile of each slot
   __shared__ long long lsum[17];
   __shared__ int last;
   const int g = blockIdx.x, tid = threadIdx.x;
   const int t0 = g * kScanChunk, r0 = g * kScanChunk;
   const int nt = max(0, min(kScanChunk, a.T - t0)), nr = max(0, min(kScanChunk, a.R - r0));
   const bool cached = a.S <= kSlotCache;
+  // every load up front: the chunk's tile and record counts (four per
+  // thread) and the slots' first tiles and tile shapes
+  int vt[4], vr[4];
+  for (int j = 0; j < 4; ++j) {
+    const int idx = tid * 4 + j;
+    vt[j] = idx < nt ? a.tile_cnt[t0 + idx] : 0;
+    vr[j] = idx < nr ? a.rec_cnt[r0 + idx] : 0;
+  }
   for (int k = tid; k < kBuckets; k += blockDim.x) hist[k] = 0;
   if (cached)
-    for (int s = tid; s < a.S; s += blockDim.x) stb[s] = a.slots[s].tile_begin;
+    for (int s = tid; s < a.S; s += blockDim.x) {
+      const ps_slot& q = a.slots[s];
+      stb[s] = q.tile_begin;
+      ssub[s] = (q.tile_w >> 3) * (q.tile_h >> 3);
+    }
   int mx_t = 0, mx_r = 0;
-  const int tot_t = chunk_scan(a.tile_cnt + t0, a.tile_off + t0, nt, lds, mx_t);
-  const int tot_r = chunk_scan(a.rec_cnt + r0, a.rec_off + r0, nr, lds, mx_r);
+  const int tot_t = chunk_scan(vt, a.tile_off + t0, nt, lds, mx_t);
+  const int tot_r = chunk_scan(vr, a.rec_off + r0, nr, lds, mx_r);
   // the chunk's render items per list-length bucket: each tile's items take
   // consecutive positions in its bucket after those of the chunk's earlier
   // claims (tile_pos holds the position inside the chunk's share of the
   // bucket; the order of tiles inside a bucket does not matter: items are
   // independent); bin_emit's scatter cursors
-  for (int t = t0 + tid; t < t0 + nt; t += blockDim.x) {
-    int si;
+  for (int j = 0; j < 4; ++j) {   // the tiles this thread scanned
+    const int t = t0 + tid * 4 + j;
+    if (t >= t0 + nt) break;
+    int si, sub_per;
     if (cached) {   // last slot whose first tile is <= t
       int lo = 0, hi = a.S - 1;
       while (lo < hi) {
@@ -286,12 +299,13 @@ __global__ __launch_bounds__(1024) void bin_scan_kernel(BinArgs a) {
         if (stb[mid] <= t) lo = mid; else hi = mid - 1;
       }
       si = lo;
+      sub_per = ssub[si];
     } else {
       si = find_slot_by_tile(a.slots, a.S, t);
+      const ps_slot& sl = a.slots[si];
+      sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
     }
-    const ps_slot& sl = a.slots[si];
-    const int sub_per = (sl.tile_w >> 3) * (sl.tile_h >> 3);
-    const int c = a.tile_cnt[t];
+    const int c = vt[j];
     a.tile_slot[t] = si;
     a.tile_pos[t] = atomicAdd(&hist[length_bucket(c)], sub_per);
     a.tile_cur[t] = 0;

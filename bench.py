@@ -298,10 +298,10 @@ def batched_bench(args):
     """Batched fitting step: --rooms synthetic rooms of uneven size (plane
     counts log-uniform in [200, 4000], 20-100 views, 320x240 or 640x480),
     every room advancing one iteration (one view) per step, all in one
-    graph-replayed step of one launch per phase.  Tile shapes per room from
-    the autotuner (tuned for throughput on copies of the first room of each
-    shape filling the GPU, cached).  Value: sum over rooms of
-    (pixels x planes) per second of step time."""
+    graph-replayed step of one launch per phase.  The tile shape from the
+    autotuner (the batch's own steps timed with each shape; --no-autotune:
+    16x16).  Value: sum over rooms of (pixels x planes) per second of step
+    time."""
     import torch
     import synth
     from paper_2412_03451_amd import learned_init as li
@@ -318,16 +318,19 @@ def batched_bench(args):
                                      f=sp["f"])
         tD, tN = li.render_targets((gt.center, gt.quat, gt.radii), cams)
         sc = Scene(init.center, init.quat, init.radii, cams, tD, tN)
-        if tuner is not None:
-            # tuned for throughput: copies of the room filling the GPU (about 2 Mpixel per step)
-            reps = max(1, round(2e6 / (sp["width"] * sp["height"])))
-            tile, _ = tuner.tune(sc, steps=10, warmup=3, pendings=(6,), replicas=reps)
-            sc.tile = tile
         scenes.append(sc)
         work += sp["width"] * sp["height"] * gt.K
     log(f"{len(scenes)} rooms ready")
     from paper_2412_03451_amd.splat import SplatParams
     params = SplatParams(flags=256 if args.per_item_launch else 0)
+    tile_times = None
+    if tuner is not None:
+        # one tile shape for the batch, from timing the batch's own steps with each shape
+        tile, tile_times = tuner.tune_batch(scenes, cfg=FitConfig(one_launch=not args.separate_calls),
+                                            params=params)
+        for sc in scenes:
+            sc.tile = tile
+        log(f"tile shape {tile}: {tile_times}")
     fit = BatchFit(scenes, cfg=FitConfig(check_every=max(1, args.warmup), one_launch=not args.separate_calls),
                    params=params)
     fit.size_capacity()
@@ -362,6 +365,7 @@ def batched_bench(args):
                    "launch": "one workgroup per 8x8 block" if args.per_item_launch else
                              "persistent (atomic work queue) where the blocks exceed 4x the resident workgroups",
                    "planes": int(fit.K), "pixels_per_step": int(fit.rend.n_pixels), "tiles": tiles,
+                   "tile_ms_tried": tile_times,
                    "pair_capacity": int(fit.rend.L.pair_capacity)},
         "phase_ms": {k: round(x, 4) for k, x in phase_ms.items()},
         "render_stats": {"composited_hits": hits, "pairs_evaluated": evals,

@@ -4,7 +4,8 @@ timing graph-replayed fitting steps on the scene itself.
 
 The results are cached in a JSON file (PLANESPLAT_TUNE_CACHE, else
 ~/.cache/planesplat/tune.json): key "WxH/K<bucket>" -> {"tile": [w, h],
-"pending": p, "ms": step time, "tried": {...}}.  Each configuration's time
+"pending": p, "ms": step time, "tried": {...}}; tune_batch chooses one shape
+for a whole batch by timing it.  Each configuration's time
 is the median of three timed runs, and the first tile shape and buffer size
 (16x16, 6) stay unless another is more than TILE_MARGIN faster, so timing
 noise does not change the choice from run to run.  Tuning only reads the
@@ -73,8 +74,32 @@ class Autotuner:
         """ms per graph-replayed fitting step of `replicas` copies of the scene
         (one batch) with this configuration."""
         sc = replace(scene, tile=tuple(tile))
-        fit = BatchFit([sc] * replicas, cfg=replace(cfg, check_every=max(1, warmup)),
-                       params=SplatParams(flags=pending_flags(pending)))
+        return Autotuner.time_batch([sc] * replicas, SplatParams(flags=pending_flags(pending)), cfg, steps, warmup)
+
+    def tune_batch(self, scenes, cfg: FitConfig | None = None, steps: int = 10, warmup: int = 3, tiles=TILES,
+                   params: SplatParams | None = None):
+        """One tile shape for a batch of scenes, chosen by timing the batch's
+        own fitting steps with each shape: the step time of a batch is what it
+        is run for, and shapes chosen per scene (alone, or on copies of it)
+        need not minimise it (smaller tiles that win for one scene add
+        binning work to the batch).  The first shape stays unless another is
+        more than TILE_MARGIN faster.  Returns (tile, {shape: ms})."""
+        cfg = cfg or FitConfig()
+        tried = {}
+        for t in tiles:
+            scs = [replace(sc, tile=tuple(t)) for sc in scenes]
+            tried[f"{t[0]}x{t[1]}"] = self.time_batch(scs, params or SplatParams(), cfg, steps, warmup)
+        t0 = tried[f"{tiles[0][0]}x{tiles[0][1]}"]
+        best = min(tiles, key=lambda t: tried[f"{t[0]}x{t[1]}"])
+        if tried[f"{best[0]}x{best[1]}"] > t0 / (1.0 + TILE_MARGIN):
+            best = tiles[0]
+        return tuple(best), tried
+
+    @staticmethod
+    def time_batch(scenes, params: SplatParams, cfg: FitConfig, steps: int, warmup: int) -> float:
+        """ms per graph-replayed fitting step of a batch of scenes."""
+        fit = BatchFit(list(scenes), cfg=replace(cfg, check_every=max(1, warmup)), params=params)
+        fit.size_capacity(rows=min(8, int(fit.table.shape[0])))
         fit.run(max(1, warmup), graph=True)
         st = torch.cuda.current_stream()
         a = torch.cuda.Event(enable_timing=True)

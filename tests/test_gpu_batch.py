@@ -118,6 +118,16 @@ def test_autotuner_caches_choice(tmp_path):
     assert len(at2.table[cache_key(W, H, K)]["tried"]) == 5
 
 
+def test_autotuner_batch_choice(tmp_path):
+    """tune_batch times the batch itself with each tile shape and keeps 16x16
+    unless another shape is more than the margin faster."""
+    from paper_2412_03451_amd.autotune import TILE_MARGIN, Autotuner
+    scenes = _room_scenes()
+    tile, tried = Autotuner(str(tmp_path / "tune.json")).tune_batch(scenes, steps=3, warmup=2)
+    assert set(tried) == {"16x16", "32x8", "8x8"} and all(0 < t < float("inf") for t in tried.values())
+    assert tile == (16, 16) or tried[f"{tile[0]}x{tile[1]}"] * (1 + TILE_MARGIN) < tried["16x16"]
+
+
 def test_full_size_batch_sampled_pixels():
     """The 64-room batch at full size, in the benchmark's launch shape (one
     job per room, 16x16 tiles, one launch per phase, lambda(0)): rooms of

@@ -1280,11 +1280,16 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
       } else {
         for (int r0 = 0; r0 < nblk; r0 += 64) {
           const int nb = min(64, nblk - r0);
-          for (int b = w; b < nb; b += 4) {
-            float v[16];
-            row_of(64 * (r0 + b) + lane, v);
-            const float t = wave_sum16(v);
-            if ((lane & 3) == 0) part[b][lane >> 2] = t;
+          for (int b = w; b < nb; b += 8) {   // blocks b and b + 4 in flight
+            float v[2][16];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) row_of(64 * (r0 + b + 4 * u) + lane, v[u]);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+              if (b + 4 * u < nb) {
+                const float t = wave_sum16(v[u]);
+                if ((lane & 3) == 0) part[b + 4 * u][lane >> 2] = t;
+              }
           }
           __syncthreads();
           if (w == 0)

@@ -727,12 +727,14 @@ struct BwdSink {
 // The fused forward-and-backward walk of the fitting step: composites depth
 // and normal like the forward (the same arithmetic, so the same bits) and
 // records what the backward needs of every committed hit: its list position
-// and the transmittance at each chunk start; of the first chunk also a*, the
-// transmittance in front of the hit and its depth.  The per-hit values of
-// the gradient pass wait for the pixel's loss gradient, which exists only
-// once the pixel is composited: they are formed from the depth and the
-// plane's normal then (a list of one chunk), or the chunks are committed
-// again from the positions (longer lists).
+// and the transmittance at each chunk start; and, in chunk slots taken
+// cyclically (hit j in slot j mod kChunk), a*, the transmittance in front of
+// the hit and its depth, so that the pixel's last chunk is in LDS when the
+// walk ends.  The per-hit values of the gradient pass wait for the pixel's
+// loss gradient, which exists only once the pixel is composited: they are
+// formed from the depth and the plane's normal then, for the last chunk
+// (the first one the backward processes); the other chunks are committed
+// again from the positions.
 struct FwdBwdSink {
   static constexpr int NP = 3;   // payload: rendered normal of the hit
   static constexpr bool BWD = true;
@@ -749,12 +751,11 @@ struct FwdBwdSink {
     BwdLds& L = g_bwd;
     const int lane = threadIdx.x;
     L.hpos[count][lane] = (int16_t)pos;
-    if (count < kChunk) {
-      L.pos[count][lane] = pos;
-      L.a[count][lane] = as;
-      L.T[count][lane] = T;
-      L.cg[count][lane] = t;   // the depth, until the loss gradient exists
-    }
+    const int j = count % kChunk;
+    L.pos[j][lane] = pos;
+    L.a[j][lane] = as;
+    L.T[j][lane] = T;
+    L.cg[j][lane] = t;   // the depth, until the loss gradient exists
     if (count == kChunk) Tb1 = T;
     if (count == 2 * kChunk) Tb2 = T;
     if (count == 3 * kChunk) Tb3 = T;
@@ -942,14 +943,15 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
       if (c.inimg) {
         gD = g[0]; gN0 = g[1]; gN1 = g[2]; gN2 = g[3];
       }
-      // a block whose pixels hold at most one chunk: its per-hit values c_j
-      // now (BwdSink::payload's arithmetic), no second commit
-      if (wave_max_int(hits) <= kChunk) {
-        for (int j = 0; j < hits; ++j) {
-          float nrm[3];
-          cand_normal(a, c, c.e, L.pos[j][lane], nrm);
-          L.cg[j][lane] = fmaf(gD, L.cg[j][lane], fmaf(gN0, nrm[0], fmaf(gN1, nrm[1], gN2 * nrm[2])));
-        }
+      // the per-hit values c_j of each pixel's last chunk now
+      // (BwdSink::payload's arithmetic); the backward's first pass takes
+      // them without committing that chunk again (a lane whose last chunk is
+      // not the block's last gets its chunks committed again later)
+      for (int j = hits > 0 ? (hits - 1) / kChunk * kChunk : 0; j < hits; ++j) {
+        const int q = j % kChunk;
+        float nrm[3];
+        cand_normal(a, c, c.e, L.pos[q][lane], nrm);
+        L.cg[q][lane] = fmaf(gD, L.cg[q][lane], fmaf(gN0, nrm[0], fmaf(gN1, nrm[1], gN2 * nrm[2])));
       }
     } else if (a.lst_pos) {
       // no walk: stage the first batch here (record heads, emit indices),
@@ -968,7 +970,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   float S = 0.f;   // composite of the hits behind the current chunk
   for (int pass = 0; pass < passes; ++pass) {
     const int chunk = passes - 1 - pass;
-    if (passes > 1) {
+    if (passes > 1 && !(FUSED && pass == 0)) {
       if (pass > 0) __threadfence_block();   // rows written by other lanes are read back below
       const float T0 = chunk == 0 ? 1.f : chunk == 1 ? s.Tb1 : chunk == 2 ? s.Tb2 : s.Tb3;
       BwdSink r{T0, chunk * kChunk, chunk * kChunk, 1.f, 1.f, 1.f, gD, gN0, gN1, gN2, lam5, a.mode};

@@ -128,6 +128,59 @@ def test_autotuner_batch_choice(tmp_path):
     assert tile == (16, 16) or tried[f"{tile[0]}x{tile[1]}"] * (1 + TILE_MARGIN) < tried["16x16"]
 
 
+def test_full_size_batch_one_launch_step_bits():
+    """The 64-room batch at full size (more 8x8 blocks than four times the
+    resident workgroups: the persistent launch): one fitting step with
+    plane_render_step against plane_render_fwd_loss + plane_render_bwd_adam,
+    the same bits for the maps, the loss, the gradients, the planes and the
+    Adam moments."""
+    from paper_2412_03451_amd.splat import Job, Renderer
+    specs = synth.room_batch_specs(64, seed=0)
+    rooms, tgts, jobs, cams, off = [], [], [], [], 0
+    for i, sp in enumerate(specs):
+        gt, info = synth.room_planes(seed=sp["seed"], target_K=sp["K"])
+        init = synth.room_init_planes(gt, seed=sp["seed"] + 1)
+        cam = synth.room_trajectory(sp["seed"], sp["views"], info, width=sp["width"], height=sp["height"],
+                                    f=sp["f"])[0]
+        rooms.append(init)
+        tgts.append(gt)
+        cams.append(cam)
+        jobs.append(Job(off, off + init.K, i, cam.width, cam.height, (16, 16), i))
+        off += init.K
+    lt = torch.tensor([f32(oracle.lambda_at(0))], device="cuda")
+    # targets: the ground-truth planes rendered by the forward at lambda = 300
+    tr = Renderer(jobs, cams)
+    tD, tN = tr.render(torch.cat([_dev(g.center) for g in tgts]), torch.cat([_dev(g.quat) for g in tgts]),
+                       torch.cat([_dev(g.radii) for g in tgts]), torch.tensor([300.0], device="cuda"))
+    del tr
+    outs = []
+    for form in ("separate", "step"):
+        rb = Renderer(jobs, cams)
+        assert rb.L.n_items > 4 * 2048
+        c = torch.cat([_dev(p.center) for p in rooms])
+        q = torch.cat([_dev(p.quat) for p in rooms])
+        r = torch.cat([_dev(p.radii) for p in rooms])
+        m = torch.zeros(11 * off, device="cuda")
+        v = torch.zeros(11 * off, device="cuda")
+        step = torch.tensor([1], dtype=torch.int32, device="cuda")
+        loss = torch.empty(64, 4, device="cuda")
+        rb.project(c, q, r, lt)
+        rb.bin()
+        if form == "step":
+            D, N, gD, gN, gc, gq, gr = rb.step(tD, tN, m, v, step, loss=loss)
+        else:
+            D, N, _, gD, gN = rb.forward_loss(tD, tN, reduce=False)
+            gc, gq, gr = rb.backward_adam(c, q, r, lt, gD, gN, m, v, step, loss=loss)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy().copy() for x in (D, N, gD, gN, loss, gc, gq, gr, c, q, r, m, v)])
+        del rb
+    names = ("depth", "normal", "g_depth", "g_normal", "loss", "g_center", "g_quat", "g_radii", "center", "quat",
+             "radii", "m", "v")
+    for n, x, y in zip(names, *outs):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), n
+    assert np.abs(outs[0][5]).max() > 0
+
+
 def test_full_size_batch_sampled_pixels():
     """The 64-room batch at full size, in the benchmark's launch shape (one
     job per room, 16x16 tiles, one launch per phase, lambda(0)): rooms of

@@ -60,7 +60,7 @@ def test_autograd_matches_stored_central_differences(name):
 
 @pytest.mark.parametrize("name", ["lam0", "lam300"])
 def test_stored_central_differences_are_the_oracles(name):
-    """25 of the stored coordinates, recomputed: same continuity verdict, same
+    """25 of the stored coordinates, recomputed: same continuity decision, same
     difference to within float64 summation order (the host's vector width
     may differ from the machine that wrote the file)."""
     m = fd_scene()

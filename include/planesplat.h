@@ -431,7 +431,9 @@ int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center, float* qu
  * Arguments as in plane_render_fwd_loss (depth, normal, targets, mask,
  * tgt_off, n_tgt, loss weights, g_depth and g_normal as outputs) and
  * plane_render_bwd_adam (planes updated in place, gradients, Adam state and
- * rates; loss: device float [n_slots][4] or NULL).  ps_params.flags bit 6
+ * rates; loss: device float [n_slots][4] or NULL).  depth and normal may
+ * both be NULL, and g_depth and g_normal both NULL: those outputs are then
+ * not written (a fitting loop needs none of them).  ps_params.flags bit 6
  * (walk statistics) is refused: the separate calls record them. */
 int plane_render_step(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
                       const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm, float* depth,

@@ -491,8 +491,10 @@ __device__ inline LossTargets loss_targets(const LossView& a, const ps_slot& sl,
 __device__ inline void loss_apply(const LossView& a, const LossTargets& t, float D, const float N[3], double l[4],
                                   float* g = nullptr) {
   if (!t.valid) {
-    a.gD[t.p] = 0.f;
-    for (int c = 0; c < 3; ++c) a.gN[t.nb + c * t.HW] = 0.f;
+    if (a.gD) {
+      a.gD[t.p] = 0.f;
+      for (int c = 0; c < 3; ++c) a.gN[t.nb + c * t.HW] = 0.f;
+    }
     if (g) g[0] = g[1] = g[2] = g[3] = 0.f;
     return;
   }
@@ -503,14 +505,14 @@ __device__ inline void loss_apply(const LossView& a, const LossTargets& t, float
   const float s1 = e1 > 0 ? 1.f : (e1 < 0 ? -1.f : 0.f);
   const float ed = D - t.Dt;
   const float gd = m * a.a_d * sgn_f(ed);
-  a.gD[t.p] = gd;
+  if (a.gD) a.gD[t.p] = gd;   // (null: the caller keeps the gradient in registers only)
   if (g) g[0] = gd;
   double nl1 = 0;
   for (int c = 0; c < 3; ++c) {
     const float ec = N[c] - Nt[c];
     nl1 += fabs((double)N[c] - (double)Nt[c]);
     const float gn = m * (-a.a_cos * s1 * Nt[c] + a.a_nl1 * sgn_f(ec));
-    a.gN[t.nb + c * t.HW] = gn;
+    if (a.gN) a.gN[t.nb + c * t.HW] = gn;
     if (g) g[1 + c] = gn;
   }
   if (m != 0.f) {

@@ -931,7 +931,7 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
       walk<P, GAUSS>(a, c, f, lam5, delta, evals, steps);
       hits = f.count;
       s.Tb1 = f.Tb1; s.Tb2 = f.Tb2; s.Tb3 = f.Tb3;
-      if (c.inimg) {
+      if (c.inimg && a.depth) {
         a.depth[c.pix] = f.D;
         const int64_t nb = 3 * c.pix_off + (c.pix - c.pix_off);
         a.normal[nb] = f.N0;
@@ -1519,11 +1519,13 @@ static int launch_bwd(RenderArgs& a, int K, void* stream, bool fused = false) {
 static int bwd_args(const ps_layout* L, void* ws, const float* center, const float* quat, const float* radii, int K,
                     const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm,
                     const float* g_depth, const float* g_normal, float* g_center, float* g_quat, float* g_radii,
-                    RenderArgs& a, const char* who) {
+                    RenderArgs& a, const char* who, bool upstream = true) {
   int rc = fill_args(L, ws, cams, n_cams, lambda, prm, a, who);
   if (rc) return rc;
-  // an empty plane set (K = 0) may come with null plane and gradient arrays
-  if (!g_depth || !g_normal || K < 0 || (K > 0 && (!center || !quat || !radii || !g_center || !g_quat || !g_radii)))
+  // an empty plane set (K = 0) may come with null plane and gradient arrays;
+  // upstream false: the loss gradient is formed inside (plane_render_step)
+  if ((upstream && (!g_depth || !g_normal)) || K < 0 ||
+      (K > 0 && (!center || !quat || !radii || !g_center || !g_quat || !g_radii)))
     return ps_set_error(PS_ERR_INVALID, "%s: null pointer or K < 0", who);
   if (K < L->n_planes) return ps_set_error(PS_ERR_INVALID, "%s: K=%d < planes referenced %d", who, K, L->n_planes);
   a.g_depth = g_depth; a.g_normal = g_normal;
@@ -1614,9 +1616,9 @@ extern "C" int plane_render_step(const ps_layout* L, void* ws, float* center, fl
                                  float* loss, void* stream) {
   RenderArgs a;
   int rc = bwd_args(L, ws, center, quat, radii, K, cams, n_cams, lambda, prm, g_depth, g_normal, g_center, g_quat,
-                    g_radii, a, "plane_render_step");
+                    g_radii, a, "plane_render_step", false);
   if (rc) return rc;
-  if (!depth || !normal || !tgt_depth || !tgt_normal || (tgt_off && n_tgt <= 0))
+  if (!tgt_depth || !tgt_normal || (tgt_off && n_tgt <= 0) || !depth != !normal || !g_depth != !g_normal)
     return ps_set_error(PS_ERR_INVALID, "plane_render_step: bad argument");
   if (K > 0 && (!m || !v || !step)) return ps_set_error(PS_ERR_INVALID, "plane_render_step: null Adam state");
   if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))

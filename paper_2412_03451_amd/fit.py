@@ -217,7 +217,7 @@ class BatchFit:
             loss = torch.empty(len(rend.jobs), 4, dtype=torch.float32, device=self.device)
             rend.step(self.tgt_depth, self.tgt_normal, self.m, self.v, self.step_no, self.tgt_off, mask=self.mask,
                       a_cos=cfg.loss_w[0], a_nl1=cfg.loss_w[1], a_d=cfg.loss_w[2], lr=cfg.lr, betas=cfg.betas,
-                      eps=cfg.eps, r_min=cfg.r_min, loss=loss)
+                      eps=cfg.eps, r_min=cfg.r_min, loss=loss, maps=False)
             m()
             m()
             m()

@@ -293,18 +293,19 @@ class Renderer:
         return gc, gq, gr
 
     def step(self, tgt_depth, tgt_normal, m, v, step, tgt_off=None, mask=None, a_cos=5.0, a_nl1=5.0, a_d=1.0,
-             lr=(1e-3, 1e-3, 1e-3), betas=(0.9, 0.999), eps=1e-8, r_min=1e-4, loss=None):
+             lr=(1e-3, 1e-3, 1e-3), betas=(0.9, 0.999), eps=1e-8, r_min=1e-4, loss=None, maps: bool = True):
         """forward_loss(reduce=False) then backward_adam(loss=...) in one
         render launch (plane_render_step), on the planes last projected:
         planes, m and v updated in place; returns depth, normal, g_depth,
-        g_normal and the gradients, the bits of the two calls."""
+        g_normal and the gradients, the bits of the two calls.  maps=False:
+        depth, normal, g_depth and g_normal are not written (None)."""
         center, quat, radii, lam = self._inputs
         K = int(center.shape[0])
         P = self.n_pixels
-        depth = torch.empty(P, dtype=torch.float32, device=self.device)
-        normal = torch.empty(3 * P, dtype=torch.float32, device=self.device)
-        gD = torch.empty_like(depth)
-        gN = torch.empty_like(normal)
+        depth = torch.empty(P, dtype=torch.float32, device=self.device) if maps else None
+        normal = torch.empty(3 * P, dtype=torch.float32, device=self.device) if maps else None
+        gD = torch.empty_like(depth) if maps else None
+        gN = torch.empty_like(normal) if maps else None
         gc = torch.empty(K, 3, dtype=torch.float32, device=self.device)
         gq = torch.empty(K, 4, dtype=torch.float32, device=self.device)
         gr = torch.empty(K, 4, dtype=torch.float32, device=self.device)

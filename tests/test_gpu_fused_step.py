@@ -145,3 +145,26 @@ def test_one_launch_step_deep_lists():
     for x, y in zip(*outs):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
     assert np.abs(outs[0][1]).max() > 0
+
+
+def test_one_launch_step_without_maps(batch):
+    """plane_render_step with null map and loss-gradient outputs (what the
+    fitting loop passes): the same loss, gradients, planes and moments."""
+    from paper_2412_03451_amd.splat import Renderer
+    init, cams, jobs, tD, tN = batch
+    outs = []
+    for maps in (True, False):
+        r = Renderer(jobs, cams)
+        c, q, rr = _dev(init.center), _dev(init.quat), _dev(init.radii)
+        m = torch.zeros(11 * c.shape[0], device="cuda")
+        v = torch.zeros(11 * c.shape[0], device="cuda")
+        step = torch.tensor([1], dtype=torch.int32, device="cuda")
+        loss = torch.empty(len(jobs), 4, device="cuda")
+        r.project(c, q, rr, torch.tensor([float(np.float32(oracle.lambda_at(0)))], device="cuda"))
+        r.bin()
+        D, N, gD, gN, gc, gq, gr = r.step(tD, tN, m, v, step, loss=loss, maps=maps)
+        assert (D is None) == (not maps)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy().copy() for x in (loss, gc, gq, gr, c, q, rr, m, v)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))

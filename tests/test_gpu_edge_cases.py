@@ -183,3 +183,55 @@ def test_empty_job_in_a_batch_and_empty_scene():
     m = torch.zeros(0, device="cuda")
     adam_step(*e, gc, gq, gr, m, m.clone(), torch.ones(1, dtype=torch.int32, device="cuda"))
     torch.cuda.synchronize()
+
+
+def test_one_launch_step_empty_job_and_empty_scene():
+    """plane_render_step with a job without planes in the batch: the other
+    jobs' maps, loss and the gradients are those of the batch without it;
+    and a scene without planes (K = 0, null plane arrays) renders zeros with
+    the loss of empty maps and updates nothing."""
+    from paper_2412_03451_amd.splat import Job, Renderer
+    ps = synth.random_planes(48, seed=8, independent_radii=True)
+    cams = [synth.tiny_camera(), synth.tiny_camera(96, 64, 80.0)]
+    K = ps.K
+    lam = torch.tensor([20.0], device="cuda")
+    tgt = synth.random_planes(48, seed=9, independent_radii=True)
+    outs = {}
+    for name, jobs in (("with_empty", [Job(0, K, 0, 128, 96), Job(K, K, 1, 96, 64), Job(0, K, 1, 96, 64)]),
+                       ("without", [Job(0, K, 0, 128, 96), Job(0, K, 1, 96, 64)])):
+        tr = Renderer(jobs, cams)
+        tD, tN = tr.render(_dev(tgt.center), _dev(tgt.quat), _dev(tgt.radii), torch.tensor([300.0], device="cuda"))
+        r = Renderer(jobs, cams)
+        c, q, rr = _dev(ps.center), _dev(ps.quat), _dev(ps.radii)
+        m, v = torch.zeros(11 * K, device="cuda"), torch.zeros(11 * K, device="cuda")
+        loss = torch.empty(len(jobs), 4, device="cuda")
+        r.project(c, q, rr, lam)
+        r.bin()
+        D, N, gD, gN, gc, gq, gr = r.step(tD, tN, m, v, torch.ones(1, dtype=torch.int32, device="cuda"),
+                                          loss=loss)
+        torch.cuda.synchronize()
+        outs[name] = (r, D, N, loss.clone(), [x.clone() for x in (gc, gq, gr, c, q, rr, m, v)])
+    r1, D1, N1, l1, g1 = outs["with_empty"]
+    r0, D0, N0, l0, g0 = outs["without"]
+    assert float(r1.job_depth(D1, 1).abs().max()) == 0.0
+    for s1, s0 in ((0, 0), (2, 1)):
+        assert torch.equal(r1.job_depth(D1, s1), r0.job_depth(D0, s0))
+        assert torch.equal(l1[s1], l0[s0])
+    for a, b in zip(g1, g0):
+        assert torch.equal(a, b)
+    # no planes at all
+    e = torch.zeros(0, 3, device="cuda"), torch.zeros(0, 4, device="cuda"), torch.zeros(0, 4, device="cuda")
+    r = Renderer([Job(0, 0, 0, 128, 96)], cams[:1])
+    tD = torch.ones(r.n_pixels, device="cuda")
+    tN = torch.zeros(3 * r.n_pixels, device="cuda")
+    r.project(*e, lam)
+    r.bin()
+    loss = torch.empty(1, 4, device="cuda")
+    m0 = torch.zeros(0, device="cuda")
+    D, N, gD, gN, gc, gq, gr = r.step(tD, tN, m0, m0.clone(), torch.ones(1, dtype=torch.int32, device="cuda"),
+                                      loss=loss)
+    torch.cuda.synchronize()
+    assert float(D.abs().max()) == 0.0 and float(N.abs().max()) == 0.0
+    assert gc.numel() == 0
+    # the depth term of empty maps against unit targets: a_d * |0 - 1| per pixel
+    assert float(loss[0, 3]) == pytest.approx(r.n_pixels, rel=1e-6)

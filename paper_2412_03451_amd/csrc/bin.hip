@@ -107,14 +107,13 @@ __device__ inline bool tile_test(const Rec& rec, const BinRec& br, const ps_slot
 // Work units of the count and emit passes: (record, group of 64 tiles of its
 // tile box, row-major); the 64 lanes of a wave test one group.  The
 // workgroups (x, y), y < gridDim.y, take the kRecPerWG records from
-// kRecPerWG x on and share their units round-robin over their
-// kRecPerWG gridDim.y waves, so a record
-// with a large box (a plane near the camera, a wide fringe at small lambda)
-// spreads over many waves, and records without tiles cost no waves of their
-// own.  The host sets gridDim.y from the record count: few records (one
-// scene, where the visible ones with large boxes are neighbours in record
-// order) get up to eight times the waves; many (a batch of scenes, most
-// records outside their job's view) get one wave per record.
+// kRecPerWG x on and deal their units round-robin to their kRecPerWG x
+// gridDim.y waves, so a record with a large box (a plane near the camera, a
+// wide fringe at small lambda) spreads over many waves, and records without
+// tiles cost no waves of their own.  The host sets gridDim.y from the record
+// count: few records (one scene, where the visible ones with large boxes are
+// neighbours in record order) get up to eight times the waves; many (a batch
+// of scenes, most records outside their job's view) get one wave per record.
 constexpr int kRecPerWG = 8;
 inline int unit_split(int R) { return std::max(1, std::min(8, 16384 / std::max(R, 1))); }
 

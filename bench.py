@@ -106,16 +106,18 @@ def _oracle_rate(init, cam, lam, budget_s: float, threads: int):
     return done_px * init.K / dt, done_px, dt, torch.get_num_threads()
 
 
-def oracle_small_step_s(reps: int = 3):
-    """Seconds of one whole float64 oracle step on the small configuration
-    (64 planes, 128x96, lambda(0)): render, Eq. 14 loss against the
-    perturbed scene's render, backward and one Adam step; best of `reps`."""
+def oracle_small_step_s(reps: int = 3, K: int = 64, width: int = 128, height: int = 96, f: float | None = None):
+    """Seconds of one whole float64 oracle step on a small configuration
+    (default 64 planes, 128x96; 256 planes at 256x192, f = 200, for the
+    differentiation-check configuration), lambda(0): render, Eq. 14 loss
+    against the perturbed scene's render, backward and one Adam step; best
+    of `reps`."""
     import torch
     import oracle
     import synth
-    ps = synth.random_planes(64, seed=0, independent_radii=True)
+    ps = synth.random_planes(K, seed=0, independent_radii=True)
     tgt = synth.perturb_planes(ps, seed=1, center_sigma=0.05, rot_sigma_deg=5.0)
-    cam = synth.tiny_camera()
+    cam = synth.tiny_camera() if f is None else synth.tiny_camera(width, height, f)
     lam = float(np.float32(oracle.lambda_at(0)))
     Dt, Nt, _ = oracle.render(tgt.center, tgt.quat, tgt.radii, cam, 300.0)
     best = float("inf")
@@ -129,6 +131,17 @@ def oracle_small_step_s(reps: int = 3):
             oracle.adam_step(x.detach().numpy(), x.grad.numpy(), z, z, 1)
         best = min(best, time.perf_counter() - t0)
     return best
+
+
+def small_config_rates():
+    """The oracle's whole step, in full, on the two small configurations:
+    64 planes at 128x96 and 256 planes at 256x192 (f = 200), as
+    Mpixel*planes/s with the GPU's formula."""
+    out = {}
+    for name, K, W, H, f in (("64 planes, 128x96", 64, 128, 96, None), ("256 planes, 256x192", 256, 256, 192, 200.0)):
+        t = oracle_small_step_s(reps=2, K=K, width=W, height=H, f=f)
+        out[name] = {"step_s": round(t, 3), "value": round(W * H * K / t / 1e6, 2), "unit": "Mpixel*planes/s"}
+    return out
 
 
 def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
@@ -153,6 +166,7 @@ def cpu_baseline(init, cams, lam, budget_s: float = 20.0):
         "sample_1_thread": f"{px1} pixels in {dt1:.1f} s on one thread",
         "fit_5000_steps_s_extrapolated": round(5000 * step_s, 1),
         "small_config_step_s": round(oracle_small_step_s(), 3),
+        "configs": small_config_rates(),
     }
 
 

@@ -877,7 +877,7 @@ def main():
                     help="batched: 16x16 tiles for every room")
     ap.add_argument("--per-item-launch", action="store_true",
                     help="batched: one workgroup per 8x8 block instead of the persistent work-queue launch")
-    ap.add_argument("--train-rooms", type=int, default=64, help="scene-fit: rooms fitted to train the initializer")
+    ap.add_argument("--train-rooms", type=int, default=256, help="scene-fit: rooms fitted to train the initializer")
     ap.add_argument("--train-fit-iters", type=int, default=1000,
                     help="scene-fit: plain-fit iterations of the training rooms")
     ap.add_argument("--train-steps", type=int, default=6000, help="scene-fit: initializer training steps")

@@ -8,8 +8,10 @@ U[0.7, 1.3]; 100 views of 640 x 480 px (f = 577) on a random path; targets are
 the ground truth rendered at lambda = 300.  One step = one fitting iteration
 on `--views` views: ps_fit_schedule (device-side lambda of Eq. 10, Adam step,
 view of the step from a shuffled cycle) -> plane_project -> tile_bin ->
-plane_render_fwd -> loss_depth_normal_cam -> plane_render_bwd ->
-adam_step_planes, captured once in a HIP graph and replayed.
+plane_render_step (forward, loss of Eq. 14, backward and the Adam update of
+the planes: one render launch, then the per-plane reduction that applies the
+update), captured once in a HIP graph and replayed.  --separate-calls times
+the same step as plane_render_fwd_loss + plane_render_bwd_adam.
 
 Metric: fwd+bwd Mpixel.planes/s = (pixels of the step) * K / step time / 1e6,
 with the whole replayed step (Adam included) inside the timed region and all
@@ -801,9 +803,9 @@ def render_roofline(phase_ms, cnt, traffic=None, peaks=None):
     achieved = ops / (phase_ms[dom] * 1e-3) / 1e12
     roof = {
         "kernel": {"fwd": "render_fwd_kernel (plane_render_fwd_loss)",
-                   "bwd": "render_bwd_kernel+bwd_reduce_kernel+adam_kernel (plane_render_bwd_adam)",
-                   "step": "render_bwd_kernel<fused>+bwd_reduce_kernel+adam_kernel (plane_render_step: forward, "
-                           "loss, backward and Adam)"}[dom],
+                   "bwd": "render_bwd_kernel+bwd_reduce_kernel<Adam> (plane_render_bwd_adam)",
+                   "step": "render_bwd_kernel<fused>+bwd_reduce_kernel<Adam> (plane_render_step: forward, "
+                           "loss, backward, then the per-plane reduction with the Adam update)"}[dom],
         "bound": "alu",
         "achieved": round(achieved, 4),
         "peak": round(MI355X_VALU_TOPS, 2),

@@ -405,9 +405,11 @@ int plane_render_bwd(const ps_layout* L, void* ws, const float* center, const fl
  * loss sums of the last plane_render_fwd_loss called with a NULL loss (its
  * per-block partials wait in the workspace) are formed here, with the bits
  * that call would have given, and the forward's own reduction launch is
- * saved.  The update itself stays a kernel of its own: inside the
- * reduction its latency (two float64 powers, the parameter reads) lengthens
- * every round of a reduction over many planes.  plane_render_step does the
+ * saved.  With fewer than 8192 planes (a workgroup per plane in the
+ * reduction, ps_params.flags bit 10 clear) the reduction applies the update
+ * itself, one launch fewer; with more the update is a kernel of its own:
+ * inside a wave-per-plane reduction its latency (two float64 powers, the
+ * parameter reads) would lengthen every round of waves.  plane_render_step does the
  * work of plane_render_fwd_loss and this call with one render launch; this
  * call is the step's form with a separate forward. */
 int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,

@@ -436,17 +436,28 @@ struct LossView {
 
 // One parameter's bias-corrected Adam update (Sec. 3.3), step t (1-based);
 // m and v are updated in place, the new parameter is returned.  Shared by
-// adam_step_planes and the backward that applies Adam itself, so both give
-// the same bits.
-__device__ inline float adam_update(float p, float g, float& m, float& v, float lr, float b1, float b2, float eps,
-                                    int t) {
-  const double bc1 = 1.0 - pow((double)b1, (double)t);
-  const double bc2 = 1.0 - pow((double)b2, (double)t);
+// adam_step_planes and the reduction that applies Adam itself, so both give
+// the same bits.  adam_bias forms the step's two bias corrections, which the
+// reduction computes before its gradients are known.
+__device__ inline void adam_bias(float b1, float b2, int t, double& bc1, double& bc2) {
+  bc1 = 1.0 - pow((double)b1, (double)t);
+  bc2 = 1.0 - pow((double)b2, (double)t);
+}
+
+__device__ inline float adam_apply(float p, float g, float& m, float& v, float lr, float b1, float b2, float eps,
+                                   double bc1, double bc2) {
   m = b1 * m + (1.f - b1) * g;
   v = b2 * v + (1.f - b2) * g * g;
   const float mhat = (float)((double)m / bc1);
   const float vhat = (float)((double)v / bc2);
   return p - lr * mhat / (sqrtf(vhat) + eps);
+}
+
+__device__ inline float adam_update(float p, float g, float& m, float& v, float lr, float b1, float b2, float eps,
+                                    int t) {
+  double bc1, bc2;
+  adam_bias(b1, b2, t, bc1, bc2);
+  return adam_apply(p, g, m, v, lr, b1, b2, eps, bc1, bc2);
 }
 
 // float64 wave sum (the loss partials), in a fixed order

@@ -87,6 +87,13 @@ struct RenderArgs {
   // formed by workgroups added to the per-plane reduction
   float* loss_out;
   const double* loss_in;
+  // plane_render_bwd_adam, plane_render_step: the Adam update, applied by the
+  // per-plane reduction to the gradients it forms (upd_m null: no update)
+  float* upd_p[3];          // center, quat, radii, updated in place
+  float* upd_m;
+  float* upd_v;
+  const int32_t* upd_step;
+  float upd_lr[3], upd_b1, upd_b2, upd_eps, upd_rmin;
 };
 
 // LDS of the render workgroups, at namespace scope so that every access
@@ -1191,7 +1198,7 @@ __device__ void loss_sums(const RenderArgs& a, int s) {
 // wave 0 adds them up (few planes: four waves on the rows of a large plane);
 // Y = 1: a wave per plane does all of it (many planes: no idle waves).  Same
 // bits either way.
-template <bool LOSS, int Y>
+template <bool LOSS, int Y, bool ADAM>
 __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
   __shared__ float part[64][16];   // Y = 4: one round of block sums
   // with LOSS the first n_slots workgroups form the loss sums, one job each
@@ -1202,7 +1209,17 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
     return;
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int k = Y == 4 ? wg : 4 * wg + w;
+  // Y = 4: the dispatcher deals workgroups to the eight XCDs in turn, so the
+  // workgroups whose indices agree mod 8 share one XCD's L2; they take a
+  // contiguous run of planes, whose parameter, moment and gradient lines are
+  // then fetched and written through that L2 alone (a permutation of the
+  // planes: each plane's sums are the same)
+  int kw = wg;
+  if (Y == 4) {
+    const int per = a.K >> 3;
+    if (wg < 8 * per) kw = (wg & 7) * per + (wg >> 3);
+  }
+  const int k = Y == 4 ? kw : 4 * wg + w;
   if (k >= a.K) return;
   // the plane's parameters, fetched up front: the chain rule at the end
   // needs them, and their latency hides behind the lookups below
@@ -1211,6 +1228,26 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
   for (int i = 0; i < 3; ++i) pc[i] = a.center[3 * k + i];
 #pragma unroll
   for (int i = 0; i < 4; ++i) pq[i] = a.quat[4 * k + i];
+  // ADAM: the update of Sec. 3.3 follows the reduction, lane i < 11 of the
+  // wave that writes the gradients taking parameter i (center 0-2, quat 3-6,
+  // radii 7-10) with the arithmetic of adam_step_planes (the same moment
+  // layout: centers at 3 k, quaternions at 3 K + 4 k, radii at 7 K + 4 k).
+  // Its state and bias corrections are fetched and formed here, their
+  // latency hidden by the reduction.  Plane k's parameters and moments are
+  // read and written by plane k's reduction only.
+  const int ugrp = lane < 3 ? 0 : lane < 7 ? 1 : 2;
+  const int upi = ugrp == 0 ? 3 * k + lane : 4 * k + lane - (ugrp == 1 ? 3 : 7);
+  const int umj = upi + (ugrp == 0 ? 0 : ugrp == 1 ? 3 * a.K : 7 * a.K);
+  float* const up = ugrp == 0 ? a.upd_p[0] : ugrp == 1 ? a.upd_p[1] : a.upd_p[2];
+  const bool uown = ADAM && lane < 11 && (Y == 1 || w == 0);
+  float um = 0.f, uv = 0.f, upar = 0.f;
+  double bc1 = 1.0, bc2 = 1.0;
+  if (uown) {
+    um = a.upd_m[umj];
+    uv = a.upd_v[umj];
+    upar = up[upi];
+    adam_bias(a.upd_b1, a.upd_b2, a.upd_step[0], bc1, bc2);
+  }
   double gp[3] = {0, 0, 0}, gw[3] = {0, 0, 0}, gr[4] = {0, 0, 0, 0};
   double qn[4] = {0, 0, 0, 0}, qnorm = 0;
   const bool ok = !a.counters[C_OVERFLOW];
@@ -1320,11 +1357,12 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
     }
     if (stop) break;
   }
-  if (lane == 0 && (Y == 1 || w == 0)) {
-    for (int i = 0; i < 3; ++i) a.g_center[3 * k + i] = (float)gp[i];
-    for (int q = 0; q < 4; ++q) a.g_radii[4 * k + q] = (float)gr[q];
+  if (Y == 1 || w == 0) {
+    // gp, gw, gr, qn and qnorm are the same in every lane of the wave
+    float gc[3], grf[4], gq[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 3; ++i) gc[i] = (float)gp[i];
+    for (int q = 0; q < 4; ++q) grf[q] = (float)gr[q];
     // 2 (0, w) (x) q^  =  2 (-(w . v), q0 w + w x v),  v = (q1, q2, q3)
-    float gq[4] = {0.f, 0.f, 0.f, 0.f};
     if (qnorm > 0) {
       const double s2 = 2.0 / qnorm;
       const double v0 = qn[1], v1 = qn[2], v2 = qn[3];
@@ -1333,7 +1371,26 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(RenderArgs a) {
       gq[2] = (float)(s2 * (qn[0] * gw[1] + (gw[2] * v0 - gw[0] * v2)));
       gq[3] = (float)(s2 * (qn[0] * gw[2] + (gw[0] * v1 - gw[1] * v0)));
     }
-    for (int q = 0; q < 4; ++q) a.g_quat[4 * k + q] = gq[q];
+    if (lane == 0) {
+      for (int i = 0; i < 3; ++i) a.g_center[3 * k + i] = gc[i];
+      for (int q = 0; q < 4; ++q) a.g_radii[4 * k + q] = grf[q];
+      for (int q = 0; q < 4; ++q) a.g_quat[4 * k + q] = gq[q];
+    }
+    if (uown) {
+      float g = gc[0];
+      g = lane == 1 ? gc[1] : g;
+      g = lane == 2 ? gc[2] : g;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        g = lane == 3 + q ? gq[q] : g;
+        g = lane == 7 + q ? grf[q] : g;
+      }
+      const float lr = ugrp == 0 ? a.upd_lr[0] : ugrp == 1 ? a.upd_lr[1] : a.upd_lr[2];
+      const float x = adam_apply(upar, g, um, uv, lr, a.upd_b1, a.upd_b2, a.upd_eps, bc1, bc2);
+      a.upd_m[umj] = um;
+      a.upd_v[umj] = uv;
+      up[upi] = ugrp == 2 ? fmaxf(x, a.upd_rmin) : x;
+    }
   }
 }
 
@@ -1487,6 +1544,15 @@ static int launch_fwd(RenderArgs& a, void* stream) {
 }
 // fused: the fitting step's forward, loss and backward in one launch (the
 // forward-with-loss fields of `a` set as well)
+template <bool LOSS, bool ADAM>
+static void launch_reduce(const RenderArgs& a, int nwg, bool per_wave, hipStream_t st) {
+  const dim3 grid(nwg + (LOSS ? a.S : 0));
+  if (per_wave)
+    hipLaunchKernelGGL((bwd_reduce_kernel<LOSS, 1, ADAM>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((bwd_reduce_kernel<LOSS, 4, ADAM>), grid, dim3(256), 0, st, a);
+}
+
 static int launch_bwd(RenderArgs& a, int K, void* stream, bool fused = false) {
   hipStream_t st = (hipStream_t)stream;
   if (a.n_items > 0) {
@@ -1501,18 +1567,24 @@ static int launch_bwd(RenderArgs& a, int K, void* stream, bool fused = false) {
   // same bits either way); ps_params.flags bit 10 asks for a wave per plane
   const bool per_wave = K >= kReduceWaveMin || (a.flags & kFlagReduceWave);
   const int nwg = per_wave ? (K + 3) / 4 : K;
+  // with the Adam state set the planes are updated: by the reduction when it
+  // has a workgroup per plane (one launch fewer per step), by a kernel of its
+  // own after a wave-per-plane reduction (many planes: there the update's
+  // latency, two float64 powers and the parameter reads, would lengthen
+  // every round of waves).  The bits are the same either way.
+  const bool adam = a.upd_m && K > 0, fold = adam && !per_wave;
   if (a.loss_out) {
-    if (per_wave)
-      hipLaunchKernelGGL((bwd_reduce_kernel<true, 1>), dim3(nwg + a.S), dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((bwd_reduce_kernel<true, 4>), dim3(nwg + a.S), dim3(256), 0, st, a);
+    if (fold) launch_reduce<true, true>(a, nwg, per_wave, st);
+    else launch_reduce<true, false>(a, nwg, per_wave, st);
   } else if (K > 0) {
-    if (per_wave)
-      hipLaunchKernelGGL((bwd_reduce_kernel<false, 1>), dim3(nwg), dim3(256), 0, st, a);
-    else
-      hipLaunchKernelGGL((bwd_reduce_kernel<false, 4>), dim3(nwg), dim3(256), 0, st, a);
+    if (fold) launch_reduce<false, true>(a, nwg, per_wave, st);
+    else launch_reduce<false, false>(a, nwg, per_wave, st);
   }
   PS_HIP_CHECK(hipGetLastError());
+  if (adam && !fold)
+    return adam_step_planes(a.upd_p[0], a.upd_p[1], a.upd_p[2], a.g_center, a.g_quat, a.g_radii, a.upd_m, a.upd_v, K,
+                            a.upd_step, a.upd_lr[0], a.upd_lr[1], a.upd_lr[2], a.upd_b1, a.upd_b2, a.upd_eps,
+                            a.upd_rmin, stream);
   return PS_OK;
 }
 
@@ -1583,6 +1655,16 @@ extern "C" int plane_render_bwd(const ps_layout* L, void* ws, const float* cente
   return launch_bwd(a, K, stream);
 }
 
+// The Adam state of the reduction's update (null m when K = 0: no update).
+static void set_adam(RenderArgs& a, float* center, float* quat, float* radii, float* m, float* v,
+                     const int32_t* step, float lr_center, float lr_quat, float lr_radii, float beta1, float beta2,
+                     float eps, float r_min) {
+  a.upd_p[0] = center; a.upd_p[1] = quat; a.upd_p[2] = radii;
+  a.upd_m = m; a.upd_v = v; a.upd_step = step;
+  a.upd_lr[0] = lr_center; a.upd_lr[1] = lr_quat; a.upd_lr[2] = lr_radii;
+  a.upd_b1 = beta1; a.upd_b2 = beta2; a.upd_eps = eps; a.upd_rmin = r_min;
+}
+
 extern "C" int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
                                      const ps_camera* cams, int n_cams, const float* lambda, const ps_params* prm,
                                      const float* g_depth, const float* g_normal, float* g_center, float* g_quat,
@@ -1600,10 +1682,8 @@ extern "C" int plane_render_bwd_adam(const ps_layout* L, void* ws, float* center
     a.loss_out = loss;
     a.loss_in = (const double*)((char*)ws + L->region[R_LOSS]);
   }
-  rc = launch_bwd(a, K, stream);
-  if (rc || K == 0) return rc;
-  return adam_step_planes(center, quat, radii, g_center, g_quat, g_radii, m, v, K, step, lr_center, lr_quat, lr_radii,
-                          beta1, beta2, eps, r_min, stream);
+  set_adam(a, center, quat, radii, m, v, step, lr_center, lr_quat, lr_radii, beta1, beta2, eps, r_min);
+  return launch_bwd(a, K, stream);
 }
 
 extern "C" int plane_render_step(const ps_layout* L, void* ws, float* center, float* quat, float* radii, int K,
@@ -1637,10 +1717,8 @@ extern "C" int plane_render_step(const ps_layout* L, void* ws, float* center, fl
     a.loss_out = loss;
     a.loss_in = a.loss_part;
   }
-  rc = launch_bwd(a, K, stream, true);
-  if (rc || K == 0) return rc;
-  return adam_step_planes(center, quat, radii, g_center, g_quat, g_radii, m, v, K, step, lr_center, lr_quat, lr_radii,
-                          beta1, beta2, eps, r_min, stream);
+  set_adam(a, center, quat, radii, m, v, step, lr_center, lr_quat, lr_radii, beta1, beta2, eps, r_min);
+  return launch_bwd(a, K, stream, true);
 }
 
 extern "C" int plane_render_fwd_lists(const ps_layout* L, void* ws, const ps_camera* cams, int n_cams,

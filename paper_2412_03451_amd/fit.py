@@ -4,7 +4,10 @@ target depth and normal maps, with the loss of Eq. 14 and lambda of Eq. 10.
 One iteration is: ps_fit_schedule (device-side iteration counter, lambda,
 Adam step and the view of each job) -> plane_project -> tile_bin ->
 plane_render_fwd -> loss_depth_normal_cam -> plane_render_bwd ->
-adam_step_planes.  Every step runs in the library's kernels and nothing in it
+adam_step_planes; by default (FitConfig.one_launch) the last four are one
+call, plane_render_step: one render launch for each 8x8 block's forward, loss
+and backward, then the per-plane reduction, which also applies Adam when it
+has a workgroup per plane.  Every step runs in the library's kernels and nothing in it
 reads back to the host, so the iteration can be captured once in a HIP graph
 (torch.cuda.CUDAGraph) and replayed.
 

@@ -89,14 +89,16 @@ def test_fused_backward_adam_gives_the_separate_calls_bits(batch):
     assert np.abs(a[0][1]).max() > 0
 
 
-@pytest.mark.parametrize("mode,flags", [(0, 0), (2, 0), (1, 1), (0, 2 << 4)])
+@pytest.mark.parametrize("mode,flags", [(0, 0), (2, 0), (1, 1), (0, 2 << 4), (0, 1 << 10)])
 def test_one_launch_step_gives_the_separate_calls_bits(batch, mode, flags):
     """plane_render_step (each 8x8 block's forward, loss and backward in one
     launch, the hits committed again from the walk's recorded positions)
     against plane_render_fwd_loss + plane_render_bwd + adam_step_planes:
     the same bits for everything, in the default weight mode, the Gaussian
-    (Eq. 5), mode 1 with the exact fallback forced for every pixel, and with
-    an 8-hit pending buffer."""
+    (Eq. 5), mode 1 with the exact fallback forced for every pixel, with an
+    8-hit pending buffer, and with the wave-per-plane reduction (flags bit
+    10), after which the Adam update is a launch of its own rather than part
+    of the reduction."""
     from paper_2412_03451_amd.splat import SplatParams
     prm = SplatParams(weight_mode=mode, flags=flags)
     a = _run(batch, fused=False, params=prm)

@@ -642,6 +642,7 @@ __global__ __launch_bounds__(64) void render_fwd_kernel(RenderArgs a) {
 
 // ------------------------------------------------------------------ backward
 constexpr int kChunk = 8;    // hits per lane kept in LDS per recompute pass
+constexpr int kPrioList = 256;   // tile lists from this length get the raised wave priority
 
 struct BwdLds {
   int16_t pos[kChunk][64];   // list positions (< 4096)
@@ -895,6 +896,12 @@ __device__ __forceinline__ void bwd_item(const RenderArgs& a, int item) {
   if (st == 2) return;
   const int lane = threadIdx.x;
   const int n = c.e - c.b;
+  // the blocks of long tile lists set the launch's length: their waves win
+  // the SIMD's instruction arbitration over the short ones sharing it (issue
+  // order only, the arithmetic is unchanged; on the 640x480 room 0.1621 ->
+  // 0.1606 ms per step, the 64-room batch unchanged)
+  if (n >= kPrioList) __builtin_amdgcn_s_setprio(2);
+  else __builtin_amdgcn_s_setprio(0);
   if (st == 1) {   // block outside the image (partial tile): zero rows
     for (int i = lane; i < n; i += 64) zero_row(a, a.emit[c.b + i], c.sub);
     return;

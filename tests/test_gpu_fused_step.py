@@ -170,3 +170,26 @@ def test_one_launch_step_without_maps(batch):
         outs.append([x.cpu().numpy().copy() for x in (loss, gc, gq, gr, c, q, rr, m, v)])
     for x, y in zip(*outs):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+
+
+@pytest.mark.parametrize("kp", [1, 5, 8, 13])
+def test_one_launch_step_bits_for_few_planes(batch, kp):
+    """With a workgroup per plane the reduction deals the planes to its
+    workgroups in contiguous runs per XCD (workgroups equal mod 8 take one
+    run), the last K mod 8 planes in order; below 8 planes every plane is
+    in that tail.  Every plane is still reduced and updated once, with the
+    separate calls' bits (plane counts 1, 5, 8 and 13 of the room's planes,
+    both jobs kept)."""
+    from types import SimpleNamespace
+    from paper_2412_03451_amd.splat import Job
+    init, cams, jobs, tD, tN = batch
+    sub = SimpleNamespace(center=init.center[:kp], quat=init.quat[:kp], radii=init.radii[:kp], K=kp)
+    jobs_k = [Job(0, kp, j.cam, j.width, j.height, j.tile) for j in jobs]
+    b = (sub, cams, jobs_k, tD, tN)
+    x = _run(b, fused=False, steps=2)
+    y = _run(b, fused="step", steps=2)
+    names = ("loss", "g_center", "g_quat", "g_radii", "center", "quat", "radii", "m", "v", "depth", "normal",
+             "g_depth", "g_normal")
+    for it, (sa, sb) in enumerate(zip(x, y)):
+        for n, p, q in zip(names, sa, sb):
+            assert np.array_equal(p.view(np.uint32), q.view(np.uint32)), (kp, it, n)
